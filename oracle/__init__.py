@@ -1,0 +1,20 @@
+"""Plain CPU oracle for the KSG conditional-mutual-information hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or runs
+anything from this package; only the tests, the smoke check and the benchmark's
+CPU baseline do.  It shares no code with the HIP library: it re-derives every
+step from the paper and from the estimator definition the paper cites.
+
+Modules
+  ksg     brute-force KSG CMI estimator (numpy, float32 subtraction, float64 sums)
+  perm    keyed surrogate permutation (SplitMix64 + Feistel cycle walking)
+  stats   maximum-statistic, minimum-statistic and omnibus tests
+  greedy  the four-step greedy multivariate TE inference for one target
+  cksg    ctypes loader for ksg_oracle.c, the same brute force in plain C (timed)
+
+Parity status: ksg, perm and stats are pinned by tests/test_oracle_*.py against
+closed forms, hand-counted cases, invariances and published generator outputs.
+greedy's selections on real data are pinned only statistically (recovery of
+known parents, no selection on independent data): beyond that, parity
+unpinned, since the paper prints no CMI or TE values.
+"""

@@ -1,0 +1,154 @@
+"""Greedy multivariate transfer-entropy inference for one target, in the paper's
+four steps (Inference algorithm section).  TEST INFRASTRUCTURE ONLY.
+
+  Step 1  target past: from the candidates Y_{t-1..t-l_target}, repeatedly take
+          the C maximising I(C; Y_t | Y^S), keep it if the maximum statistic test
+          is significant, stop at the first non-significant test or when no
+          candidate is left.
+  Step 2  sources past: the same over X_{i,t-1..t-l_sources} of every candidate
+          source with conditioning set Y^S u X^S.
+  Step 3  pruning: find the C in X^S minimising I(C; Y_t | Y^S u X^S \\ {C}); if
+          the minimum statistic test is NOT significant remove it and repeat;
+          stop when it is significant or X^S is empty.
+  Step 4  omnibus: T* = I(X^S; Y_t | Y^S) against surrogates in which the rows
+          of all selected source columns are shuffled jointly; the sources are
+          accepted only if this test is significant as well.
+
+Readings fixed where the paper is silent (each also used by the library):
+  * embedding rows t = l_M .. T-1 with l_M = max(l_target, l_sources), so
+    N = T - l_M; variable (node, lag) is series[node][t - lag];
+  * candidate order: target lags ascending; sources in the given order, each
+    with lags ascending; removal keeps the order of the rest; ties go to the
+    first candidate in that order;
+  * surrogate keys: a running test counter `tid` starts at 0 for the target;
+    every candidate of every max/min-statistic round takes the next tid, in
+    candidate order, and draws its S surrogates with keys (seed, tid, s); the
+    omnibus test takes the next tid after pruning;
+  * alpha_max = alpha_min = alpha_omnibus = alpha;
+  * the reported CMI and p of a selected variable are those of the test that
+    selected it; an empty X^S skips the omnibus test (p = 1, not significant);
+  * no normalisation of the series.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import ksg, perm, stats
+
+
+def embed(series: np.ndarray, node: int, lag: int, l_m: int) -> np.ndarray:
+    t = series.shape[1]
+    return np.ascontiguousarray(series[node, l_m - lag: t - lag][None, :])
+
+
+class _Run:
+    def __init__(self, series, target, k, n_surr, seed, l_m, estimator):
+        self.series = series
+        self.target = target
+        self.k = k
+        self.n_surr = n_surr
+        self.seed = seed
+        self.l_m = l_m
+        self.tid = 0
+        self.n_estimates = 0
+        self.est = estimator
+        self.y = embed(series, target, 0, l_m)
+
+    def cols(self, variables):
+        if not variables:
+            return None
+        return np.concatenate([embed(self.series, n, l, self.l_m) for (n, l) in variables], axis=0)
+
+    def test_candidates(self, cands, cond_of):
+        """CMI of each candidate and of its S surrogates: ([n], [n][S])."""
+        n_rows = self.y.shape[1]
+        real = np.empty(len(cands))
+        surr = np.empty((len(cands), self.n_surr))
+        for j, c in enumerate(cands):
+            x = self.cols([c])
+            z = self.cols(cond_of(c))
+            real[j] = self.est(x, self.y, z, self.k)
+            for s in range(self.n_surr):
+                p = perm.permutation(self.seed, self.tid, s, n_rows)
+                surr[j, s] = self.est(ksg.permute_rows(x, p), self.y, z, self.k)
+            self.tid += 1
+            self.n_estimates += 1 + self.n_surr
+        return real, surr
+
+
+def _numpy_estimator(x, y, z, k):
+    return ksg.cmi_ksg(x, y, z, k)
+
+
+def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
+                   max_lag_target: int = 5, alpha: float = 0.05, k: int = 4,
+                   n_surr: int = 200, seed: int = 0, estimator=None):
+    series = np.asarray(series)
+    if series.dtype != np.float32:
+        raise TypeError("series must be float32")
+    stats.require_surrogates(n_surr, alpha)
+    if target in candidates:
+        raise ValueError("target among candidates")
+    l_m = max(max_lag_target, max_lag_sources)
+    run = _Run(series, target, k, n_surr, seed, l_m, estimator or _numpy_estimator)
+
+    # Step 1: target past
+    ycand = [(target, lag) for lag in range(1, max_lag_target + 1)]
+    ysel = []
+    while ycand:
+        yv = [(n, l) for (n, l, _, _) in ysel]
+        real, surr = run.test_candidates(ycand, lambda c: yv)
+        j, p, sig = stats.max_statistic(real, surr, alpha)
+        if not sig:
+            break
+        ysel.append(ycand[j] + (float(real[j]), p))
+        del ycand[j]
+    yvars = [(n, l) for (n, l, _, _) in ysel]
+
+    # Step 2: sources past
+    xcand = [(src, lag) for src in candidates for lag in range(1, max_lag_sources + 1)]
+    xsel = []
+    while xcand:
+        xvars = [(n, l) for (n, l, _, _) in xsel]
+        real, surr = run.test_candidates(xcand, lambda c: yvars + xvars)
+        j, p, sig = stats.max_statistic(real, surr, alpha)
+        if not sig:
+            break
+        xsel.append(xcand[j] + (float(real[j]), p))
+        del xcand[j]
+
+    # Step 3: pruning
+    while xsel:
+        xvars = [(n, l) for (n, l, _, _) in xsel]
+        real, surr = run.test_candidates(
+            xvars, lambda c: yvars + [v for v in xvars if v != c])
+        j, p, sig = stats.min_statistic(real, surr, alpha)
+        if sig:
+            break
+        del xsel[j]
+
+    # Step 4: omnibus
+    omni_te, omni_p, omni_sig = 0.0, 1.0, False
+    if xsel:
+        xvars = [(n, l) for (n, l, _, _) in xsel]
+        x = run.cols(xvars)
+        z = run.cols(yvars)
+        omni_te = run.est(x, run.y, z, k)
+        n_rows = run.y.shape[1]
+        surr = np.empty(n_surr)
+        for s in range(n_surr):
+            p_ = perm.permutation(seed, run.tid, s, n_rows)
+            surr[s] = run.est(ksg.permute_rows(x, p_), run.y, z, k)
+        run.tid += 1
+        run.n_estimates += 1 + n_surr
+        omni_p, omni_sig = stats.omnibus(omni_te, surr, alpha)
+    return {
+        "target_past": ysel,
+        "sources": xsel if omni_sig else [],
+        "sources_before_omnibus": xsel,
+        "omnibus_te": omni_te,
+        "omnibus_p": omni_p,
+        "significant": bool(omni_sig),
+        "n_estimates": run.n_estimates,
+    }
