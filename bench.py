@@ -1,0 +1,261 @@
+"""Benchmark: KSG CMI evals/s at N = 10000, batched vs plain vs served.
+
+Workload (one step): one transfer-entropy test at N = 10000 rows, D = 7
+(X = a parent of the target at its true lag, Y = the target's present,
+Z = the target's lags 1..5) on a 10-node linear VAR (synthetic, seeded):
+the estimate and its 200 permutation surrogates in one batched launch on
+device-resident inputs, the results copied back and the significance test run
+on the host.  Reported beside it: the plain form (one call per estimate, 201
+calls per step), the served form (requests of uneven N and conditioning
+dimension through the request loop, Poisson arrivals, p50/p99 latency), the
+main kernel's roofline figures and the CPU oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "KSG CMI evals/s at N=10k (batched/served vs plain); p50/p99 req latency"
+N_ROWS, S, K_NN, SEED = 10000, 200, 4, 2
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz non-packed FP32/INT32 VALU issue
+PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_ops(n, dx, dy, dz, n_est):
+    """Method operations of one batched test (Roofline): per
+    ordered pair (i != j), the Y,Z max-norm once per test for each pass
+    (2*(dy+dz)-1 ops each: subtract, |.|-max), and per estimate 2*dx+1 ops in
+    the k-NN pass (X subtract/max, compare with the current k-th) and 2*dx+6 in
+    the count pass (X subtract/max, three compares, three increments)."""
+    pairs = n * (n - 1)
+    shared = 2 * (2 * (dy + dz) - 1)
+    per_est = (2 * dx + 1) + (2 * dx + 6)
+    return pairs * (shared + n_est * per_est)
+
+
+def cpu_baseline(X, Y, Z, budget_s=15.0):
+    from oracle import cksg, ksg, perm
+    threads = cksg.max_threads()
+    t = time.perf_counter()
+    cksg.cmi_ksg(X, Y, Z, K_NN)
+    one = time.perf_counter() - t
+    count = int(max(1, min(S + 1, math.floor(budget_s / max(one, 1e-3)))))
+    t = time.perf_counter()
+    for e in range(count):
+        Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(SEED, 0, e - 1, X.shape[1]))
+        cksg.cmi_ksg(Xe, Y, Z, K_NN)
+    dt = time.perf_counter() - t
+    return {"value": count / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} of the 201 C2 estimates (the estimate, then surrogates 0..{count - 2}), "
+                      f"brute-force C oracle, OpenMP over query rows"}
+
+
+def served(mte, torch, n_burst=48, n_poisson=96, load=0.8):
+    """Requests of N in {1000, 3000, 10000}, Z dim 1..15, S = 200 over a
+    100-node coupled-logistic-map network: a burst for saturation throughput,
+    then Poisson arrivals at `load` x that rate for latency."""
+    import synth
+    series, _ = synth.clm_network(100, N_ROWS, seed=4)
+    sid = mte.mte_series_register(series)
+    g = np.random.default_rng(4)
+
+    def make(r):
+        n = int(g.choice([1000, 3000, 10000]))
+        dz = int(g.integers(1, 16))
+        nodes = g.integers(0, 100, size=2 + dz).astype(np.int32)
+        lags = np.concatenate([[int(g.integers(1, 6))], [0], g.integers(1, 6, size=dz)]).astype(np.int32)
+        return dict(nodes=nodes, lags=lags, dx=1, dy=1, dz=dz, t0=5, n=n, k=K_NN, S=S, seed=9, cand=r)
+
+    warm = [make(r) for r in range(6)]
+    for q in warm:
+        mte.mte_wait(mte.mte_submit(sid, **q), S)
+    mte.mte_serve_get_stats(reset=True)
+    reqs = [make(r) for r in range(n_burst)]
+    t = time.perf_counter()
+    tickets = [mte.mte_submit(sid, **q) for q in reqs]
+    for tk in tickets:
+        mte.mte_wait(tk, S)
+    burst_s = time.perf_counter() - t
+    st_burst = mte.mte_serve_get_stats(reset=True)
+    rate = n_burst / burst_s
+    reqs = [make(r) for r in range(n_poisson)]
+    gaps = g.exponential(1.0 / (load * rate), size=n_poisson)
+    t = time.perf_counter()
+    tickets = []
+    next_t = t
+    for q, gap in zip(reqs, gaps):
+        next_t += gap
+        while time.perf_counter() < next_t:
+            time.sleep(min(0.0005, max(0.0, next_t - time.perf_counter())))
+        tickets.append(mte.mte_submit(sid, **q))
+    for tk in tickets:
+        mte.mte_wait(tk, S)
+    poisson_s = time.perf_counter() - t
+    st = mte.mte_serve_get_stats(reset=True)
+    mte.mte_series_release(sid)
+    return {
+        "workload": "100-node CLM, requests of N in {1000,3000,10000}, Z dim 1..15, S=200",
+        "saturation_evals_per_s": st_burst["estimates"] / burst_s,
+        "saturation_requests_per_s": rate,
+        "burst_mean_batch_requests": st_burst["mean_batch_requests"],
+        "offered_load": load,
+        "poisson_requests": n_poisson,
+        "poisson_evals_per_s": st["estimates"] / poisson_s,
+        "p50_latency_s": st["p50_latency_s"],
+        "p99_latency_s": st["p99_latency_s"],
+        "batches": st["batches"],
+        "mean_batch_requests": st["mean_batch_requests"],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the KSG path on a single MI355X "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1902_06828_amd as mte
+    import synth
+
+    dev = torch.device("cuda:0")
+    X, Y, Z, meta = synth.c2_te_inputs(N_ROWS, seed=SEED)
+    dX, dY, dZ = (torch.from_numpy(a).to(dev) for a in (X, Y, Z))
+    E = S + 1
+    out = torch.zeros(E, dtype=torch.float64, device=dev)
+    host = torch.zeros(E, dtype=torch.float64).pin_memory()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mte.cmi_ksg_surrogates_dev(dX, dY, dZ, K_NN, S, SEED, 0, out)
+        host.copy_(out, non_blocking=True)
+        stream.synchronize()
+        v = host.numpy()
+        return mte.mte_omnibus(float(v[0]), v[1:], 0.05)
+
+    log("batched: warm-up (includes the tile autotuner)")
+    for _ in range(args.warmup):
+        step()
+    mte.mte_kernel_timing(True)
+    mte.mte_kernel_timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        p, sig = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kernel_ms = mte.mte_kernel_timing_read(reset=True)
+    mte.mte_kernel_timing(False)
+    dt = t1 - t0
+    value = E * args.steps / dt
+    k_avg_ms = kernel_ms / max(1, launches)
+    ops = algorithmic_ops(N_ROWS, 1, 1, 5, E)
+    achieved = ops / (k_avg_ms * 1e-3) / 1e12
+    log(f"batched: {value:.1f} evals/s, {dt / args.steps * 1e3:.2f} ms/step, main kernel {k_avg_ms:.3f} ms, "
+        f"{achieved:.2f} TOP/s ({achieved / PEAK_TOPS:.1%} of {PEAK_TOPS:.1f}); TE p={p:.3f}")
+
+    # graph replay of the same step (timing off)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    graph_value = E * args.steps / (time.perf_counter() - t0)
+
+    # plain form: one call per estimate (surrogate inputs permuted up front)
+    plain = None
+    if args.plain_steps > 0:
+        perms = [np.arange(N_ROWS)] + [mte.mte_permutation(SEED, 0, s, N_ROWS).astype(np.int64) for s in range(S)]
+        dXs = [torch.from_numpy(np.ascontiguousarray(X[:, pm])).to(dev) for pm in perms]
+        outs = torch.zeros((E, 1), dtype=torch.float64, device=dev)
+
+        def plain_step():
+            for e in range(E):
+                mte.cmi_ksg_dev(dXs[e], dY, dZ, K_NN, outs[e])
+            host.copy_(outs.view(-1), non_blocking=True)
+            stream.synchronize()
+            v = host.numpy()
+            return mte.mte_omnibus(float(v[0]), v[1:], 0.05)
+        log("plain: warm-up")
+        plain_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        pt = time.perf_counter() - t0
+        same = np.array_equal(outs.view(-1).cpu().numpy(), out.cpu().numpy())
+        plain = {"evals_per_s": E * args.plain_steps / pt, "ms_per_step": pt / args.plain_steps * 1e3,
+                 "identical_to_batched": bool(same)}
+        log(f"plain: {plain['evals_per_s']:.1f} evals/s (identical results: {same})")
+
+    srv = None
+    if not args.no_served:
+        log("served: burst + Poisson arrivals")
+        srv = served(mte, torch)
+        log(f"served: {srv['saturation_evals_per_s']:.1f} evals/s saturated; Poisson p50 "
+            f"{srv['p50_latency_s'] * 1e3:.1f} ms p99 {srv['p99_latency_s'] * 1e3:.1f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: C oracle on a bounded sample")
+        cpu = cpu_baseline(X, Y, Z)
+        log(f"cpu: {cpu['value']:.3f} evals/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "one TE test: estimate + 200 permutation surrogates, N=10000, X 1-D source lag, "
+                        "Y 1-D target, Z 5-D target past (lags 1..5), 10-node linear VAR, k=4, "
+                        "201 estimates in one batched launch, host significance test",
+            "N": N_ROWS, "dims": [1, 1, 5], "k": K_NN, "estimates_per_step": E,
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_TOPS, "traffic": None,
+                     "kernel_ms": k_avg_ms, "ops_per_launch": ops},
+        "cpu_baseline": cpu,
+        "graph_replay_evals_per_s": graph_value,
+        "plain": plain,
+        "served": srv,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+/*
+ * mte.h -- C ABI of libmte.so, the MI355X (gfx950) library for the hot path of
+ * greedy multivariate transfer-entropy network inference: the KSG nearest-
+ * neighbour estimator of conditional mutual information (CMI), its permutation
+ * surrogates, the maximum/minimum-statistic and omnibus tests, the four-step
+ * greedy source selection for one target, and a continuous-batching request
+ * loop.
+ *
+ * Paper: Novelli, Wollstadt, Mediano, Wibral, Lizier, "Large-scale directed
+ * network inference with multivariate transfer entropy and hierarchical
+ * statistical testing" (arXiv:1902.06828).
+ *
+ * Conventions for every call
+ *   - Return value: MTE_OK (0) or a negative mte_status.  Outputs are written
+ *     only when MTE_OK is returned.  mte_last_error() gives a message for the
+ *     last failing call on the calling thread.
+ *   - Sample matrices are column-major ("structure of arrays"): column c of a
+ *     d-column matrix with N rows is V[c*ld + i], i < N (ld = N for the host
+ *     calls).  Values are IEEE binary32 and must be finite (MTE_EINVAL
+ *     otherwise, checked for host inputs).
+ *   - N is the number of embedded samples (rows) of one estimate; the paper's
+ *     N (number of processes) is called P here and its T (series length) T.
+ *   - Host pointers are owned by the caller and not retained after return.
+ *     Device pointers (the *_dev calls) must stay valid until the work queued
+ *     on `stream` has finished.  `stream` is a hipStream_t (NULL = the null
+ *     stream).
+ *   - The library runs on one GPU, chosen by mte_init (device 0 if the first
+ *     call is made without mte_init).  Calls are thread-safe.
+ */
+#ifndef MTE_H
+#define MTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MTE_OK = 0,
+    MTE_EINVAL = -1,   /* an argument is out of range or inconsistent */
+    MTE_ENOMEM = -2,   /* device memory (or the HBM budget) is exhausted */
+    MTE_EDEVICE = -3,  /* no usable GPU, a HIP call failed, or a kernel reported an error */
+    MTE_ETIMEOUT = -4, /* mte_wait ran out of time; the request is still pending */
+    MTE_EBUSY = -5     /* the object is in use (e.g. a series with pending requests) */
+} mte_status;
+
+/* Message for the last failing call on this thread (never NULL). */
+const char *mte_last_error(void);
+
+/* ABI version; changes whenever a declaration in this header changes. */
+int mte_abi_version(void);
+
+/*
+ * Select the GPU and the HBM budget that the request loop may use for
+ * per-request scratch memory (0 = 90% of the free memory at init).
+ * Idempotent for the same device; MTE_EINVAL for another device while
+ * initialised.  Without a GPU: MTE_EDEVICE.
+ */
+int mte_init(int device, size_t hbm_budget_bytes);
+
+/* Drain the request loop, free every device allocation, release the GPU. */
+int mte_shutdown(void);
+
+/* --------------------------------------------------------------------------
+ * KSG estimator of I(X;Y|Z), in nats (estimator named by citation in the CLM
+ * section: Kraskov's I^(1) with k neighbours and its CMI extension).
+ *   eps_i  = k-th smallest max-norm distance from row i to the other rows in
+ *            the joint (X,Y,Z) space, distances |fl32(a_i - a_j)|;
+ *   counts = strict (< eps_i) neighbour counts in the (X,Z), (Y,Z) and Z
+ *            subspaces (N-1 for Z when dz = 0);
+ *   I      = psi(k) - mean_i[psi(n_xz+1) + psi(n_yz+1) - psi(n_z+1)].
+ * The value may be negative (Statistical tests section).  eps and counts are
+ * exact; the mean is a float64 sum in a fixed order that does not depend on
+ * batching, so the plain, batched and served forms return identical bits.
+ * Limits: 1 <= dx <= 16; 1 <= dy <= 8; 0 <= dz <= 31; 1 <= k <= 16;
+ * k+1 <= N <= 2^31-1; Z must be NULL iff dz == 0.
+ * ------------------------------------------------------------------------ */
+
+/* One estimate from host buffers (blocking). */
+int cmi_ksg(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
+            int64_t N, int k, double *cmi_out);
+
+/*
+ * One estimate plus S permutation surrogates, all computed in one batched
+ * launch (blocking).  Surrogate s (0-based) keeps Y and Z and replaces the
+ * rows of X jointly: row i takes row pi_{seed,0,s}(i) (see mte_permutation).
+ * surr_out has S entries.  S >= 1.
+ */
+int cmi_ksg_surrogates(const float *X, int dx, const float *Y, int dy, const float *Z,
+                       int dz, int64_t N, int k, int S, uint64_t seed, double *cmi_out,
+                       double *surr_out);
+
+/*
+ * Diagnostic form of cmi_ksg_surrogates for parity checks: same kernel, plus
+ * the per-row radius and counts of every estimate (estimate 0 = unpermuted,
+ * estimate 1+s = surrogate s, keyed with candidate index `cand`).  Host
+ * arrays: cmi_out [1+S]; eps_out, nxz_out, nyz_out, nz_out [1+S][N].  S >= 0.
+ */
+int cmi_ksg_diag(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
+                 int64_t N, int k, int S, uint64_t seed, uint32_t cand, double *cmi_out,
+                 float *eps_out, int32_t *nxz_out, int32_t *nyz_out, int32_t *nz_out);
+
+/*
+ * Device-resident forms (asynchronous on `stream`, no host synchronisation).
+ * dX, dY, dZ are device matrices with leading dimension ld >= N; d_out is a
+ * device array of 1+S doubles (estimate first, then the surrogates; S may be
+ * 0 in cmi_ksg_surrogates_dev, and cmi_ksg_dev is the S = 0 case).
+ * Repeated calls with the same shapes and pointers replay a captured HIP
+ * graph.  Scratch memory is owned by the library and reused.
+ */
+int cmi_ksg_dev(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz,
+                int64_t N, int64_t ld, int k, double *d_out, void *stream);
+int cmi_ksg_surrogates_dev(const float *dX, int dx, const float *dY, int dy, const float *dZ,
+                           int dz, int64_t N, int64_t ld, int k, int S, uint64_t seed,
+                           uint32_t cand, double *d_out, void *stream);
+
+/*
+ * The surrogate permutation pi_{seed,cand,s} of {0..N-1} (host computation of
+ * the same definition the kernels use): a swap-or-not shuffle (Hoang, Morris,
+ * Rogaway 2012) with max(24, 6*ceil(log2 N)) rounds keyed by SplitMix64.
+ * out has N entries.  1 <= N <= 2^31-1.
+ */
+int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_t *out);
+
+/* --------------------------------------------------------------------------
+ * Significance tests over CMI estimates (Statistical tests section, Table 1).
+ * real[n] are the candidates' estimates, surr[n][S] their surrogates
+ * (row-major).  S*alpha must exceed 1 (Maximum statistic test, item a).
+ *   max: I* = max_j real[j] (first on ties); p = #{s: max_j surr[j][s] > I*}/S
+ *   min: I  = min_j real[j] (first on ties); p = #{s: min_j surr[j][s] > I}/S
+ *   omnibus: p = #{s: surr[s] > real}/S
+ * significant = (p < alpha).
+ * ------------------------------------------------------------------------ */
+int mte_max_statistic(const double *real, const double *surr, int n, int S, double alpha,
+                      int *index_out, double *p_out, int *significant_out);
+int mte_min_statistic(const double *real, const double *surr, int n, int S, double alpha,
+                      int *index_out, double *p_out, int *significant_out);
+int mte_omnibus(double real, const double *surr, int S, double alpha, double *p_out,
+                int *significant_out);
+
+/* --------------------------------------------------------------------------
+ * Greedy source selection for one target (Inference algorithm section,
+ * steps 1-4).  data: host float32 [P][T] row-major (one series per process).
+ * Embedding rows t = L..T-1 with L = max(max_lag_target, max_lag_sources);
+ * variable (node, lag) is data[node][t-lag].  Candidates: target lags
+ * 1..max_lag_target, then each candidate source (given order) with lags
+ * 1..max_lag_sources.  Every candidate test of a greedy iteration (all
+ * candidates and their S surrogates) runs as one batched launch; the tests
+ * run on the host.  Surrogate keys: a running candidate-test counter t
+ * (starting at 0, one per candidate per iteration in candidate order, then
+ * one for the omnibus test) gives pi_{seed,t,s}.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int k;              /* neighbours (default 4) */
+    int S;              /* surrogates per candidate test (default 200) */
+    int max_lag_target; /* target-past candidate lags 1..max_lag_target (default 5) */
+    uint64_t seed;      /* surrogate key seed (default 0) */
+} mte_opts;
+
+typedef struct {
+    int32_t node, lag;  /* process index and lag in samples */
+    double cmi;         /* estimate of the test that selected it */
+    double p;           /* p-value of that test */
+} mte_var;
+
+typedef struct {
+    /* caller-allocated arrays and their capacities */
+    mte_var *target_past;  /* capacity >= max_lag_target */
+    mte_var *sources;      /* capacity >= n_candidates * max_lag_sources */
+    /* results */
+    int n_target_past;
+    int n_sources;         /* accepted sources (0 unless the omnibus test passed) */
+    int n_sources_tested;  /* selected sources before the omnibus test */
+    double omnibus_te;     /* collective TE I(X^S; Y_t | Y^S); 0 if X^S is empty */
+    double omnibus_p;      /* 1 if X^S is empty */
+    int significant;       /* omnibus test passed */
+    int64_t n_estimates;   /* CMI estimates computed (real and surrogate) */
+    double gpu_seconds;    /* wall time spent waiting for the GPU */
+} mte_result;
+
+/* opts may be NULL (defaults).  alpha is used for all three tests.
+ * MTE_EINVAL if S*alpha <= 1, the target is among the candidates, a node is
+ * out of range, T <= L + k, or a capacity is missing. */
+int mte_select_sources(const float *data, int P, int64_t T, int target,
+                       const int32_t *candidates, int n_candidates, int max_lag_sources,
+                       double alpha, const mte_opts *opts, mte_result *out);
+
+/* The same greedy selection over a series registered with
+ * mte_series_register; every candidate test goes through the request loop
+ * below as one request, so concurrent calls (one per target) are batched
+ * together on the GPU.  Same arguments and results as mte_select_sources. */
+int mte_select_sources_sid(int32_t sid, int target, const int32_t *candidates, int n_candidates,
+                           int max_lag_sources, double alpha, const mte_opts *opts,
+                           mte_result *out);
+
+/* --------------------------------------------------------------------------
+ * Request loop (continuous batching).  Series registered once stay resident
+ * in HBM; each request is one candidate test (1 + S estimates of
+ * I(X;Y|Z) over lag-shifted windows of a resident series); requests are
+ * admitted while the in-flight limit and the HBM budget allow, batched with
+ * whatever else is pending, and run concurrently with earlier batches.
+ * ------------------------------------------------------------------------ */
+
+/* Upload data [P][T] (host, row-major) and keep it resident.  *sid_out >= 0. */
+int mte_series_register(const float *data, int P, int64_t T, int32_t *sid_out);
+
+/* Free a series; MTE_EBUSY while requests on it are pending. */
+int mte_series_release(int32_t sid);
+
+typedef struct {
+    int32_t sid;              /* registered series */
+    int dx, dy, dz;           /* column counts (same limits as cmi_ksg) */
+    const int32_t *nodes;     /* dx+dy+dz process indices: X columns, Y, then Z */
+    const int32_t *lags;      /* matching lags (>= 0) */
+    int64_t t0;               /* first embedded time index; rows t0..t0+N-1 */
+    int64_t N;                /* rows; needs t0-lag >= 0 and t0+N-1-lag < T */
+    int k;                    /* neighbours */
+    int S;                    /* surrogates (>= 0) */
+    uint64_t seed;            /* surrogate keys pi_{seed,cand,s} */
+    uint32_t cand;
+} mte_request;
+
+/* Queue a request without blocking; copies nodes and lags. */
+int mte_submit(const mte_request *req, uint64_t *ticket_out);
+
+/* Wait for a request: cmi_out gets the estimate, surr_out (may be NULL) the S
+ * surrogates.  timeout_s < 0 waits forever.  MTE_ETIMEOUT leaves the ticket
+ * valid; any other return retires it. */
+int mte_wait(uint64_t ticket, double *cmi_out, double *surr_out, double timeout_s);
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t batches;          /* launches made by the loop */
+    int64_t estimates;        /* CMI estimates completed */
+    double p50_latency_s, p99_latency_s, mean_batch_requests;
+    int64_t peak_bytes_in_use;
+    int64_t budget_bytes;
+} mte_serve_stats;
+
+/* Statistics since the last reset (reset = 1 clears them after reading). */
+int mte_serve_get_stats(mte_serve_stats *out, int reset);
+
+/* --------------------------------------------------------------------------
+ * Compiled tile configurations of the KSG kernel.  cfg_out receives up to
+ * `capacity` rows of 6 int32: top-k capacity, estimates per lane, queries per
+ * lane, Z, Y and X column capacities; *count_out is the total number.  The
+ * environment variables MTE_FORCE_VARIANT=<row index> and MTE_FORCE_SPLIT=<m>
+ * (0: one reference split; m: m times the default number of splits) force a
+ * configuration for testing; results do not depend on either.
+ * ------------------------------------------------------------------------ */
+int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
+
+/* --------------------------------------------------------------------------
+ * Timing of the dominant kernel: when enabled, HIP events are recorded on the
+ * launch stream around every launch of the main KSG kernel and the elapsed
+ * times are accumulated (read after the stream has finished).
+ * ------------------------------------------------------------------------ */
+int mte_kernel_timing(int enable);
+int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTE_H */

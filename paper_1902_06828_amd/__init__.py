@@ -1,0 +1,35 @@
+"""MI355X (gfx950) library for the hot path of greedy multivariate
+transfer-entropy network inference (arXiv:1902.06828): the KSG
+conditional-mutual-information estimator with permutation surrogates, the
+maximum/minimum-statistic and omnibus tests, the four-step greedy source
+selection and a continuous-batching request loop.
+
+All work runs in libmte.so (HIP kernels and C++ runtime); this package only
+marshals arguments.  The C ABI is declared in include/mte.h.
+"""
+
+from ._lib import (  # noqa: F401
+    MteError,
+    cmi_ksg,
+    cmi_ksg_dev,
+    cmi_ksg_diag,
+    cmi_ksg_surrogates,
+    cmi_ksg_surrogates_dev,
+    lib,
+    mte_init,
+    mte_kernel_timing,
+    mte_kernel_timing_read,
+    mte_max_statistic,
+    mte_min_statistic,
+    mte_omnibus,
+    mte_permutation,
+    mte_select_sources,
+    mte_select_sources_sid,
+    mte_serve_get_stats,
+    mte_series_register,
+    mte_series_release,
+    mte_shutdown,
+    mte_submit,
+    mte_tile_configs,
+    mte_wait,
+)

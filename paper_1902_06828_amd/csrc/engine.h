@@ -1,0 +1,104 @@
+// Internal interface between the host runtime and the KSG kernels.
+//
+// A launch processes a list of jobs.  A job is a set of estimates of
+// I(X;Y|Z) that share the rows of Y and Z and differ only in the permutation
+// applied to the rows of X (the candidate's own estimate uses the identity,
+// its surrogates the keyed shuffles).  Different jobs of one launch may have
+// different N, column counts and k.
+//
+// Work is split into items (job, estimate group, query tile, reference split)
+// pulled from one atomic counter by a persistent grid:
+//   phase A: fused items (whole reference range: k-NN pass, then the count
+//            pass, then the digamma partial sums) for jobs with one split, and
+//            k-NN items (partial top-k over one reference range) for jobs with
+//            several splits;
+//   phase B: count items for jobs with several splits; they wait until the
+//            last k-NN item of their (job, group, tile) has merged the radii.
+// All phase-A items are handed out before any phase-B item, and waits only go
+// from phase B to phase A, so every wait ends.
+#pragma once
+
+#include <cstdint>
+
+namespace mte {
+
+constexpr int kMaxCols = 64;       // dx + dy + dz per job
+constexpr int kMaxDx = 16;
+constexpr int kMaxDy = 8;
+constexpr int kMaxDz = 31;
+constexpr int kMaxK = 16;
+constexpr int kBlock = 256;        // threads per block (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 64;         // rows per fixed-order partial sum
+
+// One estimate's surrogate key (identity when `ident` != 0).
+struct EstKey {
+    uint64_t h;        // key hash of (seed, cand, s)
+    uint32_t ident;
+    uint32_t pad;
+};
+
+struct Job {
+    const float *cols[kMaxCols];  // X columns, then Y, then Z; each N floats
+    int n, dx, dy, dz, k;
+    int n_est;                    // estimates
+    int rs;                       // reference splits (1 = fused items)
+    int split_len;                // references per split (multiple of 64)
+    int n_tiles;                  // query tiles of the launch's tile size
+    int n_groups;                 // estimate groups of the launch's group size
+    int64_t a_off, b_off;         // first item index in phase A and phase B
+    const EstKey *keys;           // [n_est]
+    float *xp;                    // [n_est][dx][n] permuted X (scratch)
+    double *chunk;                // [n_est][ceil(n/64)] partial sums (scratch)
+    float *part;                  // [rs][n_est][n][KMAX] partial top-k (rs > 1)
+    float *eps;                   // [n_est][n] radii (rs > 1, or diagnostics)
+    int32_t *cnt;                 // [rs][n_est][3][n] per-split counts (rs > 1)
+    uint32_t *sync;               // counters, see SyncLayout
+    double *out;                  // [n_est] results
+    float *diag_eps;              // optional [n_est][n]
+    int32_t *diag_cnt;            // optional [n_est][3][n] (n_xz, n_yz, n_z)
+};
+
+// Counter words of one job (all zero before a launch):
+//   [0, G*T)        k-NN items done per (group, tile)
+//   [G*T, 2*G*T)    radii ready per (group, tile)
+//   [2GT, 3GT)      count items done per (group, tile)
+//   [3GT, 3GT+G)    tiles finished per group
+inline int64_t sync_words(int n_groups, int n_tiles) {
+    return 3LL * n_groups * n_tiles + n_groups;
+}
+
+// Tile configurations compiled into the library.
+struct TileCfg {
+    int kmax;   // top-k register slots (k <= kmax)
+    int g;      // estimates per lane
+    int qp;     // queries per lane
+    int dzm;    // Z column capacity
+    int dym;    // Y column capacity
+    int dxm;    // X column capacity
+};
+
+struct LaunchInfo {
+    int64_t items_a, items_b;     // item counts of the two phases
+    int grid;                     // persistent blocks
+};
+
+// Host-side launch helpers implemented in kernels.hip.
+// jobs_dev: device copy of `n_jobs` Job records; work: 2 device words
+// (queue head, error flag) cleared by `launch_reset`.
+int kernel_variant_count();
+bool kernel_variant(int i, TileCfg *cfg);
+int variant_blocks_per_cu(int variant);
+int launch_reset(uint32_t *words, int64_t n_words, void *stream);
+int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_rows, const int64_t *row_off,
+                   void *stream);
+int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_off_dev,
+                const int64_t *b_off_dev, const LaunchInfo &li, uint32_t *work,
+                const double *harm, void *stream);
+
+// Host reference of the surrogate permutation (same definition as the device).
+uint64_t mix64(uint64_t z);
+uint64_t surrogate_key(uint64_t seed, uint32_t cand, uint32_t s);
+void permutation_host(uint64_t h, int64_t n, uint32_t *out);
+
+}  // namespace mte

@@ -1,0 +1,160 @@
+// Auxiliary kernels of the KSG launch (queue/counter reset, surrogate
+// permutation of the X columns) and the launch helpers; the main kernel's
+// device code is in ksg_device.h and its instantiations in kernels_k*.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include <vector>
+
+#include "engine.h"
+#include "ksg_device.h"
+
+namespace mte {
+
+namespace {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output function (Steele, Lea and Flood 2014).
+__device__ __forceinline__ uint64_t dmix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Swap-or-not rounds for a domain of n: max(24, 6*ceil(log2 n)).
+__device__ __forceinline__ int n_rounds_dev(int64_t n) {
+    int bits = 0;
+    for (uint64_t v = (uint64_t)(n - 1); v; v >>= 1) ++bits;
+    const int r = 6 * bits;
+    return r < 24 ? 24 : r;
+}
+
+// ------------------------------------------------------------------ permute
+// xp[e][c][i] = X_c[pi_e(i)] for every job, estimate and row.  One block per
+// (job, estimate, 1024-row chunk); the block derives the round keys in LDS.
+__global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
+                                                     const int64_t *__restrict__ blk_off) {
+    __shared__ uint64_t s_rk[192];
+    __shared__ uint32_t s_k[192];
+    __shared__ int s_job;
+    const int64_t b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
+        }
+        s_job = lo;
+    }
+    __syncthreads();
+    const Job &J = jobs[s_job];
+    const int64_t local = b - blk_off[s_job];
+    const int chunks = (J.n + 1023) / 1024;
+    const int e = (int)(local / chunks);
+    const int c0 = (int)(local % chunks) * 1024;
+    const EstKey key = J.keys[e];
+    const int rounds = n_rounds_dev(J.n);
+    if (!key.ident) {
+        for (int r = threadIdx.x; r < rounds; r += blockDim.x) {
+            uint64_t rk = dmix64(key.h + (uint64_t)(r + 1) * kGolden);
+            s_rk[r] = rk;
+            s_k[r] = (uint32_t)(((rk >> 32) * (uint64_t)J.n) >> 32);
+        }
+    }
+    __syncthreads();
+    const uint32_t n = (uint32_t)J.n;
+    for (int ii = threadIdx.x; ii < 1024; ii += blockDim.x) {
+        const int i = c0 + ii;
+        if (i >= J.n) break;
+        uint32_t x = (uint32_t)i;
+        if (!key.ident) {
+            for (int r = 0; r < rounds; ++r) {
+                const uint32_t k = s_k[r];
+                const uint32_t xp = (x <= k) ? (k - x) : (k - x + n);
+                const uint32_t hi = x > xp ? x : xp;
+                if (dmix64((uint64_t)hi ^ s_rk[r]) >> 63) x = xp;
+            }
+        }
+        for (int c = 0; c < J.dx; ++c)
+            J.xp[((int64_t)e * J.dx + c) * J.n + i] = J.cols[c][x];
+    }
+}
+
+__global__ void reset_kernel(uint32_t *__restrict__ w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0u;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ variants
+// Compiled in kernels_k4.hip, kernels_k8.hip and kernels_k16.hip (one top-k
+// capacity each, built in parallel).
+const dev::VariantEntry *variants_k4(int *n);
+const dev::VariantEntry *variants_k8(int *n);
+const dev::VariantEntry *variants_k16(int *n);
+
+namespace {
+struct Registry {
+    std::vector<dev::VariantEntry> v;
+    Registry() {
+        int n = 0;
+        const dev::VariantEntry *p = variants_k4(&n);
+        v.insert(v.end(), p, p + n);
+        p = variants_k8(&n);
+        v.insert(v.end(), p, p + n);
+        p = variants_k16(&n);
+        v.insert(v.end(), p, p + n);
+    }
+};
+const Registry &registry() {
+    static Registry r;
+    return r;
+}
+}  // namespace
+
+int kernel_variant_count() { return (int)registry().v.size(); }
+
+bool kernel_variant(int i, TileCfg *cfg) {
+    if (i < 0 || i >= kernel_variant_count()) return false;
+    *cfg = registry().v[i].cfg;
+    return true;
+}
+
+int variant_blocks_per_cu(int v) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, registry().v[v].fn, kBlock, 0) != hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+int launch_reset(uint32_t *words, int64_t n_words, void *stream) {
+    if (n_words <= 0) return 0;
+    int64_t blocks = (n_words + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, words,
+                       n_words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_blocks, const int64_t *blk_off,
+                   void *stream) {
+    if (total_blocks <= 0) return 0;
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)total_blocks), dim3(256), 0, (hipStream_t)stream,
+                       jobs_dev, n_jobs, blk_off);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_main(int v, const Job *jobs_dev, int n_jobs, const int64_t *a_off, const int64_t *b_off,
+                const LaunchInfo &li, uint32_t *work, const double *harm, void *stream) {
+    void *args[] = {(void *)&jobs_dev, (void *)&n_jobs, (void *)&a_off, (void *)&b_off,
+                    (void *)&li.items_a, (void *)&li.items_b, (void *)&work, (void *)&harm};
+    hipError_t e = hipLaunchKernel(registry().v[v].fn, dim3(li.grid), dim3(kBlock), args, 0,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mte

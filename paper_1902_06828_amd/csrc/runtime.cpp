@@ -1,0 +1,603 @@
+// Host runtime: errors, device memory, the harmonic table, batch layout and
+// launch, HIP graph capture, and the tile autotuner.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace mte {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string t_err = "no error";
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? MTE_ENOMEM : MTE_EDEVICE, "%s failed: %s", what,
+                hipGetErrorString(e));
+}
+
+const char *last_error() { return t_err.c_str(); }
+
+// ---------------------------------------------------------------- memory
+static size_t round_size(size_t b) {
+    const size_t g = b < (16u << 20) ? (64u << 10) : (2u << 20);
+    return (b + g - 1) / g * g;
+}
+
+void *DeviceAllocator::alloc(size_t bytes) {
+    bytes = round_size(bytes ? bytes : 1);
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find(bytes);
+    void *p = nullptr;
+    if (it != free_.end()) {
+        p = it->second;
+        free_.erase(it);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto &kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    in_use_ += bytes;
+    peak_ = std::max(peak_, in_use_);
+    return p;
+}
+
+void DeviceAllocator::release(void *p, size_t bytes) {
+    if (!p) return;
+    bytes = round_size(bytes ? bytes : 1);
+    std::lock_guard<std::mutex> lk(mu_);
+    in_use_ -= bytes;
+    free_.emplace(bytes, p);
+}
+
+void DeviceAllocator::trim() {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto &kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+}
+
+DevBuf::~DevBuf() { reset(); }
+
+void DevBuf::reset() {
+    if (p) ctx().alloc.release(p, bytes);
+    p = nullptr;
+    bytes = 0;
+}
+
+int DevBuf::ensure(size_t n) {
+    if (n <= bytes && p) return MTE_OK;
+    if (p) ctx().alloc.release(p, bytes);
+    p = ctx().alloc.alloc(n);
+    bytes = p ? n : 0;
+    return p ? MTE_OK : fail(MTE_ENOMEM, "device allocation of %zu bytes failed", n);
+}
+
+HostBuf::~HostBuf() { reset(); }
+
+void HostBuf::reset() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+int HostBuf::ensure(size_t n) {
+    if (n <= bytes && p) return MTE_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    MTE_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+    bytes = n;
+    return MTE_OK;
+}
+
+// ---------------------------------------------------------------- context
+Ctx &ctx() {
+    static Ctx c;
+    return c;
+}
+
+static int init_locked(int device, size_t budget) {
+    Ctx &c = ctx();
+    if (c.inited) {
+        if (device != c.device) return fail(MTE_EINVAL, "already initialised on device %d", c.device);
+        MTE_HIP(hipSetDevice(c.device));
+        if (budget) c.budget = budget;
+        return MTE_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(MTE_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return fail(MTE_EINVAL, "device %d out of range (%d devices)", device, n);
+    MTE_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    MTE_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MTE_EDEVICE, "libmte is built for gfx950, device is %s", prop.gcnArchName);
+    c.device = device;
+    c.n_cu = prop.multiProcessorCount;
+    size_t fr = 0, tot = 0;
+    MTE_HIP(hipMemGetInfo(&fr, &tot));
+    c.budget = budget ? budget : (size_t)(0.9 * (double)fr);
+    MTE_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+    c.inited = true;
+    return MTE_OK;
+}
+
+int init_device(int device, size_t budget) {
+    std::lock_guard<std::mutex> lk(ctx().mu);
+    return init_locked(device, budget);
+}
+
+int ensure_init() {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.inited) {
+        MTE_HIP(hipSetDevice(c.device));
+        return MTE_OK;
+    }
+    return init_locked(0, 0);
+}
+
+double harmonic_host(int64_t n) {
+    double h = 0.0;
+    for (int64_t m = 1; m <= n; ++m) h += 1.0 / (double)m;
+    return h;
+}
+
+int ensure_harm(int64_t n) {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.harm && n <= c.harm_n) return MTE_OK;
+    int64_t cap = std::max<int64_t>(n, std::max<int64_t>(2 * c.harm_n, int64_t(1) << 20));
+    std::vector<double> h((size_t)cap + 1);
+    h[0] = 0.0;
+    for (int64_t m = 1; m <= cap; ++m) h[(size_t)m] = h[(size_t)m - 1] + 1.0 / (double)m;
+    double *d = nullptr;
+    MTE_HIP(hipMalloc(&d, sizeof(double) * h.size()));
+    MTE_HIP(hipMemcpy(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+    if (c.harm) c.retired.push_back(c.harm);
+    c.harm = d;
+    c.harm_n = cap;
+    return MTE_OK;
+}
+
+const double *harm_table() { return ctx().harm; }
+
+int shutdown_all() {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (!c.inited) return MTE_OK;
+    MTE_HIP(hipDeviceSynchronize());
+    for (auto &pe : c.pending_events) {
+        (void)hipEventDestroy(pe.first);
+        (void)hipEventDestroy(pe.second);
+    }
+    c.pending_events.clear();
+    if (c.harm) (void)hipFree(c.harm);
+    for (double *p : c.retired) (void)hipFree(p);
+    c.retired.clear();
+    c.harm = nullptr;
+    c.harm_n = 0;
+    c.alloc.trim();
+    if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
+    c.capture_stream = nullptr;
+    c.tuned.clear();
+    c.inited = false;
+    c.device = -1;
+    return MTE_OK;
+}
+
+// ---------------------------------------------------------------- validation
+int validate_dims(int dx, int dy, int dz, int64_t n, int k) {
+    if (dx < 1 || dx > kMaxDx) return fail(MTE_EINVAL, "dx=%d out of range [1,%d]", dx, kMaxDx);
+    if (dy < 1 || dy > kMaxDy) return fail(MTE_EINVAL, "dy=%d out of range [1,%d]", dy, kMaxDy);
+    if (dz < 0 || dz > kMaxDz) return fail(MTE_EINVAL, "dz=%d out of range [0,%d]", dz, kMaxDz);
+    if (k < 1 || k > kMaxK) return fail(MTE_EINVAL, "k=%d out of range [1,%d]", k, kMaxK);
+    if (n < (int64_t)k + 1) return fail(MTE_EINVAL, "N=%lld must be at least k+1", (long long)n);
+    if (n > 0x7fffffffLL) return fail(MTE_EINVAL, "N=%lld exceeds 2^31-1", (long long)n);
+    return MTE_OK;
+}
+
+int validate_host_finite(const float *p, int64_t count, const char *name) {
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(p[i]))
+            return fail(MTE_EINVAL, "%s[%lld] is not finite", name, (long long)i);
+    return MTE_OK;
+}
+
+void record_timing_pair(hipEvent_t a, hipEvent_t b) {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.pending_events.emplace_back(a, b);
+}
+
+// ---------------------------------------------------------------- tiles
+static int kmax_class(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : 16); }
+
+struct Need {
+    int k = 0, dx = 0, dy = 0, dz = 0;
+};
+
+static Need need_of(const std::vector<JobSpec> &specs) {
+    Need n;
+    for (const auto &s : specs) {
+        n.k = std::max(n.k, s.k);
+        n.dx = std::max(n.dx, s.dx);
+        n.dy = std::max(n.dy, s.dy);
+        n.dz = std::max(n.dz, s.dz);
+    }
+    return n;
+}
+
+static bool fits(const TileCfg &c, const Need &n) {
+    return c.kmax == kmax_class(n.k) && c.dxm >= n.dx && c.dym >= n.dy && c.dzm >= n.dz;
+}
+
+int variant_for(const std::vector<JobSpec> &specs, int g_pref) {
+    const Need nd = need_of(specs);
+    int best = -1;
+    TileCfg bc{};
+    // smallest column capacities first, then the largest G <= g_pref
+    auto score = [&](const TileCfg &t) {
+        int gpen = t.g <= g_pref ? (g_pref - t.g) : 100 + t.g;
+        return std::make_tuple(t.dxm, t.dym, t.dzm, gpen);
+    };
+    for (int v = 0; v < kernel_variant_count(); ++v) {
+        TileCfg c;
+        kernel_variant(v, &c);
+        if (!fits(c, nd)) continue;
+        if (best < 0 || score(c) < score(bc)) { best = v; bc = c; }
+    }
+    return best;
+}
+
+static std::string shape_key(const std::vector<JobSpec> &specs) {
+    int64_t nsum = 0, esum = 0;
+    int dxm = 0, dym = 0, dzm = 0, km = 0;
+    for (const auto &s : specs) {
+        nsum += s.n;
+        esum += s.n_est();
+        dxm = std::max(dxm, s.dx);
+        dym = std::max(dym, s.dy);
+        dzm = std::max(dzm, s.dz);
+        km = std::max(km, s.k);
+    }
+    char buf[160];
+    snprintf(buf, sizeof buf, "j%zu:n%lld:e%lld:dx%d:dy%d:dz%d:k%d", specs.size(), (long long)nsum,
+             (long long)esum, dxm, dym, dzm, km);
+    return buf;
+}
+
+static int g_pref_for(const std::vector<JobSpec> &specs) {
+    int64_t e = 0;
+    for (const auto &s : specs) e += s.n_est();
+    const double avg = (double)e / (double)std::max<size_t>(1, specs.size());
+    return avg >= 16 ? 8 : (avg >= 4 ? 4 : 1);
+}
+
+static int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, bool tune, TileChoice *out) {
+    Ctx &c = ctx();
+    // test hooks: MTE_FORCE_VARIANT (tile configuration index, used when it
+    // fits) and MTE_FORCE_SPLIT (0 = one reference split, m = m times the
+    // heuristic split count)
+    const int fv = env_int("MTE_FORCE_VARIANT", -1), fs = env_int("MTE_FORCE_SPLIT", -1);
+    if (fv >= 0 || fs >= 0) {
+        TileChoice tc;
+        tc.variant = variant_for(specs, g_pref_for(specs));
+        tc.rs_mult = fs >= 0 ? fs : 1;
+        TileCfg fc;
+        if (fv >= 0 && kernel_variant(fv, &fc) && fits(fc, need_of(specs))) tc.variant = fv;
+        if (tc.variant < 0) return fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions");
+        *out = tc;
+        return MTE_OK;
+    }
+    const std::string key = shape_key(specs);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.tuned.find(key);
+        if (it != c.tuned.end()) { *out = it->second; return MTE_OK; }
+    }
+    TileChoice heur;
+    heur.variant = variant_for(specs, g_pref_for(specs));
+    heur.rs_mult = 1;
+    if (heur.variant < 0) return fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions");
+    if (!tune) { *out = heur; return MTE_OK; }
+    // candidate set: every fitting variant with the exact k class, and split
+    // multipliers 0 (one split), 1, 2
+    std::vector<TileChoice> cand;
+    const Need nd = need_of(specs);
+    TileCfg hc;
+    kernel_variant(heur.variant, &hc);
+    for (int v = 0; v < kernel_variant_count(); ++v) {
+        TileCfg t;
+        kernel_variant(v, &t);
+        if (!fits(t, nd) || t.dxm != hc.dxm || t.dym != hc.dym || t.dzm > hc.dzm) continue;
+        for (int m : {0, 1, 2}) cand.push_back(TileChoice{v, m});
+    }
+    hipEvent_t e0, e1;
+    MTE_HIP(hipEventCreate(&e0));
+    MTE_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    TileChoice best = heur;
+    for (const auto &tc : cand) {
+        Batch b;
+        if (b.prepare(specs, tc, s) != MTE_OK) continue;
+        if (b.enqueue(s, false) != MTE_OK) continue;      // warm-up
+        (void)hipEventRecord(e0, s);
+        if (b.enqueue(s, false) != MTE_OK) continue;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) continue;
+        if (b.check_error(s) != MTE_OK) continue;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = tc; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.tuned[key] = best;
+    }
+    *out = best;
+    return MTE_OK;
+}
+
+// ---------------------------------------------------------------- batch
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Batch::~Batch() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+}
+
+size_t Batch::device_bytes() const { return tables_.bytes + scratch_.bytes + sync_.bytes; }
+
+int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+    Ctx &c = ctx();
+    if (specs.empty()) return fail(MTE_EINVAL, "empty batch");
+    TileCfg cfg;
+    if (!kernel_variant(tc.variant, &cfg)) return fail(MTE_EINVAL, "bad tile variant");
+    variant_ = tc.variant;
+    n_jobs_ = (int)specs.size();
+    int64_t nmax = 0;
+    for (const auto &sp : specs) {
+        if (sp.n_est() < 1) return fail(MTE_EINVAL, "job without estimates");
+        if (sp.k > cfg.kmax || sp.dx > cfg.dxm || sp.dy > cfg.dym || sp.dz > cfg.dzm)
+            return fail(MTE_EINVAL, "job does not fit the tile configuration");
+        if (sp.n < sp.k + 1) return fail(MTE_EINVAL, "N < k+1");
+        for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc)
+            if (!sp.cols[cc]) return fail(MTE_EINVAL, "null column pointer");
+        if (!sp.out) return fail(MTE_EINVAL, "null output pointer");
+        nmax = std::max<int64_t>(nmax, sp.n);
+    }
+    int rc = ensure_harm(nmax);
+    if (rc) return rc;
+    const int qt = kWaves * 64 * cfg.qp;
+    const int bpc = variant_blocks_per_cu(variant_);
+    const int64_t slots = (int64_t)c.n_cu * bpc;
+    int64_t base_items = 0;
+    for (const auto &sp : specs)
+        base_items += (int64_t)((sp.n_est() + cfg.g - 1) / cfg.g) * ((sp.n + qt - 1) / qt);
+    int64_t rs_base = 1;
+    if (tc.rs_mult > 0 && base_items < 3 * slots) rs_base = (3 * slots + base_items - 1) / base_items;
+    if (tc.rs_mult > 1) rs_base *= tc.rs_mult;
+
+    // layout
+    std::vector<Job> jobs(n_jobs_);
+    std::vector<int64_t> a_off(n_jobs_ + 1), b_off(n_jobs_ + 1), blk_off(n_jobs_ + 1);
+    size_t scratch_bytes = 0;
+    int64_t sync_words_total = 2;   // queue head + error flag
+    struct Off { size_t xp, chunk, part, eps, cnt; int64_t sync; };
+    std::vector<Off> offs(n_jobs_);
+    int64_t n_keys = 0;
+    a_off[0] = b_off[0] = blk_off[0] = 0;
+    for (int j = 0; j < n_jobs_; ++j) {
+        const JobSpec &sp = specs[j];
+        Job &J = jobs[j];
+        std::memset(&J, 0, sizeof J);
+        for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
+        J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
+        J.n_est = sp.n_est();
+        J.n_tiles = (sp.n + qt - 1) / qt;
+        J.n_groups = (J.n_est + cfg.g - 1) / cfg.g;
+        int64_t rs = rs_base;
+        const int64_t max_rs = std::max<int64_t>(1, sp.n / 256);
+        rs = std::min(rs, max_rs);
+        int64_t split_len = ((sp.n + rs - 1) / rs + 63) / 64 * 64;
+        rs = (sp.n + split_len - 1) / split_len;
+        J.rs = (int)rs;
+        J.split_len = (int)split_len;
+        const int64_t items = (int64_t)J.n_groups * J.n_tiles * J.rs;
+        a_off[j + 1] = a_off[j] + items;
+        b_off[j + 1] = b_off[j] + (J.rs > 1 ? items : 0);
+        blk_off[j + 1] = blk_off[j] + (int64_t)J.n_est * ((sp.n + 1023) / 1024);
+        J.a_off = a_off[j];
+        J.b_off = b_off[j];
+        const int64_t nch = (sp.n + kChunk - 1) / kChunk;
+        Off &o = offs[j];
+        o.xp = scratch_bytes;
+        scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.n_est * sp.dx * sp.n, 256);
+        o.chunk = scratch_bytes;
+        scratch_bytes = align_up(scratch_bytes + sizeof(double) * (size_t)J.n_est * nch, 256);
+        if (J.rs > 1) {
+            o.part = scratch_bytes;
+            scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.rs * J.n_est * sp.n * cfg.kmax, 256);
+            o.eps = scratch_bytes;
+            scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.n_est * sp.n, 256);
+            o.cnt = scratch_bytes;
+            scratch_bytes = align_up(scratch_bytes + sizeof(int32_t) * (size_t)J.rs * J.n_est * 3 * sp.n, 256);
+        }
+        o.sync = sync_words_total;
+        sync_words_total += sync_words(J.n_groups, J.n_tiles);
+        sync_words_total = (sync_words_total + 63) / 64 * 64;
+        J.out = sp.out;
+        J.diag_eps = sp.diag_eps;
+        J.diag_cnt = sp.diag_cnt;
+        n_keys += J.n_est;
+    }
+    li_.items_a = a_off[n_jobs_];
+    li_.items_b = b_off[n_jobs_];
+    const int64_t total = li_.items_a + li_.items_b;
+    if (total >= (int64_t)0x7fffffff) return fail(MTE_EINVAL, "batch too large");
+    li_.grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, slots));
+    permute_blocks_ = blk_off[n_jobs_];
+    sync_total_ = sync_words_total;
+    n_est_total_ = n_keys;
+
+    if ((rc = scratch_.ensure(std::max<size_t>(scratch_bytes, 256)))) return rc;
+    if ((rc = sync_.ensure(sizeof(uint32_t) * (size_t)sync_total_))) return rc;
+    uint8_t *sb = scratch_.as<uint8_t>();
+    uint32_t *sy = sync_.as<uint32_t>();
+    work_ = sy;
+    const size_t tbl_jobs = align_up(sizeof(Job) * n_jobs_, 256);
+    const size_t tbl_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
+    const size_t tbl_offs = align_up(sizeof(int64_t) * 3 * (n_jobs_ + 1), 256);
+    const size_t tbl_bytes = tbl_jobs + tbl_keys + tbl_offs;
+    if ((rc = tables_.ensure(tbl_bytes))) return rc;
+    // pinned staging, reused by this thread (the copy below completes before
+    // prepare returns)
+    static thread_local HostBuf staging;
+    if ((rc = staging.ensure(tbl_bytes))) return rc;
+    uint8_t *tb = tables_.as<uint8_t>();
+    uint8_t *hs = static_cast<uint8_t *>(staging.p);
+    EstKey *keys_dev = reinterpret_cast<EstKey *>(tb + tbl_jobs);
+    EstKey *keys_host = reinterpret_cast<EstKey *>(hs + tbl_jobs);
+    int64_t kpos = 0;
+    for (int j = 0; j < n_jobs_; ++j) {
+        Job &J = jobs[j];
+        const Off &o = offs[j];
+        J.xp = reinterpret_cast<float *>(sb + o.xp);
+        J.chunk = reinterpret_cast<double *>(sb + o.chunk);
+        if (J.rs > 1) {
+            J.part = reinterpret_cast<float *>(sb + o.part);
+            J.eps = reinterpret_cast<float *>(sb + o.eps);
+            J.cnt = reinterpret_cast<int32_t *>(sb + o.cnt);
+        }
+        J.sync = sy + o.sync;
+        J.keys = keys_dev + kpos;
+        std::memcpy(keys_host + kpos, specs[j].keys.data(), sizeof(EstKey) * J.n_est);
+        kpos += J.n_est;
+    }
+    std::memcpy(hs, jobs.data(), sizeof(Job) * n_jobs_);
+    int64_t *offs_host = reinterpret_cast<int64_t *>(hs + tbl_jobs + tbl_keys);
+    std::memcpy(offs_host, a_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    std::memcpy(offs_host + (n_jobs_ + 1), b_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    std::memcpy(offs_host + 2 * (n_jobs_ + 1), blk_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    jobs_dev_ = reinterpret_cast<Job *>(tb);
+    a_off_ = reinterpret_cast<int64_t *>(tb + tbl_jobs + tbl_keys);
+    b_off_ = a_off_ + (n_jobs_ + 1);
+    blk_off_ = b_off_ + (n_jobs_ + 1);
+    MTE_HIP(hipMemcpyAsync(tb, hs, tbl_bytes, hipMemcpyHostToDevice, s));
+    // the staging buffer must not be rewritten before the copy has run
+    MTE_HIP(hipStreamSynchronize(s));
+    return MTE_OK;
+}
+
+int Batch::launch_direct(hipStream_t s) {
+    if (launch_reset(sync_.as<uint32_t>(), sync_total_, s)) return hip_fail(hipGetLastError(), "reset launch");
+    if (launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, s))
+        return hip_fail(hipGetLastError(), "permute launch");
+    Ctx &c = ctx();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c.timing) {
+        MTE_HIP(hipEventCreate(&e0));
+        MTE_HIP(hipEventCreate(&e1));
+        MTE_HIP(hipEventRecord(e0, s));
+    }
+    if (launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), s))
+        return hip_fail(hipGetLastError(), "main kernel launch");
+    if (c.timing) {
+        MTE_HIP(hipEventRecord(e1, s));
+        record_timing_pair(e0, e1);
+    }
+    return MTE_OK;
+}
+
+int Batch::capture() {
+    Ctx &c = ctx();
+    hipStream_t cs = c.capture_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        graph_failed_ = true;
+        return MTE_OK;
+    }
+    bool ok = launch_reset(sync_.as<uint32_t>(), sync_total_, cs) == 0 &&
+              launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, cs) == 0 &&
+              launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), cs) == 0;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (!ok || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        graph_failed_ = true;
+        return MTE_OK;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        graph_failed_ = true;
+        return MTE_OK;
+    }
+    graph_ = g;
+    exec_ = x;
+    return MTE_OK;
+}
+
+int Batch::enqueue(hipStream_t s, bool use_graph) {
+    if (use_graph && !ctx().timing && !graph_failed_) {
+        if (!exec_) {
+            int rc = capture();
+            if (rc) return rc;
+        }
+        if (exec_) {
+            MTE_HIP(hipGraphLaunch(exec_, s));
+            return MTE_OK;
+        }
+    }
+    return launch_direct(s);
+}
+
+int Batch::check_error(hipStream_t s) {
+    uint32_t flag = 0;
+    MTE_HIP(hipMemcpyAsync(&flag, work_ + 1, sizeof flag, hipMemcpyDeviceToHost, s));
+    MTE_HIP(hipStreamSynchronize(s));
+    if (flag) return fail(MTE_EDEVICE, "a kernel exceeded its bounded wait");
+    return MTE_OK;
+}
+
+int run_blocking(const std::vector<JobSpec> &specs, hipStream_t s) {
+    TileChoice tc;
+    int rc = choose_tiles(specs, s, false, &tc);
+    if (rc) return rc;
+    Batch b;
+    if ((rc = b.prepare(specs, tc, s))) return rc;
+    if ((rc = b.enqueue(s, false))) return rc;
+    return b.check_error(s);
+}
+
+}  // namespace mte

@@ -1,0 +1,163 @@
+// Host runtime shared by the C ABI, the greedy driver and the request loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "mte.h"
+
+namespace mte {
+
+// ---------------------------------------------------------------- errors
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+#define MTE_HIP(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return ::mte::hip_fail(e_, #expr); \
+    } while (0)
+
+// ---------------------------------------------------------------- memory
+// Caching device allocator: freed blocks are kept by exact size and reused.
+class DeviceAllocator {
+public:
+    void *alloc(size_t bytes);          // nullptr on failure
+    void release(void *p, size_t bytes);
+    void trim();                        // free every cached block
+    size_t in_use() const { return in_use_; }
+    size_t peak() const { return peak_; }
+    void reset_peak() { peak_ = in_use_; }
+private:
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+    size_t in_use_ = 0, peak_ = 0;
+};
+
+// RAII device buffer from the context allocator.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    int ensure(size_t n);               // MTE_OK or MTE_ENOMEM
+    void reset();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Pinned host staging buffer.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf();
+    int ensure(size_t n);
+    void reset();
+};
+
+// ---------------------------------------------------------------- jobs
+// Host description of one job (device pointers for the columns and outputs).
+struct JobSpec {
+    const float *cols[kMaxCols] = {};
+    int n = 0, dx = 0, dy = 0, dz = 0, k = 0;
+    std::vector<EstKey> keys;          // one per estimate
+    double *out = nullptr;             // device [n_est]
+    float *diag_eps = nullptr;         // device [n_est][n] or null
+    int32_t *diag_cnt = nullptr;       // device [n_est][3][n] or null
+    int n_est() const { return (int)keys.size(); }
+};
+
+struct TileChoice {
+    int variant = -1;
+    int rs_mult = 1;                   // multiplier on the heuristic split count
+};
+
+// One launch: its tables, scratch and (optionally) a captured graph.
+class Batch {
+public:
+    ~Batch();
+    // Lay out and upload everything for `specs` with the given tile choice.
+    int prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s);
+    // Enqueue reset -> permute -> main kernel on s (graph replay if captured).
+    int enqueue(hipStream_t s, bool use_graph);
+    // Non-zero when a kernel reported an error (reads a device word; syncs s).
+    int check_error(hipStream_t s);
+    size_t device_bytes() const;
+    int variant() const { return variant_; }
+    int64_t estimates() const { return n_est_total_; }
+private:
+    int capture();
+    int launch_direct(hipStream_t s);
+    int variant_ = -1;
+    int n_jobs_ = 0;
+    int64_t n_est_total_ = 0;
+    LaunchInfo li_{};
+    int64_t permute_blocks_ = 0;
+    int64_t sync_total_ = 0;           // words, including the 2 work words
+    DevBuf tables_, scratch_, sync_;
+    Job *jobs_dev_ = nullptr;
+    int64_t *a_off_ = nullptr, *b_off_ = nullptr, *blk_off_ = nullptr;
+    uint32_t *work_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    bool graph_failed_ = false;
+};
+
+// ---------------------------------------------------------------- context
+struct Ctx {
+    std::mutex mu;
+    bool inited = false;
+    int device = -1;
+    int n_cu = 0;
+    size_t budget = 0;
+    hipStream_t capture_stream = nullptr;
+    DeviceAllocator alloc;
+    // harmonic numbers H[0..harm_n]; old tables stay alive until shutdown
+    double *harm = nullptr;
+    int64_t harm_n = 0;
+    std::vector<double *> retired;
+    // autotuner: shape key -> choice
+    std::map<std::string, TileChoice> tuned;
+    // kernel timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
+    int64_t timed_launches = 0;
+    double timed_ms = 0.0;
+};
+
+Ctx &ctx();
+int ensure_init();                     // lazily initialises device 0
+int ensure_harm(int64_t n);            // H table covers 0..n
+const double *harm_table();
+
+// Pick the tile variant classes for a set of jobs; -1 if nothing fits.
+int variant_for(const std::vector<JobSpec> &specs, int g_pref);
+// Choose (variant, split multiplier) for a batch, running the autotuner on
+// the first call for a shape when `tune` is set.
+int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, bool tune, TileChoice *out);
+
+// Run a batch to completion on an internal stream (used by the host-pointer
+// calls and the greedy driver).  Outputs land in the JobSpec device buffers.
+int run_blocking(const std::vector<JobSpec> &specs, hipStream_t s);
+
+// Validation shared by the entry points.
+int validate_dims(int dx, int dy, int dz, int64_t n, int k);
+int validate_host_finite(const float *p, int64_t count, const char *name);
+
+// Host mirror of the device harmonic table (same summation order).
+double harmonic_host(int64_t n);
+
+void record_timing_pair(hipEvent_t a, hipEvent_t b);
+
+}  // namespace mte

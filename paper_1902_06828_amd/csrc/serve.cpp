@@ -1,0 +1,424 @@
+// Request loop: resident series, admission by HBM footprint, continuous
+// batching over several HIP streams, latency statistics.
+//
+// A worker thread owns the GPU side.  Each turn it (1) retires batches whose
+// completion event has fired, (2) while a stream slot is free and requests
+// are pending, forms one batch from the pending queue in arrival order,
+// bounded by the remaining HBM budget, and launches it, and (3) sleeps
+// briefly.  Requests that arrive while earlier batches are on the GPU are
+// admitted into the next batch as soon as a slot and memory free up; that
+// batch runs on another stream, so its blocks start as the earlier kernel's
+// persistent blocks drain.  Each estimate's result does not depend on the
+// batch it ran in (exact counts, fixed-order sums).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "runtime.h"
+
+namespace mte {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Series {
+    std::unique_ptr<DevBuf> buf;
+    int P = 0;
+    int64_t T = 0;
+    int pending = 0;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    mte_request r{};
+    std::vector<int32_t> nodes, lags;
+    Clock::time_point t_submit, t_done;
+    int state = 0;                 // 0 queued, 1 on the GPU, 2 done
+    int status = MTE_OK;
+    std::string error;
+    std::vector<double> result;    // 1 + S
+};
+
+struct Slot {
+    bool busy = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::unique_ptr<Batch> batch;
+    std::vector<std::shared_ptr<Req>> reqs;
+    DevBuf out;
+    HostBuf hout;
+    size_t bytes = 0;
+};
+
+constexpr int kSlots = 3;
+constexpr size_t kMaxBatchRequests = 512;
+
+class Server {
+public:
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::unordered_map<int32_t, Series> series;
+    int32_t next_sid = 0;
+    std::deque<std::shared_ptr<Req>> queue;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    Slot slots[kSlots];
+    std::thread worker;
+    bool running = false, stop = false;
+    size_t bytes_in_flight = 0;
+    // statistics
+    int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, estimates = 0, batch_reqs = 0;
+    std::vector<double> latencies;
+    size_t peak_bytes = 0;
+
+    int start_locked() {
+        if (running) return MTE_OK;
+        int rc = ensure_init();
+        if (rc) return rc;
+        for (auto &s : slots) {
+            if (!s.stream) MTE_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+            if (!s.done) MTE_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        }
+        stop = false;
+        running = true;
+        const int dev = ctx().device;
+        worker = std::thread([this, dev] { loop(dev); });
+        return MTE_OK;
+    }
+
+    void finish_req(const std::shared_ptr<Req> &q, int status, const char *msg) {
+        q->status = status;
+        if (msg) q->error = msg;
+        q->state = 2;
+        q->t_done = Clock::now();
+        auto it = series.find(q->r.sid);
+        if (it != series.end()) it->second.pending--;
+        if (status == MTE_OK) {
+            completed++;
+            estimates += (int64_t)q->result.size();
+            latencies.push_back(std::chrono::duration<double>(q->t_done - q->t_submit).count());
+        } else {
+            rejected++;
+        }
+    }
+
+    // Retire finished slots (called with mu held).
+    void retire() {
+        for (auto &s : slots) {
+            if (!s.busy) continue;
+            hipError_t e = hipEventQuery(s.done);
+            if (e == hipErrorNotReady) continue;
+            int status = e == hipSuccess ? MTE_OK : MTE_EDEVICE;
+            if (status == MTE_OK && s.batch->check_error(s.stream) != MTE_OK) status = MTE_EDEVICE;
+            const double *h = static_cast<const double *>(s.hout.p);
+            size_t pos = 0;
+            for (auto &q : s.reqs) {
+                const size_t E = (size_t)q->r.S + 1;
+                if (status == MTE_OK) q->result.assign(h + pos, h + pos + E);
+                pos += E;
+                finish_req(q, status, status ? "kernel failure" : nullptr);
+            }
+            s.reqs.clear();
+            s.batch.reset();
+            bytes_in_flight -= s.bytes;
+            s.bytes = 0;
+            s.busy = false;
+            cv_done.notify_all();
+        }
+    }
+
+    JobSpec spec_for(const Req &q, double *out) {
+        const Series &se = series.at(q.r.sid);
+        JobSpec sp;
+        const int d = q.r.dx + q.r.dy + q.r.dz;
+        for (int c = 0; c < d; ++c)
+            sp.cols[c] = se.buf->as<float>() + (size_t)q.nodes[c] * se.T + (q.r.t0 - q.lags[c]);
+        sp.n = (int)q.r.N;
+        sp.dx = q.r.dx;
+        sp.dy = q.r.dy;
+        sp.dz = q.r.dz;
+        sp.k = q.r.k;
+        sp.keys.resize((size_t)q.r.S + 1);
+        sp.keys[0] = EstKey{0, 1, 0};
+        for (int s = 0; s < q.r.S; ++s)
+            sp.keys[(size_t)s + 1] = EstKey{surrogate_key(q.r.seed, q.r.cand, (uint32_t)s), 0, 0};
+        sp.out = out;
+        return sp;
+    }
+
+    // Form and launch one batch on slot s from the queue front (mu held).
+    void admit(Slot &s) {
+        const size_t budget = ctx().budget;
+        std::vector<std::shared_ptr<Req>> take;
+        size_t n_out = 0;
+        for (auto &q : queue) {
+            if (take.size() >= kMaxBatchRequests) break;
+            take.push_back(q);
+            n_out += (size_t)q->r.S + 1;
+        }
+        while (!take.empty()) {
+            int rc = s.out.ensure(sizeof(double) * n_out);
+            if (rc == MTE_OK) rc = s.hout.ensure(sizeof(double) * n_out);
+            std::vector<JobSpec> specs;
+            size_t pos = 0;
+            for (auto &q : take) {
+                specs.push_back(spec_for(*q, s.out.as<double>() + pos));
+                pos += (size_t)q->r.S + 1;
+            }
+            auto b = std::make_unique<Batch>();
+            TileChoice tc;
+            if (rc == MTE_OK) rc = choose_tiles(specs, s.stream, false, &tc);
+            if (rc == MTE_OK) rc = b->prepare(specs, tc, s.stream);
+            const size_t bytes = rc == MTE_OK ? b->device_bytes() + s.out.bytes : 0;
+            if (rc == MTE_OK && bytes_in_flight + bytes > budget) {
+                if (take.size() == 1) {
+                    if (bytes > budget) {
+                        // can never fit: reject
+                        finish_req(take[0], MTE_ENOMEM, "request exceeds the HBM budget");
+                        queue.pop_front();
+                        cv_done.notify_all();
+                    }
+                    return;   // wait for memory
+                }
+                n_out = 0;
+                take.resize(take.size() / 2);
+                for (auto &q : take) n_out += (size_t)q->r.S + 1;
+                continue;
+            }
+            if (rc != MTE_OK) {
+                for (auto &q : take) finish_req(q, rc, "batch preparation failed");
+                queue.erase(queue.begin(), queue.begin() + (long)take.size());
+                cv_done.notify_all();
+                return;
+            }
+            rc = b->enqueue(s.stream, false);
+            if (rc == MTE_OK && hipMemcpyAsync(s.hout.p, s.out.p, sizeof(double) * n_out,
+                                               hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+                rc = MTE_EDEVICE;
+            if (rc == MTE_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rc = MTE_EDEVICE;
+            if (rc != MTE_OK) {
+                (void)hipStreamSynchronize(s.stream);
+                for (auto &q : take) finish_req(q, MTE_EDEVICE, "launch failed");
+                queue.erase(queue.begin(), queue.begin() + (long)take.size());
+                cv_done.notify_all();
+                return;
+            }
+            for (auto &q : take) q->state = 1;
+            queue.erase(queue.begin(), queue.begin() + (long)take.size());
+            s.reqs = std::move(take);
+            s.batch = std::move(b);
+            s.bytes = bytes;
+            s.busy = true;
+            bytes_in_flight += bytes;
+            peak_bytes = std::max(peak_bytes, bytes_in_flight);
+            batches++;
+            batch_reqs += (int64_t)s.reqs.size();
+            return;
+        }
+    }
+
+    void loop(int dev) {
+        (void)hipSetDevice(dev);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            retire();
+            bool any_busy = false;
+            for (auto &s : slots) {
+                if (!s.busy && !queue.empty()) admit(s);
+                any_busy |= s.busy;
+            }
+            if (stop && !any_busy && queue.empty()) break;
+            if (any_busy) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            }
+        }
+    }
+
+    int shutdown() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!running) return MTE_OK;
+            stop = true;
+        }
+        cv_work.notify_all();
+        worker.join();
+        std::lock_guard<std::mutex> lk(mu);
+        running = false;
+        for (auto &s : slots) {
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            s.stream = nullptr;
+            s.done = nullptr;
+            s.out.reset();
+            s.hout.reset();
+        }
+        series.clear();
+        reqs.clear();
+        queue.clear();
+        return MTE_OK;
+    }
+};
+
+Server &server() {
+    static Server s;
+    return s;
+}
+
+}  // namespace
+
+int serve_shutdown() { return server().shutdown(); }
+
+int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32_t *candidates,
+                          int n_candidates, int max_lag_sources, double alpha, const mte_opts *opts,
+                          mte_result *out);
+
+int series_shape(int32_t sid, int *P, int64_t *T) {
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+    *P = it->second.P;
+    *T = it->second.T;
+    return MTE_OK;
+}
+
+}  // namespace mte
+
+using namespace mte;
+
+extern "C" {
+
+int mte_series_register(const float *data, int P, int64_t T, int32_t *sid_out) {
+    if (!data || !sid_out || P < 1 || T < 2) return fail(MTE_EINVAL, "bad series arguments");
+    int rc = validate_host_finite(data, (int64_t)P * T, "data");
+    if (rc) return rc;
+    if ((rc = ensure_init())) return rc;
+    auto buf = std::make_unique<DevBuf>();
+    if ((rc = buf->ensure(sizeof(float) * (size_t)P * T))) return rc;
+    MTE_HIP(hipMemcpy(buf->p, data, sizeof(float) * (size_t)P * T, hipMemcpyHostToDevice));
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    const int32_t sid = sv.next_sid++;
+    Series &s = sv.series[sid];
+    s.buf = std::move(buf);
+    s.P = P;
+    s.T = T;
+    *sid_out = sid;
+    return MTE_OK;
+}
+
+int mte_series_release(int32_t sid) {
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+    if (it->second.pending > 0) return fail(MTE_EBUSY, "series %d has pending requests", sid);
+    sv.series.erase(it);
+    return MTE_OK;
+}
+
+int mte_submit(const mte_request *req, uint64_t *ticket_out) {
+    if (!req || !ticket_out || !req->nodes || !req->lags) return fail(MTE_EINVAL, "null argument");
+    int rc = validate_dims(req->dx, req->dy, req->dz, req->N, req->k);
+    if (rc) return rc;
+    if (req->S < 0) return fail(MTE_EINVAL, "S must be >= 0");
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(req->sid);
+    if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", req->sid);
+    const Series &se = it->second;
+    const int d = req->dx + req->dy + req->dz;
+    for (int c = 0; c < d; ++c) {
+        if (req->nodes[c] < 0 || req->nodes[c] >= se.P) return fail(MTE_EINVAL, "node out of range");
+        if (req->lags[c] < 0) return fail(MTE_EINVAL, "negative lag");
+        if (req->t0 - req->lags[c] < 0 || req->t0 + req->N - 1 - req->lags[c] >= se.T)
+            return fail(MTE_EINVAL, "window of column %d leaves the series", c);
+    }
+    if ((rc = sv.start_locked())) return rc;
+    auto q = std::make_shared<Req>();
+    q->ticket = sv.next_ticket++;
+    q->r = *req;
+    q->nodes.assign(req->nodes, req->nodes + d);
+    q->lags.assign(req->lags, req->lags + d);
+    q->r.nodes = q->nodes.data();
+    q->r.lags = q->lags.data();
+    q->t_submit = Clock::now();
+    sv.reqs[q->ticket] = q;
+    sv.queue.push_back(q);
+    sv.series[req->sid].pending++;
+    sv.submitted++;
+    *ticket_out = q->ticket;
+    sv.cv_work.notify_one();
+    return MTE_OK;
+}
+
+int mte_wait(uint64_t ticket, double *cmi_out, double *surr_out, double timeout_s) {
+    if (!cmi_out) return fail(MTE_EINVAL, "null output pointer");
+    Server &sv = server();
+    std::unique_lock<std::mutex> lk(sv.mu);
+    auto it = sv.reqs.find(ticket);
+    if (it == sv.reqs.end()) return fail(MTE_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    std::shared_ptr<Req> q = it->second;
+    auto done = [&] { return q->state == 2; };
+    if (timeout_s < 0) sv.cv_done.wait(lk, done);
+    else if (!sv.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+        return fail(MTE_ETIMEOUT, "request %llu still pending", (unsigned long long)ticket);
+    sv.reqs.erase(ticket);
+    if (q->status != MTE_OK) return fail(q->status, "request failed: %s", q->error.c_str());
+    *cmi_out = q->result[0];
+    if (surr_out && q->r.S > 0) std::memcpy(surr_out, q->result.data() + 1, sizeof(double) * q->r.S);
+    return MTE_OK;
+}
+
+int mte_serve_get_stats(mte_serve_stats *out, int reset) {
+    if (!out) return fail(MTE_EINVAL, "null argument");
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    std::memset(out, 0, sizeof *out);
+    out->submitted = sv.submitted;
+    out->completed = sv.completed;
+    out->rejected = sv.rejected;
+    out->batches = sv.batches;
+    out->estimates = sv.estimates;
+    out->mean_batch_requests = sv.batches ? (double)sv.batch_reqs / (double)sv.batches : 0.0;
+    out->peak_bytes_in_use = (int64_t)sv.peak_bytes;
+    out->budget_bytes = (int64_t)ctx().budget;
+    if (!sv.latencies.empty()) {
+        std::vector<double> l = sv.latencies;
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double p) {
+            size_t i = (size_t)std::min<double>((double)l.size() - 1, std::ceil(p * (double)l.size()) - 1);
+            return l[i];
+        };
+        out->p50_latency_s = pct(0.50);
+        out->p99_latency_s = pct(0.99);
+    }
+    if (reset) {
+        sv.submitted = sv.completed = sv.rejected = sv.batches = sv.estimates = sv.batch_reqs = 0;
+        sv.latencies.clear();
+        sv.peak_bytes = sv.bytes_in_flight;
+    }
+    return MTE_OK;
+}
+
+int mte_select_sources_sid(int32_t sid, int target, const int32_t *candidates, int n_candidates,
+                           int max_lag_sources, double alpha, const mte_opts *opts, mte_result *out) {
+    int P = 0;
+    int64_t T = 0;
+    int rc = series_shape(sid, &P, &T);
+    if (rc) return rc;
+    return select_sources_served(sid, P, T, target, candidates, n_candidates, max_lag_sources,
+                                     alpha, opts, out);
+}
+
+}  // extern "C"

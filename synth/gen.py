@@ -169,19 +169,22 @@ def clm_network(p_nodes: int, n_rows: int, seed: int, coupling: float = 0.5,
     x[:MAX_LAG] = h.random((MAX_LAG, p_nodes))
     noise = h.standard_normal((total, p_nodes)) * noise_sd
     f = lambda v: 4.0 * v * (1.0 - v)
-    src = [[(j, lag) for (i2, j, lag, _) in links if i2 == i] for i in range(p_nodes)]
+    # coupling matrices per lag: w[lag-1][i, j] = 1/|parents(i)| (mean over sources)
+    w = np.zeros((MAX_LAG, p_nodes, p_nodes))
+    self_w = np.ones(p_nodes)
+    for (i, j, lag, _) in links:
+        w[lag - 1][i, j] += 1.0 / len(parents[i])
+        self_w[i] = 1.0 - coupling
+    fx = np.zeros((total, p_nodes))
+    fx[:MAX_LAG] = f(x[:MAX_LAG])
     for t in range(MAX_LAG, total):
-        fx = f(x[t - 1])
-        new = np.empty(p_nodes)
-        for i in range(p_nodes):
-            if src[i]:
-                m = np.mean([f(x[t - lag, j]) for (j, lag) in src[i]])
-                new[i] = (1.0 - coupling) * fx[i] + coupling * m
-            else:
-                new[i] = fx[i]
-        v = np.mod(new + noise[t], 1.0)
+        acc = self_w * fx[t - 1]
+        for lag in range(1, MAX_LAG + 1):
+            acc = acc + coupling * (w[lag - 1] @ fx[t - lag])
+        v = np.mod(acc + noise[t], 1.0)
         v[v >= 1.0] = 0.0
         x[t] = v
+        fx[t] = f(v)
     return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32)), links
 
 

@@ -1,0 +1,98 @@
+"""Host-side checks of libmte.so that need no GPU: every symbol declared in
+include/mte.h is exported, the host implementation of the surrogate
+permutation and the significance tests agree with the oracle, and invalid
+arguments are rejected before any device work."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1902_06828_amd as mte
+from oracle import perm, stats
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mte.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "cmi_ksg" in names and "mte_select_sources" in names and "mte_submit" in names
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1902_06828_amd", "libmte.so"))
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(mte._lib.SIGNATURES) | {"mte_last_error"} >= set(names)
+
+
+def test_abi_version():
+    assert mte.lib().mte_abi_version() == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 100, 1000, 4097, 10000])
+def test_host_permutation_matches_oracle(n):
+    for (seed, cand, s) in [(0, 0, 0), (123, 7, 199), (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 31)]:
+        assert np.array_equal(mte.mte_permutation(seed, cand, s, n), perm.permutation(seed, cand, s, n))
+
+
+def test_statistics_match_oracle():
+    g = np.random.default_rng(3)
+    for trial in range(300):
+        n = int(g.integers(1, 7))
+        S = int(g.integers(21, 60))
+        alpha = float(g.choice([0.05, 0.1, 0.2]))
+        real = g.random(n)
+        surr = g.random((n, S))
+        if trial % 3 == 0:              # ties between candidates and surrogates
+            real = np.round(real * 4) / 4
+            surr = np.round(surr * 4) / 4
+        assert mte.mte_max_statistic(real, surr, alpha) == stats.max_statistic(real, surr, alpha)
+        assert mte.mte_min_statistic(real, surr, alpha) == stats.min_statistic(real, surr, alpha)
+        assert mte.mte_omnibus(real[0], surr[0], alpha) == stats.omnibus(real[0], surr[0], alpha)
+
+
+def test_statistics_reject_too_few_surrogates():
+    with pytest.raises(mte.MteError) as e:
+        mte.mte_max_statistic([0.1], np.zeros((1, 20)), 0.05)
+    assert e.value.code == mte._lib.MTE_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(k=0), dict(k=17), dict(n=4, k=4), dict(dx=17), dict(dy=9),
+                                dict(dz=32)])
+def test_estimator_argument_validation(kw):
+    n = kw.get("n", 50)
+    k = kw.get("k", 4)
+    X = np.zeros((kw.get("dx", 1), n), np.float32)
+    Y = np.zeros((kw.get("dy", 1), n), np.float32)
+    Z = np.zeros((kw.get("dz", 1), n), np.float32)
+    with pytest.raises(mte.MteError) as e:
+        mte.cmi_ksg(X, Y, Z, k)
+    assert e.value.code == mte._lib.MTE_EINVAL
+
+
+def test_non_finite_inputs_rejected():
+    X = np.zeros((1, 50), np.float32)
+    X[0, 7] = np.nan
+    with pytest.raises(mte.MteError) as e:
+        mte.cmi_ksg(X, np.zeros((1, 50), np.float32), None, 4)
+    assert e.value.code == mte._lib.MTE_EINVAL and "not finite" in str(e.value)
+
+
+def test_greedy_argument_validation():
+    data = np.zeros((3, 100), np.float32)
+    with pytest.raises(mte.MteError):
+        mte.mte_select_sources(data, 0, [1, 2], alpha=0.05, S=20)     # S*alpha <= 1
+    with pytest.raises(mte.MteError):
+        mte.mte_select_sources(data, 0, [0, 1], alpha=0.1, S=20)      # target among candidates
+    with pytest.raises(mte.MteError):
+        mte.mte_select_sources(data, 0, [5], alpha=0.1, S=20)         # node out of range
+    with pytest.raises(mte.MteError):
+        mte.mte_select_sources(data[:, :8], 0, [1], alpha=0.1, S=20)  # series too short

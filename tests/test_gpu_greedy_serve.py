@@ -1,0 +1,134 @@
+"""The library's greedy selection and request loop against the oracle.
+
+Greedy: the same readings of the paper on both sides (see oracle/greedy.py),
+so the selections, p-values and every reported estimate must agree; the
+library's values within 1e-9 of the oracle's.  Request loop: each request's
+result is bitwise the same alone and in a mix of concurrent requests of uneven
+N and conditioning dimension, and equal to the direct estimator.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1902_06828_amd as mte
+import synth
+from oracle import cksg, greedy, ksg, perm
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def est(x, y, z, k):
+    return cksg.cmi_ksg(x, y, z, k)
+
+
+def compare_results(lib_res, ora):
+    def same(a, b):
+        assert [(n, l) for (n, l, _, _) in a] == [(n, l) for (n, l, _, _) in b]
+        for (_, _, c1, p1), (_, _, c2, p2) in zip(a, b):
+            assert abs(c1 - c2) <= 1e-9 and p1 == p2
+    same(lib_res["target_past"], ora["target_past"])
+    same(lib_res["sources_before_omnibus"], ora["sources_before_omnibus"])
+    same(lib_res["sources"], ora["sources"])
+    assert abs(lib_res["omnibus_te"] - ora["omnibus_te"]) <= 1e-9
+    assert lib_res["omnibus_p"] == ora["omnibus_p"]
+    assert lib_res["significant"] == ora["significant"]
+    assert lib_res["n_estimates"] == ora["n_estimates"]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_greedy_matches_oracle(seed):
+    series, links = synth.var_network(5, 400, seed=seed)
+    target = min(i for (i, _, _, _) in links)
+    cands = [j for j in range(5) if j != target]
+    kw = dict(max_lag_sources=3, alpha=0.1, k=4, max_lag_target=3, seed=seed)
+    say("greedy", seed, "target", target)
+    lib_res = mte.mte_select_sources(series, target, cands, S=20, **kw)
+    ora = greedy.select_sources(series, target, cands, max_lag_sources=3, max_lag_target=3,
+                                alpha=0.1, k=4, n_surr=20, seed=seed, estimator=est)
+    compare_results(lib_res, ora)
+    say("served greedy", seed)
+    sid = mte.mte_series_register(series)
+    served = mte.mte_select_sources_sid(sid, target, cands, S=20, **kw)
+    mte.mte_series_release(sid)
+    compare_results(served, ora)
+
+
+def test_greedy_recovers_var_parents():
+    # 10-node VAR, N = 3000: the selected sources are true parents
+    series, links = synth.var_network(10, 3000, seed=3)
+    target = min(i for (i, _, _, _) in links)
+    parents = {(j, l) for (i, j, l, _) in links if i == target}
+    cands = [j for j in range(10) if j != target]
+    say("recovery", target, parents)
+    res = mte.mte_select_sources(series, target, cands, max_lag_sources=5, alpha=0.05, S=100, seed=3)
+    got = {(n, l) for (n, l, _, _) in res["sources"]}
+    assert res["significant"]
+    assert len(got & parents) >= 1 and len(got - parents) <= 1
+
+
+def _requests(P, T, count, seed):
+    g = np.random.default_rng(seed)
+    reqs = []
+    for r in range(count):
+        n = int(g.choice([400, 1000, 2500]))
+        dz = int(g.integers(0, 7))
+        S = int(g.choice([0, 5, 20]))
+        d = 2 + dz
+        nodes = g.integers(0, P, size=d).astype(np.int32)
+        lags = np.concatenate([[int(g.integers(1, 6))], [0], g.integers(1, 6, size=dz)]).astype(np.int32)
+        t0 = 5 + int(g.integers(0, T - n - 5))
+        reqs.append(dict(nodes=nodes, lags=lags, dx=1, dy=1, dz=dz, t0=t0, n=n, k=4, S=S,
+                         seed=int(seed), cand=r))
+    return reqs
+
+
+def test_request_loop_alone_vs_mix():
+    P, T = 20, 3005
+    series, _ = synth.clm_network(P, T - 5, seed=4)
+    sid = mte.mte_series_register(series)
+    reqs = _requests(P, T, 40, 8)
+    say("mix of", len(reqs))
+    tickets = [mte.mte_submit(sid, **q) for q in reqs]
+    mix = [mte.mte_wait(t, q["S"]) for t, q in zip(tickets, reqs)]
+    st = mte.mte_serve_get_stats(reset=True)
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    say("alone")
+    for q, (v, s) in zip(reqs, mix):
+        t = mte.mte_submit(sid, **q)
+        v1, s1 = mte.mte_wait(t, q["S"])
+        assert v1 == v and np.array_equal(s1, s)
+    # and the same as the direct estimator on the same windows
+    for q, (v, s) in list(zip(reqs, mix))[:6]:
+        cols = [series[nd, q["t0"] - lg: q["t0"] - lg + q["n"]] for nd, lg in zip(q["nodes"], q["lags"])]
+        X = np.ascontiguousarray(np.array(cols[:1], np.float32))
+        Y = np.ascontiguousarray(np.array(cols[1:2], np.float32))
+        Z = np.ascontiguousarray(np.array(cols[2:], np.float32)) if q["dz"] else None
+        cmi = mte.cmi_ksg_diag(X, Y, Z, 4, q["S"], q["seed"], q["cand"])[0]
+        assert cmi[0] == v and np.array_equal(cmi[1:], s)
+        if q["n"] <= 1000:
+            assert abs(v - cksg.cmi_ksg(X, Y, Z, 4)) <= 1e-9
+    mte.mte_series_release(sid)
+
+
+def test_admission_rejects_oversized_request():
+    series = np.random.default_rng(1).standard_normal((3, 5000)).astype(np.float32)
+    sid = mte.mte_series_register(series)
+    mte.mte_init(0, 1 << 20)                  # 1 MiB budget
+    try:
+        t = mte.mte_submit(sid, [0, 1, 2], [1, 0, 1], 1, 1, 1, 5, 4900, k=4, S=200)
+        with pytest.raises(mte.MteError) as e:
+            mte.mte_wait(t, 200)
+        assert e.value.code == mte._lib.MTE_ENOMEM
+        t = mte.mte_submit(sid, [0, 1], [1, 0], 1, 1, 0, 5, 300, k=4, S=0)
+        v, _ = mte.mte_wait(t, 0)
+        assert np.isfinite(v)
+    finally:
+        mte.mte_init(0, 64 << 30)
+    mte.mte_series_release(sid)

@@ -1,0 +1,220 @@
+"""Parity of the HIP estimator with the oracle.
+
+Radii and the three neighbour counts must match the oracle bit for bit
+(they are exact: one float32 subtraction per coordinate, exact |.| and max,
+strict integer counts); the CMI must match within 1e-9 absolute (both sides
+sum float64 digamma terms, in different but fixed orders).  Every surrogate is
+checked against the oracle run on X permuted with the oracle's own
+implementation of the permutation.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1902_06828_amd as mte
+import synth
+from oracle import cksg, ksg, perm
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_estimates(X, Y, Z, k, S, seed, cand, queries=None):
+    """[(cmi or None, eps, nxz, nyz, nz)] for the estimate and its S surrogates."""
+    n = X.shape[1]
+    out = []
+    for e in range(S + 1):
+        Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(seed, cand, e - 1, n))
+        eps, a, b, c, v = cksg.eps_and_counts(Xe, Y, Z, k, queries=queries)
+        out.append((v, eps, a, b, c))
+    return out
+
+
+def check_against_oracle(X, Y, Z, k, S=0, seed=11, cand=3):
+    cmi, eps, cx, cy, cz = mte.cmi_ksg_diag(X, Y, Z, k, S, seed, cand)
+    ref = oracle_estimates(X, Y, Z, k, S, seed, cand)
+    for e, (v, re, ra, rb, rc) in enumerate(ref):
+        assert np.array_equal(eps[e].view(np.uint32), re.view(np.uint32)), f"eps differ, estimate {e}"
+        assert np.array_equal(cx[e], ra), f"n_xz differ, estimate {e}"
+        assert np.array_equal(cy[e], rb), f"n_yz differ, estimate {e}"
+        assert np.array_equal(cz[e], rc), f"n_z differ, estimate {e}"
+        assert abs(cmi[e] - v) <= TOL, (e, cmi[e], v)
+    return cmi, eps, cx, cy, cz
+
+
+def test_hand_counted_case():
+    g = json.load(open(os.path.join(GOLD, "hand_counted_k2_n6.json")))
+    f = lambda a: np.array([a], np.float32)
+    say("hand-counted case")
+    cmi, eps, cx, cy, cz = mte.cmi_ksg_diag(f(g["X"]), f(g["Y"]), f(g["Z"]), g["k"])
+    assert eps[0].tolist() == g["eps"]
+    assert cx[0].tolist() == g["n_xz"] and cy[0].tolist() == g["n_yz"] and cz[0].tolist() == g["n_z"]
+    assert abs(cmi[0] + 1 / 120) < 1e-14
+    assert abs(mte.cmi_ksg(f(g["X"]), f(g["Y"]), f(g["Z"]), g["k"]) + 1 / 120) < 1e-14
+
+
+CASES = [
+    # (n, (dx, dy, dz), k, kind, S)
+    (2, (1, 1, 0), 1, "normal", 0),
+    (5, (1, 1, 0), 4, "normal", 2),
+    (17, (1, 1, 1), 4, "grid", 3),
+    (64, (1, 1, 5), 4, "normal", 2),
+    (65, (2, 1, 3), 3, "dup", 2),
+    (300, (1, 1, 5), 4, "normal", 3),
+    (777, (1, 2, 4), 7, "grid", 2),
+    (1500, (3, 1, 9), 8, "wide", 1),
+    (2000, (1, 1, 15), 16, "normal", 1),
+    (513, (16, 8, 31), 5, "tiny", 1),
+    (256, (1, 1, 0), 4, "tiny", 2),
+    (129, (4, 1, 2), 1, "dup", 4),
+]
+
+
+@pytest.mark.parametrize("n,dims,k,kind,S", CASES)
+def test_random_parity(n, dims, k, kind, S):
+    say("case", n, dims, k, kind, S)
+    X, Y, Z = synth.random_points(n, dims, seed=n * 7 + k, kind=kind)
+    check_against_oracle(X, Y, Z, k, S)
+
+
+def test_c1_gaussian_parity():
+    X, Y, Z, true = synth.c1_gaussian(1000, 1)
+    say("C1 gaussian")
+    cmi, *_ = check_against_oracle(X, Y, Z, 4, 0)
+    assert abs(cmi[0] - true) < 0.1
+
+
+def test_all_duplicates_give_zero_radius():
+    n = 50
+    X = np.zeros((1, n), np.float32)
+    say("all duplicates")
+    cmi, eps, cx, cy, cz = check_against_oracle(X, X.copy(), X.copy(), 4, 1)
+    assert np.all(eps == 0) and np.all(cx == 0)
+
+
+def test_overflowing_differences():
+    g = np.random.default_rng(5)
+    n = 200
+    vals = np.array([-3e38, 3e38, 0.0, 1.0, -2.5e38], np.float32)
+    X, Y, Z = (vals[g.integers(0, 5, size=(d, n))] for d in (1, 1, 2))
+    say("overflow to inf")
+    check_against_oracle(np.ascontiguousarray(X), np.ascontiguousarray(Y), np.ascontiguousarray(Z), 4, 2)
+
+
+def test_splits_do_not_change_results(monkeypatch):
+    X, Y, Z = synth.random_points(3000, (1, 1, 5), seed=9)
+    res = []
+    for split in ("0", "1", "4"):
+        monkeypatch.setenv("MTE_FORCE_SPLIT", split)
+        say("split multiplier", split)
+        res.append(mte.cmi_ksg_diag(X, Y, Z, 4, 3, 5, 1))
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
+
+
+def test_every_tile_configuration(monkeypatch):
+    X, Y, Z = synth.random_points(700, (1, 1, 4), seed=21)
+    ref = mte.cmi_ksg_diag(X, Y, Z, 4, 9, 2, 0)
+    tested = 0
+    for idx, cfg in enumerate(mte.mte_tile_configs()):
+        kmax, g, qp, dzm, dym, dxm = cfg
+        if kmax != 4:
+            continue
+        for split in ("0", "2"):
+            monkeypatch.setenv("MTE_FORCE_VARIANT", str(idx))
+            monkeypatch.setenv("MTE_FORCE_SPLIT", split)
+            say("variant", idx, cfg, "split", split)
+            got = mte.cmi_ksg_diag(X, Y, Z, 4, 9, 2, 0)
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (idx, cfg, split)
+            tested += 1
+    assert tested >= 8
+    # the radius list capacities 8 and 16 against the oracle
+    for k in (6, 12):
+        for idx, cfg in enumerate(mte.mte_tile_configs()):
+            if cfg[0] == (8 if k <= 8 else 16) and cfg[5] == 1 and cfg[3] >= 4:
+                monkeypatch.setenv("MTE_FORCE_VARIANT", str(idx))
+                monkeypatch.setenv("MTE_FORCE_SPLIT", "0")
+                say("k", k, "variant", idx, cfg)
+                check_against_oracle(X, Y, Z, k, 2)
+
+
+def test_batched_equals_plain():
+    X, Y, Z = synth.random_points(1200, (1, 1, 3), seed=33)
+    S, seed = 6, 99
+    say("batched vs plain")
+    v, surr = mte.cmi_ksg_surrogates(X, Y, Z, 4, S, seed)
+    assert v == mte.cmi_ksg(X, Y, Z, 4)
+    for s in range(S):
+        Xs = ksg.permute_rows(X, perm.permutation(seed, 0, s, X.shape[1]))
+        assert surr[s] == mte.cmi_ksg(Xs, Y, Z, 4)
+
+
+def test_device_api_and_graph_replay():
+    torch = pytest.importorskip("torch")
+    X, Y, Z = synth.random_points(2500, (1, 1, 5), seed=44)
+    S, seed, cand = 20, 7, 5
+    ref = mte.cmi_ksg_diag(X, Y, Z, 4, S, seed, cand)[0]
+    dev = torch.device("cuda:0")
+    dX, dY, dZ = (torch.from_numpy(a).to(dev) for a in (X, Y, Z))
+    out = torch.zeros(S + 1, dtype=torch.float64, device=dev)
+    for rep in range(4):
+        say("device call", rep)
+        out.zero_()
+        mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, S, seed, cand, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+    one = torch.zeros(1, dtype=torch.float64, device=dev)
+    mte.cmi_ksg_dev(dX, dY, dZ, 4, one)
+    torch.cuda.synchronize()
+    assert one.item() == ref[0]
+    # a strided view: rows 100..2099 of columns with leading dimension 2500
+    sub = torch.zeros(S + 1, dtype=torch.float64, device=dev)
+    mte.cmi_ksg_surrogates_dev(dX[:, 100:], dY[:, 100:], dZ[:, 100:], 4, S, seed, cand, sub, n=2000)
+    torch.cuda.synchronize()
+    ref2 = mte.cmi_ksg_diag(np.ascontiguousarray(X[:, 100:2100]), np.ascontiguousarray(Y[:, 100:2100]),
+                            np.ascontiguousarray(Z[:, 100:2100]), 4, S, seed, cand)[0]
+    assert np.array_equal(sub.cpu().numpy(), ref2)
+
+
+def test_full_size_c2_sampled():
+    # one TE estimate and 200 surrogates at N = 10000 (10-node VAR), as timed
+    # by the benchmark; rows sampled from every 25th estimate are checked
+    # against the oracle one query at a time, estimate 0 and surrogate 0 in full
+    X, Y, Z, meta = synth.c2_te_inputs(10000, seed=2)
+    S, seed, k = 200, 2, 4
+    say("C2 full size")
+    cmi, eps, cx, cy, cz = mte.cmi_ksg_diag(X, Y, Z, k, S, seed, 0)
+    n = X.shape[1]
+    rows = np.random.default_rng(0).choice(n, size=24, replace=False)
+    rows = np.concatenate([rows, [0, 1, n - 1, n - 64, 63, 64]])
+    for e in range(0, S + 1, 25):
+        Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(seed, 0, e - 1, n))
+        re, ra, rb, rc, _ = cksg.eps_and_counts(Xe, Y, Z, k, queries=rows)
+        assert np.array_equal(eps[e, rows], re) and np.array_equal(cx[e, rows], ra)
+        assert np.array_equal(cy[e, rows], rb) and np.array_equal(cz[e, rows], rc)
+    for e in (0, 1):
+        Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(seed, 0, e - 1, n))
+        assert abs(cmi[e] - cksg.cmi_ksg(Xe, Y, Z, k)) <= TOL
+    # properties at any size
+    assert np.all((cx >= 0) & (cx <= cz) & (cy <= cz) & (cz <= n - 1))
+    assert cmi[0] > np.max(cmi[1:])          # a true coupling beats every surrogate
+    # the device form used by the benchmark gives the same bits
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cuda:0")
+    out = torch.zeros(S + 1, dtype=torch.float64, device=dev)
+    mte.cmi_ksg_surrogates_dev(*(torch.from_numpy(a).to(dev) for a in (X, Y, Z)), k, S, seed, 0, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), cmi)
