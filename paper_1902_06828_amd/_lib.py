@@ -102,6 +102,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_1902_06828_amd.build.build() first")
+        # One HIP runtime per process: load PyTorch's first, so that
+        # libmte's libamdhip64.so.7 dependency binds to the copy PyTorch
+        # already mapped (it owns the device buffers and streams we receive).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         L.mte_last_error.restype = ctypes.c_char_p
         L.mte_last_error.argtypes = []
@@ -209,10 +216,14 @@ def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, s
         chk(Z, "Z")
     if out.dtype != torch.float64 or not out.is_cuda or out.numel() < S + 1:
         raise TypeError("out must be a float64 CUDA tensor with S+1 entries")
-    ld = X.stride(0)
-    if Y.stride(0) != ld or (Z is not None and Z.stride(0) != ld):
-        raise ValueError("X, Y and Z must share the leading dimension")
     rows = X.shape[1] if n is None else n
+    # the column stride of a one-column tensor is never used
+    multi = [t.stride(0) for t in (X, Y, Z) if t is not None and t.shape[0] > 1]
+    ld = multi[0] if multi else max(t.shape[1] for t in (X, Y, Z) if t is not None)
+    if any(s != ld for s in multi):
+        raise ValueError("X, Y and Z must share the leading dimension")
+    if any(t is not None and t.shape[1] < rows for t in (X, Y, Z)) or rows > ld:
+        raise ValueError("fewer columns than rows requested")
     _check(lib().cmi_ksg_surrogates_dev(
         ctypes.c_void_p(X.data_ptr()), X.shape[0], ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
         None if Z is None else ctypes.c_void_p(Z.data_ptr()), 0 if Z is None else Z.shape[0],

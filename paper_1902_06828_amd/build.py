@@ -26,6 +26,7 @@ SOURCES = ["kernels_k4.hip", "kernels_k8.hip", "kernels_k16.hip", "kernels.hip",
            "api.cpp", "greedy.cpp", "serve.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+CLANGXX = "/opt/rocm/llvm/bin/clang++" if os.path.exists("/opt/rocm/llvm/bin/clang++") else "g++"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-I", INCLUDE, "-I", CSRC]
 # Device code: gfx950 only; denormals kept (distances are exact binary32
@@ -48,12 +49,28 @@ def _compile(src: str) -> str:
     return obj
 
 
+def hip_runtime() -> str:
+    """The HIP runtime library to link: the copy bundled with PyTorch when it
+    is installed (PyTorch owns the device buffers and streams handed to the
+    library, and one process must use a single HIP runtime), else ROCm's."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec and spec.origin:
+        cand = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+        if os.path.exists(cand):
+            return cand
+    return "/opt/rocm/lib/libamdhip64.so"
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    rt = hip_runtime()
+    # plain link (no hipcc driver), so the only HIP runtime dependency is `rt`
+    cmd = [CLANGXX, "-shared", "-fPIC", "-o", tmp] + objs + [
+        rt, "-Wl,-rpath," + os.path.dirname(rt), "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -150,7 +150,9 @@ struct DevEntry {
 };
 
 static std::mutex g_dev_mu;
-static std::list<DevEntry> g_dev_cache;   // most recent first
+// most recent first; never destroyed, so no HIP call runs during static
+// destruction at exit (mte_shutdown clears it)
+static std::list<DevEntry> &g_dev_cache = *new std::list<DevEntry>;
 static constexpr size_t kDevCacheMax = 512;
 
 static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz,

@@ -480,10 +480,11 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     if ((rc = tables_.ensure(tbl_bytes))) return rc;
     // pinned staging, reused by this thread (the copy below completes before
     // prepare returns)
-    static thread_local HostBuf staging;
-    if ((rc = staging.ensure(tbl_bytes))) return rc;
+    // (never freed, so no HIP call runs in thread-exit destructors)
+    static thread_local HostBuf *staging = new HostBuf;
+    if ((rc = staging->ensure(tbl_bytes))) return rc;
     uint8_t *tb = tables_.as<uint8_t>();
-    uint8_t *hs = static_cast<uint8_t *>(staging.p);
+    uint8_t *hs = static_cast<uint8_t *>(staging->p);
     EstKey *keys_dev = reinterpret_cast<EstKey *>(tb + tbl_jobs);
     EstKey *keys_host = reinterpret_cast<EstKey *>(hs + tbl_jobs);
     int64_t kpos = 0;

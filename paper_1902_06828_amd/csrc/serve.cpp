@@ -269,9 +269,11 @@ public:
     }
 };
 
+// Never destroyed: the worker thread may still exist at process exit, and a
+// joinable std::thread must not be destroyed (mte_shutdown joins it).
 Server &server() {
-    static Server s;
-    return s;
+    static Server *s = new Server;
+    return *s;
 }
 
 }  // namespace

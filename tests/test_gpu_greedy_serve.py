@@ -94,6 +94,7 @@ def test_request_loop_alone_vs_mix():
     series, _ = synth.clm_network(P, T - 5, seed=4)
     sid = mte.mte_series_register(series)
     reqs = _requests(P, T, 40, 8)
+    mte.mte_serve_get_stats(reset=True)
     say("mix of", len(reqs))
     tickets = [mte.mte_submit(sid, **q) for q in reqs]
     mix = [mte.mte_wait(t, q["S"]) for t, q in zip(tickets, reqs)]
