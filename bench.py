@@ -29,8 +29,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KSG CMI evals/s at N=10k (batched/served vs plain); p50/p99 req latency"
 N_ROWS, S, K_NN, SEED = 10000, 200, 4, 2
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz non-packed FP32/INT32 VALU issue
-PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X FP32 vector peak 157.3 TFLOP/s counts an FMA as 2: 256 CUs x 128
+# lanes per clock x 2.4 GHz = 78.6 T operations/s for the non-FMA operations
+# (subtract, max, min, med3, compare, integer add) this kernel issues.
+PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -38,7 +40,7 @@ def log(*a):
 
 
 def algorithmic_ops(n, dx, dy, dz, n_est):
-    """Method operations of one batched test (Roofline): per
+    """Method operations of one batched test: per
     ordered pair (i != j), the Y,Z max-norm once per test for each pass
     (2*(dy+dz)-1 ops each: subtract, |.|-max), and per estimate 2*dx+1 ops in
     the k-NN pass (X subtract/max, compare with the current k-th) and 2*dx+6 in
@@ -132,10 +134,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one elementwise copy of 1 GiB (256Mi float32 read + written) before the "
+                         "timed region, as the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the KSG path on a single MI355X "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the KSG path runs on a single MI355X and no multi-GPU "
+              "form is implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -157,6 +162,14 @@ def main():
         stream.synchronize()
         v = host.numpy()
         return mte.mte_omnibus(float(v[0]), v[1:], 0.05)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log("calibration copy: 1073741824 bytes read, 1073741824 bytes written (torch.neg)")
+        del src, dst
 
     log("batched: warm-up (includes the tile autotuner)")
     for _ in range(args.warmup):
