@@ -7,6 +7,7 @@ namespace mte {
 
 const dev::VariantEntry *variants_k16(int *n) {
     static const dev::VariantEntry v[] = {
+    MTE_VARIANT_ENTRY(16, 8, 1, 8, 1, 1)
     MTE_VARIANT_ENTRY(16, 8, 2, 8, 1, 1)
     MTE_VARIANT_ENTRY(16, 4, 2, 8, 1, 1)
     MTE_VARIANT_ENTRY(16, 4, 2, 16, 1, 1)

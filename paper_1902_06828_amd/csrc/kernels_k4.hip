@@ -7,7 +7,10 @@ namespace mte {
 
 const dev::VariantEntry *variants_k4(int *n) {
     static const dev::VariantEntry v[] = {
+    MTE_VARIANT_ENTRY(4, 16, 1, 8, 1, 1)
+    MTE_VARIANT_ENTRY(4, 8, 1, 8, 1, 1)
     MTE_VARIANT_ENTRY(4, 8, 2, 8, 1, 1)
+    MTE_VARIANT_ENTRY(4, 16, 1, 16, 1, 1)
     MTE_VARIANT_ENTRY(4, 4, 2, 8, 1, 1)
     MTE_VARIANT_ENTRY(4, 4, 2, 16, 1, 1)
     MTE_VARIANT_ENTRY(4, 4, 2, 32, 1, 1)

@@ -45,6 +45,16 @@ __device__ __forceinline__ float fmin_(float a, float b) { return __builtin_fmin
 __device__ __forceinline__ float absdiff(float a, float b) { return __builtin_fabsf(a - b); }
 __device__ __forceinline__ float inf_f() { return __builtin_inff(); }
 
+// c += (a < b): the compare writes VCC and the carry-in add consumes it right
+// away.  Written as one ALU-only asm pair because the compiler otherwise
+// hoists all compares of a step and spills their 64-bit masks.
+__device__ __forceinline__ void count_lt(int &c, float a, float b) {
+    asm("v_cmp_lt_f32_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, 0, %0, vcc"
+        : "+v"(c)
+        : "v"(a), "v"(b)
+        : "vcc");
+}
+
 // Insert d into the ascending list t[0..K-1], dropping the largest entry.
 template <int K>
 __device__ __forceinline__ void topk_insert(float (&t)[K], float d) {
@@ -88,7 +98,7 @@ struct Smem {
     float ry[DYM][Tile<KMAX, G, QP, DZM, DYM, DXM>::RT];
     float rx[G][DXM][Tile<KMAX, G, QP, DZM, DYM, DXM>::RT];
     const float *col[kMaxCols];
-    double red[512];
+    double red[G * 64];                    // chunk sums staged by the final reduction
     int item;
     int flag;
 };
@@ -328,9 +338,9 @@ struct Worker {
                         const float e = eps[gg][q];
 #pragma unroll
                         for (int r = 0; r < kSteps; ++r) {
-                            cxz[gg][q] += dxz[q][r] < e ? 1 : 0;
-                            cyz[gg][q] += ayz[q][r] < e ? 1 : 0;
-                            if (HASZ) cz[gg][q] += az[q][r] < e ? 1 : 0;
+                            count_lt(cxz[gg][q], dxz[q][r], e);
+                            count_lt(cyz[gg][q], ayz[q][r], e);
+                            if (HASZ) count_lt(cz[gg][q], az[q][r], e);
                         }
                     }
                 });
