@@ -40,7 +40,7 @@ def log(*a):
 
 
 def algorithmic_ops(n, dx, dy, dz, n_est):
-    """Method operations of one batched test: per
+    """Method operations of one all-pairs test: per
     ordered pair (i != j), the Y,Z max-norm once per test for each pass
     (2*(dy+dz)-1 ops each: subtract, |.|-max), and per estimate 2*dx+1 ops in
     the k-NN pass (X subtract/max, compare with the current k-th) and 2*dx+6 in
@@ -49,6 +49,21 @@ def algorithmic_ops(n, dx, dy, dz, n_est):
     shared = 2 * (2 * (dy + dz) - 1)
     per_est = (2 * dx + 1) + (2 * dx + 6)
     return pairs * (shared + n_est * per_est)
+
+
+def build_ops(n, dy, dz):
+    """Neighbour-list build, per (Y,Z) sample: the Y,Z and Z max-norms of every
+    ordered pair once (2*(dy+dz)-1 ops: subtract, |.|-max)."""
+    return n * (n - 1) * (2 * (dy + dz) - 1)
+
+
+def scan_ops(dx, entries):
+    """Neighbour-list scan, from the list entries read: a k-NN entry costs
+    2*dx+1 ops (X subtract/|.|-max, max with d_yz, compare with the k-th), an
+    n_yz entry 2 (compare, add), a Z-list entry 2*dx+5 (X subtract/|.|-max, max
+    with d_z, two compares, two adds)."""
+    knn, yz, zl = entries
+    return knn * (2 * dx + 1) + yz * 2 + zl * (2 * dx + 5)
 
 
 def cpu_baseline(X, Y, Z, budget_s=15.0):
@@ -174,23 +189,48 @@ def main():
     log("batched: warm-up (includes the tile autotuner)")
     for _ in range(args.warmup):
         step()
+    stages = list(mte._lib.STAGES)
     mte.mte_kernel_timing(True)
-    mte.mte_kernel_timing_read(reset=True)
+    for st in stages:
+        mte.mte_kernel_timing_stage(st, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         p, sig = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, kernel_ms = mte.mte_kernel_timing_read(reset=True)
+    stage_ms = {}
+    for st in stages:
+        launches, ms = mte.mte_kernel_timing_stage(st, reset=True)
+        if launches:
+            stage_ms[st] = {"launches_per_step": launches / args.steps, "ms_per_step": ms / args.steps,
+                            "ms_per_launch": ms / launches}
     mte.mte_kernel_timing(False)
     dt = t1 - t0
     value = E * args.steps / dt
-    k_avg_ms = kernel_ms / max(1, launches)
-    ops = algorithmic_ops(N_ROWS, 1, 1, 5, E)
-    achieved = ops / (k_avg_ms * 1e-3) / 1e12
-    log(f"batched: {value:.1f} evals/s, {dt / args.steps * 1e3:.2f} ms/step, main kernel {k_avg_ms:.3f} ms, "
-        f"{achieved:.2f} TOP/s ({achieved / PEAK_TOPS:.1%} of {PEAK_TOPS:.1f}); TE p={p:.3f}")
+    # the list path's entry counts for this input (one checked call, same data)
+    mte.mte_list_stats(reset=True)
+    mte.cmi_ksg_surrogates(X, Y, Z, K_NN, S, SEED)
+    pairs, undecided, entries = mte.mte_list_stats(reset=True, entries=True)
+    dominant = max(stage_ms, key=lambda k: stage_ms[k]["ms_per_launch"] * stage_ms[k]["launches_per_step"])
+    if dominant == "all_pairs":
+        ops = algorithmic_ops(N_ROWS, 1, 1, 5, E)
+    elif dominant == "build":
+        ops = build_ops(N_ROWS, 1, 5)
+    elif dominant == "scan":
+        ops = scan_ops(1, entries)
+    else:
+        ops = None
+    k_avg_ms = stage_ms[dominant]["ms_per_launch"]
+    achieved = ops / (k_avg_ms * 1e-3) / 1e12 if ops else None
+    equiv = algorithmic_ops(N_ROWS, 1, 1, 5, E) / (dt / args.steps) / 1e12
+    log(f"batched: {value:.1f} evals/s, {dt / args.steps * 1e3:.3f} ms/step; stages (ms/step): " +
+        ", ".join(f"{k} {v['ms_per_step']:.3f}" for k, v in stage_ms.items()))
+    log(f"list path: {pairs} pairs, {undecided} redone over all rows, entries read {entries}")
+    if achieved:
+        log(f"dominant kernel: {dominant} {k_avg_ms:.3f} ms, {achieved:.2f} TOP/s "
+            f"({achieved / PEAK_TOPS:.1%} of {PEAK_TOPS:.1f}); all-pairs-equivalent rate {equiv:.1f} TOP/s; "
+            f"TE p={p:.3f}")
 
     # graph replay of the same step (timing off)
     torch.cuda.synchronize()
@@ -260,8 +300,11 @@ def main():
             "N": N_ROWS, "dims": [1, 1, 5], "k": K_NN, "estimates_per_step": E,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_TOPS, "traffic": None,
-                     "kernel_ms": k_avg_ms, "ops_per_launch": ops},
+                     "frac": achieved / PEAK_TOPS if achieved else None, "traffic": None,
+                     "kernel": dominant, "kernel_ms": k_avg_ms, "ops_per_launch": ops},
+        "stages_ms_per_step": {k: v["ms_per_step"] for k, v in stage_ms.items()},
+        "list_path": {"pairs": pairs, "redone_over_all_rows": undecided, "entries_read": entries},
+        "all_pairs_equivalent_tops": equiv,
         "cpu_baseline": cpu,
         "graph_replay_evals_per_s": graph_value,
         "plain": plain,

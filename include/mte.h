@@ -253,12 +253,40 @@ int mte_serve_get_stats(mte_serve_stats *out, int reset);
 int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
 
 /* --------------------------------------------------------------------------
- * Timing of the dominant kernel: when enabled, HIP events are recorded on the
- * launch stream around every launch of the main KSG kernel and the elapsed
- * times are accumulated (read after the stream has finished).
+ * Kernel timing: when enabled, launches are made directly (no graph replay)
+ * and HIP events are recorded on the launch stream around every kernel
+ * launch of the stages below; the elapsed times are accumulated per stage
+ * (reading waits for the recorded events).  mte_kernel_timing_read reads
+ * stage MTE_STAGE_ALL_PAIRS.  reset = 1 clears the stage after reading.
+ *   MTE_STAGE_ALL_PAIRS  all-pairs KSG kernel (jobs without Z columns, or
+ *                        with too few estimates per (Y,Z) sample)
+ *   MTE_STAGE_BUILD      neighbour-list build, once per (Y,Z) sample
+ *   MTE_STAGE_SCAN       per (row, estimate) k-NN radius and counts over the lists
+ *   MTE_STAGE_FALLBACK   all-rows redo of the pairs the lists cannot decide
+ *   MTE_STAGE_REDUCE     fixed-order digamma sums of the list path
+ *   MTE_STAGE_PERMUTE    surrogate permutation of the X columns (both paths)
  * ------------------------------------------------------------------------ */
+enum {
+    MTE_STAGE_ALL_PAIRS = 0,
+    MTE_STAGE_BUILD = 1,
+    MTE_STAGE_SCAN = 2,
+    MTE_STAGE_FALLBACK = 3,
+    MTE_STAGE_REDUCE = 4,
+    MTE_STAGE_PERMUTE = 5
+};
 int mte_kernel_timing(int enable);
 int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int reset);
+int mte_kernel_timing_stage(int stage, int64_t *launches_out, double *total_ms_out, int reset);
+
+/* --------------------------------------------------------------------------
+ * Neighbour-list path statistics over the launches whose completion the
+ * library has checked (the host-pointer calls, the greedy driver and the
+ * request loop): (row, estimate) pairs computed on the list path, how many of
+ * them the lists could not decide and were redone over all rows, and (if
+ * entries_out is not NULL) entries_out[0..2] = list entries read by the
+ * k-NN scan, the n_yz scan and the Z-list scan.  reset = 1 clears them.
+ * ------------------------------------------------------------------------ */
+int mte_list_stats(int64_t *pairs_out, int64_t *undecided_out, int64_t *entries_out, int reset);
 
 #ifdef __cplusplus
 }

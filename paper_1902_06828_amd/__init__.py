@@ -19,6 +19,8 @@ from ._lib import (  # noqa: F401
     mte_init,
     mte_kernel_timing,
     mte_kernel_timing_read,
+    mte_kernel_timing_stage,
+    mte_list_stats,
     mte_max_statistic,
     mte_min_statistic,
     mte_omnibus,

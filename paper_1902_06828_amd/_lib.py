@@ -91,6 +91,8 @@ SIGNATURES = {
     "mte_tile_configs": [_P, _I, _P],
     "mte_kernel_timing": [_I],
     "mte_kernel_timing_read": [_P, _P, _I],
+    "mte_kernel_timing_stage": [_I, _P, _P, _I],
+    "mte_list_stats": [_P, _P, _P, _I],
 }
 
 _lib = None
@@ -367,7 +369,29 @@ def mte_kernel_timing(enable: bool) -> None:
 
 
 def mte_kernel_timing_read(reset: bool = False):
-    """Returns (launches, total milliseconds) of the main KSG kernel."""
+    """Returns (launches, total milliseconds) of the all-pairs KSG kernel."""
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _check(lib().mte_kernel_timing_read(ctypes.byref(n), ctypes.byref(ms), int(reset)))
     return n.value, ms.value
+
+
+STAGES = {"all_pairs": 0, "build": 1, "scan": 2, "fallback": 3, "reduce": 4, "permute": 5}
+
+
+def mte_kernel_timing_stage(stage, reset: bool = False):
+    """Returns (launches, total milliseconds) of one timed stage (name or number)."""
+    st = STAGES[stage] if isinstance(stage, str) else int(stage)
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().mte_kernel_timing_stage(st, ctypes.byref(n), ctypes.byref(ms), int(reset)))
+    return n.value, ms.value
+
+
+def mte_list_stats(reset: bool = False, entries: bool = False):
+    """Returns (pairs on the list path, pairs redone over all rows), plus the
+    list entries read by the three scans when `entries` is set."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    ent = np.zeros(3, np.int64)
+    _check(lib().mte_list_stats(ctypes.byref(a), ctypes.byref(b), _ptr(ent), int(reset)))
+    if entries:
+        return a.value, b.value, [int(v) for v in ent]
+    return a.value, b.value

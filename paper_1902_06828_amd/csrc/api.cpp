@@ -280,30 +280,53 @@ int mte_kernel_timing(int enable) {
     return MTE_OK;
 }
 
-int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int reset) {
+int mte_kernel_timing_stage(int stage, int64_t *launches_out, double *total_ms_out, int reset) {
+    if (stage < 0 || stage >= kStages) return fail(MTE_EINVAL, "stage %d out of range", stage);
     Ctx &c = ctx();
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<Ctx::Pending> ev;
     {
         std::lock_guard<std::mutex> lk(c.mu);
         ev.swap(c.pending_events);
     }
-    double add = 0.0;
+    double add[kStages] = {};
+    int64_t cnt[kStages] = {};
     for (auto &pe : ev) {
-        MTE_HIP(hipEventSynchronize(pe.second));
+        MTE_HIP(hipEventSynchronize(pe.b));
         float ms = 0.f;
-        MTE_HIP(hipEventElapsedTime(&ms, pe.first, pe.second));
-        add += ms;
-        (void)hipEventDestroy(pe.first);
-        (void)hipEventDestroy(pe.second);
+        MTE_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
+        add[pe.stage] += ms;
+        cnt[pe.stage] += 1;
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
     }
     std::lock_guard<std::mutex> lk(c.mu);
-    c.timed_ms += add;
-    c.timed_launches += (int64_t)ev.size();
-    if (launches_out) *launches_out = c.timed_launches;
-    if (total_ms_out) *total_ms_out = c.timed_ms;
+    for (int t = 0; t < kStages; ++t) {
+        c.timed_ms[t] += add[t];
+        c.timed_launches[t] += cnt[t];
+    }
+    if (launches_out) *launches_out = c.timed_launches[stage];
+    if (total_ms_out) *total_ms_out = c.timed_ms[stage];
     if (reset) {
-        c.timed_ms = 0.0;
-        c.timed_launches = 0;
+        c.timed_ms[stage] = 0.0;
+        c.timed_launches[stage] = 0;
+    }
+    return MTE_OK;
+}
+
+int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int reset) {
+    return mte_kernel_timing_stage(kStageAllPairs, launches_out, total_ms_out, reset);
+}
+
+int mte_list_stats(int64_t *pairs_out, int64_t *undecided_out, int64_t *entries_out, int reset) {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (pairs_out) *pairs_out = c.list_pairs;
+    if (undecided_out) *undecided_out = c.list_undecided;
+    if (entries_out)
+        for (int t = 0; t < 3; ++t) entries_out[t] = c.list_seen[t];
+    if (reset) {
+        c.list_pairs = c.list_undecided = 0;
+        for (int t = 0; t < 3; ++t) c.list_seen[t] = 0;
     }
     return MTE_OK;
 }

@@ -57,6 +57,56 @@ struct Job {
     double *out;                  // [n_est] results
     float *diag_eps;              // optional [n_est][n]
     int32_t *diag_cnt;            // optional [n_est][3][n] (n_xz, n_yz, n_z)
+    // neighbour-list path only (see ListSet): list set index, and the
+    // permuted X columns transposed so that the estimates of one row are
+    // adjacent: xt[c][i][e] = X_c[pi_e(i)] ([dx][n][n_est]).  eps and cnt
+    // hold the per-row radii and counts ([n_est][n], [n_est][3][n]).
+    int set;
+    float *xt;
+};
+
+// Neighbour lists of one (Y, Z) sample, shared by every job of a launch whose
+// Y and Z columns are the same.  For row i, list 1 holds the other rows j with
+// the (Y,Z) max-norm distance d_yz(i,j) in the smallest key buckets that fit
+// m1 entries, list 2 the same for the Z distance d_z(i,j) and m2.  A key is
+// the top 12 bits of the distance's float encoding (exponent and 3 mantissa
+// bits), so a list is ordered by bucket, not fully sorted.  bound[i][w] is a
+// lower bound of every unlisted distance (+inf when nothing is left out), so
+// a radius r <= bound[i][w] is decided by the list alone.
+struct LEnt {
+    float d;                      // distance
+    int32_t j;                    // row
+};
+
+struct ListSet {
+    const float *cols[kMaxDy + kMaxDz];   // Y columns, then Z columns
+    int n, dy, dz;
+    int m1, m2;                   // entries reserved per row
+    LEnt *l1;                     // [n][m1]  (Y,Z) list
+    LEnt *l2;                     // [n][m2]  Z list
+    int32_t *len;                 // [n][2]
+    float *bound;                 // [n][2]
+};
+
+constexpr int kListStatWord = 16;
+constexpr int kKeyShift = 19;                 // 4096 key buckets
+constexpr int kKeyBins = 1 << (32 - kKeyShift - 1);
+
+// One launch of the list path over `n_jobs` jobs (all with dz > 0).
+struct ListLaunch {
+    const Job *jobs;              // device
+    const ListSet *sets;          // device
+    const int64_t *lane_off;      // [n_jobs+1] prefix sums of n * n_est
+    const int64_t *row_off;       // [n_sets+1] prefix sums of the sets' n
+    const int64_t *est_off;       // [n_jobs+1] prefix sums of n_est
+    int n_jobs, n_sets;
+    int64_t lanes, rows, ests;
+    uint64_t *failq;              // [lanes] (job << 40 | i * n_est + e) of undecided pairs
+    uint32_t *counters;           // [0] undecided pairs; from word kListStatWord three
+                                  // uint64 totals of list entries read (k-NN scan,
+                                  // n_yz scan, Z-list scan); 64 words, zeroed per launch
+    int kmax, dxm;                // compile-time classes of the scan kernel
+    int fb_grid;                  // blocks of the fallback kernel
 };
 
 // Counter words of one job (all zero before a launch):
@@ -95,6 +145,11 @@ int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_rows, const in
 int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_off_dev,
                 const int64_t *b_off_dev, const LaunchInfo &li, uint32_t *work,
                 const double *harm, void *stream);
+
+int launch_list_build(const ListLaunch &L, void *stream);
+int launch_list_scan(const ListLaunch &L, void *stream);
+int launch_list_fallback(const ListLaunch &L, void *stream);
+int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream);
 
 // Host reference of the surrogate permutation (same definition as the device).
 uint64_t mix64(uint64_t z);

@@ -32,7 +32,8 @@ __device__ __forceinline__ int n_rounds_dev(int64_t n) {
 }
 
 // ------------------------------------------------------------------ permute
-// xp[e][c][i] = X_c[pi_e(i)] for every job, estimate and row.  One block per
+// xp[e][c][i] = X_c[pi_e(i)] (or, for the list path, xt[c][i][e]) for every
+// job, estimate and row.  One block per
 // (job, estimate, 1024-row chunk); the block derives the round keys in LDS.
 __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
                                                      const int64_t *__restrict__ blk_off) {
@@ -77,8 +78,13 @@ __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jo
                 if (dmix64((uint64_t)hi ^ s_rk[r]) >> 63) x = xp;
             }
         }
-        for (int c = 0; c < J.dx; ++c)
-            J.xp[((int64_t)e * J.dx + c) * J.n + i] = J.cols[c][x];
+        if (J.xt) {
+            for (int c = 0; c < J.dx; ++c)
+                J.xt[((int64_t)c * J.n + i) * J.n_est + e] = J.cols[c][x];
+        } else {
+            for (int c = 0; c < J.dx; ++c)
+                J.xp[((int64_t)e * J.dx + c) * J.n + i] = J.cols[c][x];
+        }
     }
 }
 

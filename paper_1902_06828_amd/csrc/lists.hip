@@ -1,0 +1,602 @@
+// Neighbour-list path of the KSG estimator (gfx950).
+//
+// Every estimate of a job shares the rows of Y and Z; only X is permuted.  A
+// row's k-th neighbour distance eps and its three strict counts below eps
+// only involve rows that are close to it in the (Y,Z) subspace (for the k-NN
+// radius and n_yz) or in the Z subspace (n_z and n_xz, since both need
+// d_z < eps).  So, once per (Y,Z) sample:
+//
+//   build    for each row i, the other rows bucketed by d_yz(i,j) and by
+//            d_z(i,j) (12-bit keys of the float encoding), keeping the
+//            smallest buckets that fit the list capacity, in bucket order,
+//            with a lower bound of every distance left out;
+//
+// and then, for every (row, estimate) pair, one lane:
+//
+//   scan     k-NN over list 1 in bucket order, max(d_x, d_yz) with the
+//            estimate's permuted X; it stops at the first bucket whose floor
+//            reaches the current k-th distance (nothing later can enter).  The
+//            radius is exact when it stopped that way or when the k-th
+//            distance is at most the list's bound.  n_yz counts list 1 below
+//            eps; n_z and n_xz scan list 2 until its bucket floor reaches eps,
+//            exact when it stopped that way or eps <= the bound of list 2;
+//   fallback the pairs the lists cannot decide (rare) are queued and redone
+//            by one wave each over all rows;
+//   reduce   the digamma sum per estimate in the same fixed order as the
+//            all-pairs kernel (64-row butterfly, then chunks in index order),
+//            so both paths return the same bits.
+//
+// The results are the definitions' exact values: every distance is the same
+// fl32 subtraction, |.| and max as in the all-pairs kernel, and the lists only
+// skip rows whose distances provably cannot change the outcome.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "engine.h"
+#include "ksg_device.h"
+
+namespace mte {
+
+namespace {
+
+using dev::absdiff;
+using dev::find_job;
+using dev::fmax_;
+using dev::inf_f;
+using dev::topk_insert;
+using dev::Unroll;
+
+constexpr uint32_t kKeyMask = kKeyBins - 1;
+constexpr uint32_t kFloorMask = ~((1u << kKeyShift) - 1u);
+
+// Work-item and work-group indices straight from the hardware registers (the
+// group index is a scalar value, so it stays wave-uniform).
+__device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int64_t bid_x() { return (int64_t)__builtin_amdgcn_workgroup_id_x(); }
+
+__device__ __forceinline__ uint32_t key_of(float d) {
+    return (__float_as_uint(d) >> kKeyShift) & kKeyMask;
+}
+
+// Smallest value of d's bucket (d >= 0).
+__device__ __forceinline__ float bucket_floor(float d) {
+    return __uint_as_float(__float_as_uint(d) & kFloorMask);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = __builtin_fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Inclusive scan over the 256 threads of a block; returns the block total.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint32_t *wtot) {
+    const int lane = tid_x() & 63, wave = tid_x() >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) wtot[wave] = v;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        before += w < wave ? wtot[w] : 0u;
+        total += wtot[w];
+    }
+    incl = before + v;
+    __syncthreads();
+    return total;
+}
+
+// ------------------------------------------------------------------ build
+// One block per (list set, row).  Pass 1 histograms the keys of d_yz and d_z
+// over the other rows; the largest key prefix of each histogram that fits the
+// capacity is kept and the histogram becomes the bucket write cursors; pass 2
+// recomputes the same distances and writes the kept rows bucket by bucket.
+struct BuildSmem {
+    uint32_t h[2][kKeyBins];
+    float q[kMaxDy + kMaxDz];
+    uint32_t wtot[kWaves];
+    uint32_t red[2][kWaves];
+    int set;
+};
+
+// Calls f(j, d_z, d_yz) for every row j != i, kRowBatch rows per thread at a
+// time so that the loads of a column for all of them are in flight together.
+constexpr int kRowBatch = 8;
+
+template <class F>
+__device__ __forceinline__ void for_each_row(const ListSet &S, const float *q, int i, int tid, F &&f) {
+    const int n = S.n;
+    for (int j0 = tid; j0 < n; j0 += kBlock * kRowBatch) {
+        float a[kRowBatch], b[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) a[u] = 0.f;
+        for (int c = 0; c < S.dz; ++c) {
+            const float *col = S.cols[S.dy + c];
+            const float qc = q[S.dy + c];
+            float v[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int j = j0 + u * kBlock;
+                v[u] = j < n ? col[j] : qc;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) a[u] = fmax_(a[u], absdiff(qc, v[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) b[u] = a[u];
+        for (int c = 0; c < S.dy; ++c) {
+            const float *col = S.cols[c];
+            const float qc = q[c];
+            float v[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int j = j0 + u * kBlock;
+                v[u] = j < n ? col[j] : qc;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) b[u] = fmax_(b[u], absdiff(qc, v[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+            const int j = j0 + u * kBlock;
+            if (j < n && j != i) f(j, a[u], b[u]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__restrict__ sets, int n_sets,
+                                                           const int64_t *__restrict__ row_off) {
+    __shared__ BuildSmem sm;
+    const int tid = tid_x();
+    const int64_t b = bid_x();
+    if (tid == 0) sm.set = find_job(row_off, n_sets, b);
+    for (int x = tid; x < 2 * kKeyBins; x += kBlock) (&sm.h[0][0])[x] = 0u;
+    __syncthreads();
+    const ListSet &S = sets[sm.set];
+    const int i = (int)(b - row_off[sm.set]);
+    const int n = S.n;
+    if (tid < S.dy + S.dz) sm.q[tid] = S.cols[tid][i];
+    __syncthreads();
+
+    for_each_row(S, sm.q, i, tid, [&](int, float a, float c) {
+        atomicAdd(&sm.h[0][key_of(c)], 1u);
+        atomicAdd(&sm.h[1][key_of(a)], 1u);
+    });
+    __syncthreads();
+
+    // per list: keep the largest bucket prefix with at most m entries
+    constexpr int kPer = kKeyBins / kBlock;
+    uint32_t kept_bins[2], kept_rows[2];
+    for (int w = 0; w < 2; ++w) {
+        const uint32_t cap = (uint32_t)(w == 0 ? S.m1 : S.m2);
+        uint32_t local = 0;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) local += sm.h[w][tid * kPer + x];
+        uint32_t incl;
+        block_scan(local, incl, sm.wtot);
+        uint32_t run = incl - local, nb = 0, nr = 0;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) {
+            const uint32_t cnt = sm.h[w][tid * kPer + x];
+            sm.h[w][tid * kPer + x] = run;          // exclusive start = write cursor
+            run += cnt;
+            if (run <= cap) { ++nb; nr += cnt; }
+        }
+        nb = (uint32_t)wave_sum((int)nb);
+        nr = (uint32_t)wave_sum((int)nr);
+        if ((tid & 63) == 0) { sm.red[0][tid >> 6] = nb; sm.red[1][tid >> 6] = nr; }
+        __syncthreads();
+        kept_bins[w] = kept_rows[w] = 0;
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) { kept_bins[w] += sm.red[0][v]; kept_rows[w] += sm.red[1][v]; }
+        __syncthreads();
+    }
+    // bucket keys below kept_bins[w] are listed (the prefix is contiguous
+    // because the cumulative counts grow with the key)
+    LEnt *l1 = S.l1 + (int64_t)i * S.m1;
+    LEnt *l2 = S.l2 + (int64_t)i * S.m2;
+    for_each_row(S, sm.q, i, tid, [&](int j, float a, float c) {
+        const uint32_t k1 = key_of(c), k2 = key_of(a);
+        if (k1 < kept_bins[0]) {
+            const uint32_t pos = atomicAdd(&sm.h[0][k1], 1u);
+            if (pos < (uint32_t)S.m1) l1[pos] = LEnt{c, j};
+        }
+        if (k2 < kept_bins[1]) {
+            const uint32_t pos = atomicAdd(&sm.h[1][k2], 1u);
+            if (pos < (uint32_t)S.m2) l2[pos] = LEnt{a, j};
+        }
+    });
+    if (tid < 2) {
+        const uint32_t total = (uint32_t)(n - 1);
+        const float bound = kept_rows[tid] == total
+                                ? inf_f()
+                                : __uint_as_float(kept_bins[tid] << kKeyShift);
+        S.len[2 * (int64_t)i + tid] = (int32_t)kept_rows[tid];
+        S.bound[2 * (int64_t)i + tid] = bound;
+    }
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int kU = 8;   // list entries per step; the next step's are loaded ahead
+
+template <int KMAX, int DXM>
+struct Lane {
+    const Job &J;
+    const float *xt;
+    int64_t cs;     // xt column stride n * n_est
+    int E, e, i;
+    float xq[DXM];
+
+    __device__ Lane(const Job &j, int i_, int e_) : J(j), i(i_), e(e_) {
+        xt = J.xt;
+        E = J.n_est;
+        cs = (int64_t)J.n * E;
+        Unroll<0, DXM>::upto(J.dx, [&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            xq[c] = xt[c * cs + (int64_t)i * E + e];
+        });
+    }
+
+    // max-norm over the X columns between this lane's row and the rows of a
+    // step (under the estimate's permutation); all loads issued before use
+    __device__ __forceinline__ void xdist(const LEnt (&en)[kU], float (&d)[kU]) const {
+        float v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = xt[(int64_t)en[u].j * E + e];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) d[u] = absdiff(xq[0], v[u]);
+        Unroll<1, DXM>::upto(J.dx, [&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v[u] = xt[c * cs + (int64_t)en[u].j * E + e];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) d[u] = fmax_(d[u], absdiff(xq[c], v[u]));
+        });
+    }
+};
+
+// entries [m, m+kU) of a list of length len; past the end: (+inf, self)
+__device__ __forceinline__ void load_step(const LEnt *l, int m, int len, int self, LEnt (&en)[kU]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) en[u] = m + u < len ? l[m + u] : LEnt{inf_f(), self};
+}
+
+// distance of the last listed entry of a step (entries are in bucket order)
+__device__ __forceinline__ float last_d(const LEnt (&en)[kU], int m, int len) {
+    float last = 0.f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (m + u < len) last = en[u].d;
+    return last;
+}
+
+template <int KMAX, int DXM>
+__global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
+    const int64_t g = bid_x() * kBlock + tid_x();
+    if (g >= L.lanes) return;
+    const int jb = find_job(L.lane_off, L.n_jobs, g);
+    const Job &J = L.jobs[jb];
+    const int64_t r = g - L.lane_off[jb];
+    const int i = (int)(r / J.n_est);
+    const int e = (int)(r - (int64_t)i * J.n_est);
+    const ListSet &S = L.sets[J.set];
+    const int n = J.n;
+    Lane<KMAX, DXM> ln(J, i, e);
+
+    // k-NN radius over list 1
+    float top[KMAX];
+    const int pad_front = KMAX - J.k;
+#pragma unroll
+    for (int m = 0; m < KMAX; ++m) top[m] = m < pad_front ? -inf_f() : inf_f();
+    const LEnt *l1 = S.l1 + (int64_t)i * S.m1;
+    const int len1 = S.len[2 * (int64_t)i];
+    bool done = false;
+    int seen1 = 0, seen_yz = 0, seen2 = 0;     // list entries read (statistics)
+    {
+        LEnt cur[kU];
+        load_step(l1, 0, len1, i, cur);
+        for (int m = 0; m < len1; m += kU) {
+            seen1 = min(m + kU, len1);
+            LEnt nxt[kU];
+            load_step(l1, m + kU, len1, i, nxt);
+            float dx[kU];
+            ln.xdist(cur, dx);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) topk_insert<KMAX>(top, fmax_(dx[u], cur[u].d));
+            if (bucket_floor(last_d(cur, m, len1)) >= top[KMAX - 1]) { done = true; break; }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+        }
+    }
+    const float eps = top[KMAX - 1];
+    bool decided = done || eps <= S.bound[2 * (int64_t)i];
+
+    int cxz = 0, cyz = 0, cz = 0;
+    if (decided) {
+        // n_yz: list 1 below eps (every row with d_yz < eps is listed)
+        for (int m = 0; m < len1; m += 2 * kU) {
+            seen_yz = min(m + 2 * kU, len1);
+            float d[2 * kU];
+#pragma unroll
+            for (int u = 0; u < 2 * kU; ++u) d[u] = m + u < len1 ? l1[m + u].d : inf_f();
+            float last = 0.f;
+#pragma unroll
+            for (int u = 0; u < 2 * kU; ++u) {
+                cyz += d[u] < eps;
+                if (m + u < len1) last = d[u];
+            }
+            if (bucket_floor(last) >= eps) break;
+        }
+        // n_z and n_xz: list 2 below eps
+        const LEnt *l2 = S.l2 + (int64_t)i * S.m2;
+        const int len2 = S.len[2 * (int64_t)i + 1];
+        bool stop = false;
+        LEnt cur[kU];
+        load_step(l2, 0, len2, i, cur);
+        for (int m = 0; m < len2; m += kU) {
+            seen2 = min(m + kU, len2);
+            LEnt nxt[kU];
+            load_step(l2, m + kU, len2, i, nxt);
+            float dx[kU];
+            ln.xdist(cur, dx);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                cz += cur[u].d < eps;
+                cxz += fmax_(dx[u], cur[u].d) < eps;
+            }
+            if (bucket_floor(last_d(cur, m, len2)) >= eps) { stop = true; break; }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+        }
+        decided = stop || eps <= S.bound[2 * (int64_t)i + 1];
+    }
+    if (!decided) {
+        const uint32_t pos = atomicAdd(&L.counters[0], 1u);
+        L.failq[pos] = ((uint64_t)jb << 40) | (uint64_t)r;
+    } else {
+        J.eps[(int64_t)e * n + i] = eps;
+        J.cnt[((int64_t)e * 3 + 0) * n + i] = cxz;
+        J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
+        J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
+    }
+    unsigned long long *st = reinterpret_cast<unsigned long long *>(L.counters + kListStatWord);
+    atomicAdd(&st[0], (unsigned long long)seen1);
+    atomicAdd(&st[1], (unsigned long long)seen_yz);
+    atomicAdd(&st[2], (unsigned long long)seen2);
+}
+
+// ------------------------------------------------------------------ fallback
+// One block per undecided (row, estimate): every other row, as in the
+// definition.  Each thread keeps the KMAX smallest distances of its rows; k
+// pops of the wave-wide minimum give each wave's k smallest, and the k-th
+// smallest of the four waves' lists is the radius.
+constexpr int kFbBatch = 4;
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch L) {
+    __shared__ float wtop[kWaves][KMAX];
+    __shared__ int wcnt[kWaves][3];
+    __shared__ float s_eps;
+    const int tid = tid_x();
+    const int lane = tid & 63;
+    // The item count, the wave index and the block index are scalar values,
+    // so the item loop and everything derived from an item are uniform and
+    // all lanes stay together through the cross-lane steps below.
+    const uint32_t total = __builtin_amdgcn_readfirstlane(__atomic_load_n(&L.counters[0], __ATOMIC_RELAXED));
+    const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+    for (uint32_t it = (uint32_t)bid_x(); it < total; it += (uint32_t)L.fb_grid) {
+        const uint64_t item = L.failq[it];
+        const int jb = (int)(item >> 40);
+        const int64_t r = (int64_t)(item & ((1ull << 40) - 1));
+        const Job &J = L.jobs[jb];
+        const int E = J.n_est, n = J.n, dx = J.dx, dy = J.dy, dz = J.dz;
+        const int i = (int)(r / E), e = (int)(r - (int64_t)i * E);
+        const int64_t cs = (int64_t)n * E;
+        const float *const *yc = J.cols + dx;
+        const float *const *zc = J.cols + dx + dy;
+        // distances of kFbBatch rows j0, j0 + kBlock, ... (row i and rows past
+        // the end get +inf in every subspace)
+        auto dists = [&](int j0, float (&ax)[kFbBatch], float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
+            int jj[kFbBatch];
+#pragma unroll
+            for (int u = 0; u < kFbBatch; ++u) {
+                const int j = j0 + u * kBlock;
+                jj[u] = j < n ? j : i;
+                ax[u] = ay[u] = az[u] = 0.f;
+            }
+            for (int c = 0; c < dx; ++c) {
+                const float q = J.xt[c * cs + (int64_t)i * E + e];
+                float v[kFbBatch];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) v[u] = J.xt[c * cs + (int64_t)jj[u] * E + e];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) ax[u] = fmax_(ax[u], absdiff(q, v[u]));
+            }
+            for (int c = 0; c < dy; ++c) {
+                const float q = yc[c][i];
+                float v[kFbBatch];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) v[u] = yc[c][jj[u]];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) ay[u] = fmax_(ay[u], absdiff(q, v[u]));
+            }
+            for (int c = 0; c < dz; ++c) {
+                const float q = zc[c][i];
+                float v[kFbBatch];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) v[u] = zc[c][jj[u]];
+#pragma unroll
+                for (int u = 0; u < kFbBatch; ++u) az[u] = fmax_(az[u], absdiff(q, v[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kFbBatch; ++u)
+                if (jj[u] == i) ax[u] = ay[u] = az[u] = inf_f();
+        };
+        float top[KMAX];
+#pragma unroll
+        for (int m = 0; m < KMAX; ++m) top[m] = inf_f();
+        for (int j0 = tid; j0 < n; j0 += kBlock * kFbBatch) {
+            float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
+            dists(j0, ax, ay, az);
+#pragma unroll
+            for (int u = 0; u < kFbBatch; ++u) topk_insert<KMAX>(top, fmax_(fmax_(ax[u], ay[u]), az[u]));
+        }
+        for (int t = 0; t < J.k; ++t) {
+            const float mn = wave_min(top[0]);
+            const uint64_t bal = __ballot(top[0] == mn);
+            const int first = __builtin_ctzll(bal);
+            if (lane == first) {
+#pragma unroll
+                for (int m = 0; m < KMAX - 1; ++m) top[m] = top[m + 1];
+                top[KMAX - 1] = inf_f();
+            }
+            if (lane == 0) wtop[wave][t] = mn;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int pos[kWaves] = {0, 0, 0, 0};
+            float kth = inf_f();
+            for (int t = 0; t < J.k; ++t) {
+                int best = 0;
+                float bv = inf_f();
+                for (int w = 0; w < kWaves; ++w)
+                    if (pos[w] < J.k && wtop[w][pos[w]] < bv) { bv = wtop[w][pos[w]]; best = w; }
+                ++pos[best];
+                kth = bv;
+            }
+            s_eps = kth;
+        }
+        __syncthreads();
+        const float eps = s_eps;
+        int cxz = 0, cyz = 0, cz = 0;
+        for (int j0 = tid; j0 < n; j0 += kBlock * kFbBatch) {
+            float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
+            dists(j0, ax, ay, az);
+#pragma unroll
+            for (int u = 0; u < kFbBatch; ++u) {
+                cxz += fmax_(ax[u], az[u]) < eps;
+                cyz += fmax_(ay[u], az[u]) < eps;
+                cz += az[u] < eps;
+            }
+        }
+        cxz = wave_sum(cxz);
+        cyz = wave_sum(cyz);
+        cz = wave_sum(cz);
+        if (lane == 0) { wcnt[wave][0] = cxz; wcnt[wave][1] = cyz; wcnt[wave][2] = cz; }
+        __syncthreads();
+        if (tid == 0) {
+            int c3[3] = {0, 0, 0};
+            for (int w = 0; w < kWaves; ++w)
+                for (int t = 0; t < 3; ++t) c3[t] += wcnt[w][t];
+            J.eps[(int64_t)e * n + i] = eps;
+            for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ reduce
+// One block per (job, estimate): (H[n_xz] + H[n_yz]) - H[n_z] per row, 64-row
+// butterfly sums (the four waves take 16 chunks each per round), then the
+// chunk sums added in index order: the all-pairs kernel's order.
+constexpr int kRedChunks = 16;
+
+__global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L, const double *__restrict__ harm) {
+    __shared__ double part[kWaves * kRedChunks];
+    __shared__ double s_acc;
+    const int64_t g = bid_x();
+    const int jb = find_job(L.est_off, L.n_jobs, g);
+    const Job &J = L.jobs[jb];
+    const int e = (int)(g - L.est_off[jb]);
+    const int n = J.n, tid = tid_x(), lane = tid & 63;
+    const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+    const int32_t *cx = J.cnt + ((int64_t)e * 3 + 0) * n;
+    const int32_t *cy = J.cnt + ((int64_t)e * 3 + 1) * n;
+    const int32_t *cz = J.cnt + ((int64_t)e * 3 + 2) * n;
+    const int nch = (n + kChunk - 1) / kChunk;
+    constexpr int kRound = kWaves * kRedChunks;
+    if (tid == 0) s_acc = 0.0;
+    for (int c0 = 0; c0 < nch; c0 += kRound) {
+        double v[kRedChunks];
+#pragma unroll
+        for (int u = 0; u < kRedChunks; ++u) {
+            const int i = (c0 + wave * kRedChunks + u) * kChunk + lane;
+            v[u] = i < n ? (harm[cx[i]] + harm[cy[i]]) - harm[cz[i]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRedChunks; ++u)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v[u] = v[u] + __shfl_xor(v[u], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int u = 0; u < kRedChunks; ++u) part[wave * kRedChunks + u] = v[u];
+        __syncthreads();
+        if (tid == 0) {
+            double acc = s_acc;
+            const int m = min(kRound, nch - c0);
+            for (int c = 0; c < m; ++c) acc += part[c];
+            s_acc = acc;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) J.out[e] = harm[J.k - 1] - s_acc / (double)n;
+}
+
+template <int KMAX, int DXM>
+void *scan_fn() {
+    return reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM>);
+}
+
+}  // namespace
+
+int launch_list_build(const ListLaunch &L, void *stream) {
+    if (L.rows <= 0) return 0;
+    hipLaunchKernelGGL(list_build_kernel, dim3((unsigned)L.rows), dim3(kBlock), 0, (hipStream_t)stream, L.sets,
+                       L.n_sets, L.row_off);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_scan(const ListLaunch &L, void *stream) {
+    if (L.lanes <= 0) return 0;
+    const int64_t blocks = (L.lanes + kBlock - 1) / kBlock;
+    void *fn = nullptr;
+    const bool wide = L.dxm > 1;
+    if (L.kmax == 4) fn = wide ? scan_fn<4, kMaxDx>() : scan_fn<4, 1>();
+    else if (L.kmax == 8) fn = wide ? scan_fn<8, kMaxDx>() : scan_fn<8, 1>();
+    else if (L.kmax == 16) fn = wide ? scan_fn<16, kMaxDx>() : scan_fn<16, 1>();
+    else return -1;
+    ListLaunch arg = L;
+    void *args[] = {(void *)&arg};
+    return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kBlock), args, 0, (hipStream_t)stream) == hipSuccess
+               ? 0
+               : -1;
+}
+
+int launch_list_fallback(const ListLaunch &L, void *stream) {
+    if (L.lanes <= 0) return 0;
+    const dim3 grid((unsigned)L.fb_grid), block(kBlock);
+    if (L.kmax == 4) hipLaunchKernelGGL(list_fallback_kernel<4>, grid, block, 0, (hipStream_t)stream, L);
+    else if (L.kmax == 8) hipLaunchKernelGGL(list_fallback_kernel<8>, grid, block, 0, (hipStream_t)stream, L);
+    else if (L.kmax == 16) hipLaunchKernelGGL(list_fallback_kernel<16>, grid, block, 0, (hipStream_t)stream, L);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream) {
+    if (L.ests <= 0) return 0;
+    hipLaunchKernelGGL(list_reduce_kernel, dim3((unsigned)L.ests), dim3(kBlock), 0, (hipStream_t)stream, L, harm);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mte

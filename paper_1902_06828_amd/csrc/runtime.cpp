@@ -188,8 +188,8 @@ int shutdown_all() {
     if (!c.inited) return MTE_OK;
     MTE_HIP(hipDeviceSynchronize());
     for (auto &pe : c.pending_events) {
-        (void)hipEventDestroy(pe.first);
-        (void)hipEventDestroy(pe.second);
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
     }
     c.pending_events.clear();
     if (c.harm) (void)hipFree(c.harm);
@@ -224,10 +224,55 @@ int validate_host_finite(const float *p, int64_t count, const char *name) {
     return MTE_OK;
 }
 
-void record_timing_pair(hipEvent_t a, hipEvent_t b) {
+void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b) {
     Ctx &c = ctx();
     std::lock_guard<std::mutex> lk(c.mu);
-    c.pending_events.emplace_back(a, b);
+    c.pending_events.push_back(Ctx::Pending{stage, a, b});
+}
+
+// ---------------------------------------------------------------- paths
+static int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, int *n_sets) {
+    const char *fm = std::getenv("MTE_FORCE_MODE");
+    const int force = fm && std::strcmp(fm, "brute") == 0 ? 0 : (fm && std::strcmp(fm, "list") == 0 ? 1 : -1);
+    set_of->assign(specs.size(), -1);
+    // group by (n, dy, dz, Y and Z column pointers)
+    std::map<std::vector<uintptr_t>, int> groups;
+    std::vector<int64_t> group_est;
+    std::vector<int> gid(specs.size(), -1);
+    for (size_t j = 0; j < specs.size(); ++j) {
+        const JobSpec &sp = specs[j];
+        if (sp.dz <= 0 || force == 0) continue;
+        std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz};
+        for (int c = 0; c < sp.dy + sp.dz; ++c) key.push_back((uintptr_t)sp.cols[sp.dx + c]);
+        auto it = groups.emplace(key, (int)group_est.size()).first;
+        if (it->second == (int)group_est.size()) group_est.push_back(0);
+        gid[j] = it->second;
+        group_est[it->second] += sp.n_est();
+    }
+    // keep the groups that take the list path and renumber them densely
+    std::vector<int> dense(group_est.size(), -1);
+    int ns = 0;
+    for (size_t g = 0; g < group_est.size(); ++g)
+        if (force == 1 || group_est[g] >= kListMinEstimates) dense[g] = ns++;
+    for (size_t j = 0; j < specs.size(); ++j)
+        if (gid[j] >= 0) (*set_of)[j] = dense[gid[j]];
+    *n_sets = ns;
+    return MTE_OK;
+}
+
+static std::vector<JobSpec> pair_specs(const std::vector<JobSpec> &specs) {
+    std::vector<int> set_of;
+    int ns = 0;
+    assign_paths(specs, &set_of, &ns);
+    std::vector<JobSpec> out;
+    for (size_t j = 0; j < specs.size(); ++j)
+        if (set_of[j] < 0) out.push_back(specs[j]);
+    return out;
 }
 
 // ---------------------------------------------------------------- tiles
@@ -294,13 +339,14 @@ static int g_pref_for(const std::vector<JobSpec> &specs) {
     return avg >= 16 ? 8 : (avg >= 4 ? 4 : 1);
 }
 
-static int env_int(const char *name, int dflt) {
-    const char *v = std::getenv(name);
-    return v && *v ? std::atoi(v) : dflt;
-}
-
-int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, bool tune, TileChoice *out) {
+int choose_tiles(const std::vector<JobSpec> &all_specs, hipStream_t s, bool tune, TileChoice *out) {
     Ctx &c = ctx();
+    // only the jobs of the all-pairs kernel have a tile choice
+    const std::vector<JobSpec> specs = pair_specs(all_specs);
+    if (specs.empty()) {
+        *out = TileChoice{-1, 1};
+        return MTE_OK;
+    }
     // test hooks: MTE_FORCE_VARIANT (tile configuration index, used when it
     // fits) and MTE_FORCE_SPLIT (0 = one reference split, m = m times the
     // heuristic split count)
@@ -374,28 +420,220 @@ Batch::~Batch() {
     if (graph_) (void)hipGraphDestroy(graph_);
 }
 
-size_t Batch::device_bytes() const { return tables_.bytes + scratch_.bytes + sync_.bytes; }
+size_t Batch::device_bytes() const {
+    return tables_.bytes + scratch_.bytes + sync_.bytes + ltables_.bytes + lscratch_.bytes + lcounters_.bytes;
+}
+
+static int check_spec(const JobSpec &sp) {
+    if (sp.n_est() < 1) return fail(MTE_EINVAL, "job without estimates");
+    if (sp.n < sp.k + 1) return fail(MTE_EINVAL, "N < k+1");
+    if (sp.k < 1 || sp.k > kMaxK || sp.dx < 1 || sp.dx > kMaxDx || sp.dy < 1 || sp.dy > kMaxDy || sp.dz < 0 ||
+        sp.dz > kMaxDz)
+        return fail(MTE_EINVAL, "job dimensions out of range");
+    for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc)
+        if (!sp.cols[cc]) return fail(MTE_EINVAL, "null column pointer");
+    if (!sp.out) return fail(MTE_EINVAL, "null output pointer");
+    return MTE_OK;
+}
 
 int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
-    Ctx &c = ctx();
     if (specs.empty()) return fail(MTE_EINVAL, "empty batch");
+    int rc;
+    int64_t nmax = 0;
+    for (const auto &sp : specs) {
+        if ((rc = check_spec(sp))) return rc;
+        nmax = std::max<int64_t>(nmax, sp.n);
+    }
+    if ((rc = ensure_harm(nmax))) return rc;
+    std::vector<int> set_of;
+    int n_sets = 0;
+    assign_paths(specs, &set_of, &n_sets);
+    std::vector<JobSpec> pairs, lists;
+    std::vector<int> lset;
+    for (size_t j = 0; j < specs.size(); ++j) {
+        if (set_of[j] < 0) {
+            pairs.push_back(specs[j]);
+        } else {
+            lists.push_back(specs[j]);
+            lset.push_back(set_of[j]);
+        }
+    }
+    n_est_total_ = 0;
+    for (const auto &sp : specs) n_est_total_ += sp.n_est();
+    n_jobs_ = 0;
+    variant_ = -1;
+    if (!pairs.empty() && (rc = prepare_pairs(pairs, tc, s))) return rc;
+    n_ljobs_ = 0;
+    if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, s))) return rc;
+    return MTE_OK;
+}
+
+// List capacities per row: MTE_LIST_CAP="m1,m2" overrides the defaults.
+static void list_caps(int *m1, int *m2) {
+    *m1 = 1024;
+    *m2 = 2048;
+    const char *v = std::getenv("MTE_LIST_CAP");
+    if (v && *v) {
+        int a = 0, b = 0;
+        if (std::sscanf(v, "%d,%d", &a, &b) == 2 && a >= 1 && b >= 1) {
+            *m1 = a;
+            *m2 = b;
+        }
+    }
+}
+
+int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
+                         hipStream_t s) {
+    Ctx &c = ctx();
+    int cap1 = 0, cap2 = 0;
+    list_caps(&cap1, &cap2);
+    n_ljobs_ = (int)specs.size();
+    std::vector<Job> jobs(n_ljobs_);
+    std::vector<ListSet> sets(n_sets);
+    std::vector<int> set_rep(n_sets, -1);
+    std::vector<int64_t> lane_off(n_ljobs_ + 1, 0), est_off(n_ljobs_ + 1, 0), blk_off(n_ljobs_ + 1, 0),
+        row_off(n_sets + 1, 0);
+    int kmax = 0, dxm = 0;
+    int64_t n_keys = 0;
+    for (int j = 0; j < n_ljobs_; ++j) {
+        const JobSpec &sp = specs[j];
+        if (set_rep[set_of[j]] < 0) set_rep[set_of[j]] = j;
+        lane_off[j + 1] = lane_off[j] + (int64_t)sp.n * sp.n_est();
+        est_off[j + 1] = est_off[j] + sp.n_est();
+        blk_off[j + 1] = blk_off[j] + (int64_t)sp.n_est() * ((sp.n + 1023) / 1024);
+        kmax = std::max(kmax, sp.k);
+        dxm = std::max(dxm, sp.dx);
+        n_keys += sp.n_est();
+    }
+    // scratch layout: per set its lists, per job xt, eps, cnt; then the queue
+    size_t bytes = 0;
+    std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets);
+    for (int t = 0; t < n_sets; ++t) {
+        const JobSpec &sp = specs[set_rep[t]];
+        ListSet &S = sets[t];
+        std::memset(&S, 0, sizeof S);
+        for (int cc = 0; cc < sp.dy + sp.dz; ++cc) S.cols[cc] = sp.cols[sp.dx + cc];
+        S.n = sp.n;
+        S.dy = sp.dy;
+        S.dz = sp.dz;
+        S.m1 = std::min(sp.n - 1, cap1);
+        S.m2 = std::min(sp.n - 1, cap2);
+        row_off[t + 1] = row_off[t] + sp.n;
+        // 8 spare entries after each list array: the scan reads in groups of 4
+        o_l1[t] = bytes;
+        bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.m1 + 8), 256);
+        o_l2[t] = bytes;
+        bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.m2 + 8), 256);
+        o_len[t] = bytes;
+        bytes = align_up(bytes + sizeof(int32_t) * 2 * (size_t)sp.n, 256);
+        o_bound[t] = bytes;
+        bytes = align_up(bytes + sizeof(float) * 2 * (size_t)sp.n, 256);
+    }
+    struct Off { size_t xt, eps, cnt; };
+    std::vector<Off> offs(n_ljobs_);
+    for (int j = 0; j < n_ljobs_; ++j) {
+        const JobSpec &sp = specs[j];
+        const size_t pairs = (size_t)sp.n * sp.n_est();
+        offs[j].xt = bytes;
+        bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
+        if (!sp.diag_eps) {
+            offs[j].eps = bytes;
+            bytes = align_up(bytes + sizeof(float) * pairs, 256);
+        }
+        if (!sp.diag_cnt) {
+            offs[j].cnt = bytes;
+            bytes = align_up(bytes + sizeof(int32_t) * 3 * pairs, 256);
+        }
+    }
+    const size_t o_failq = bytes;
+    bytes = align_up(bytes + sizeof(uint64_t) * (size_t)lane_off[n_ljobs_], 256);
+    int rc;
+    if ((rc = lscratch_.ensure(bytes))) return rc;
+    if ((rc = lcounters_.ensure(256))) return rc;
+    uint8_t *sb = lscratch_.as<uint8_t>();
+    for (int t = 0; t < n_sets; ++t) {
+        ListSet &S = sets[t];
+        S.l1 = reinterpret_cast<LEnt *>(sb + o_l1[t]);
+        S.l2 = reinterpret_cast<LEnt *>(sb + o_l2[t]);
+        S.len = reinterpret_cast<int32_t *>(sb + o_len[t]);
+        S.bound = reinterpret_cast<float *>(sb + o_bound[t]);
+    }
+    // tables: jobs, sets, keys, offsets
+    const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
+    const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
+    const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
+    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + n_sets + 1), 256);
+    const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
+    if ((rc = ltables_.ensure(tbytes))) return rc;
+    static thread_local HostBuf *staging = new HostBuf;
+    if ((rc = staging->ensure(tbytes))) return rc;
+    uint8_t *tb = ltables_.as<uint8_t>();
+    uint8_t *hs = static_cast<uint8_t *>(staging->p);
+    EstKey *keys_dev = reinterpret_cast<EstKey *>(tb + t_jobs + t_sets);
+    EstKey *keys_host = reinterpret_cast<EstKey *>(hs + t_jobs + t_sets);
+    int64_t kpos = 0;
+    for (int j = 0; j < n_ljobs_; ++j) {
+        const JobSpec &sp = specs[j];
+        Job &J = jobs[j];
+        std::memset(&J, 0, sizeof J);
+        for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
+        J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
+        J.n_est = sp.n_est();
+        J.rs = 1;
+        J.set = set_of[j];
+        J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
+        J.eps = sp.diag_eps ? sp.diag_eps : reinterpret_cast<float *>(sb + offs[j].eps);
+        J.cnt = sp.diag_cnt ? sp.diag_cnt : reinterpret_cast<int32_t *>(sb + offs[j].cnt);
+        J.out = sp.out;
+        J.keys = keys_dev + kpos;
+        std::memcpy(keys_host + kpos, sp.keys.data(), sizeof(EstKey) * J.n_est);
+        kpos += J.n_est;
+    }
+    std::memcpy(hs, jobs.data(), sizeof(Job) * n_ljobs_);
+    std::memcpy(hs + t_jobs, sets.data(), sizeof(ListSet) * n_sets);
+    int64_t *oh = reinterpret_cast<int64_t *>(hs + t_jobs + t_sets + t_keys);
+    int64_t *od = reinterpret_cast<int64_t *>(tb + t_jobs + t_sets + t_keys);
+    const size_t nj1 = (size_t)n_ljobs_ + 1;
+    std::memcpy(oh, lane_off.data(), sizeof(int64_t) * nj1);
+    std::memcpy(oh + nj1, est_off.data(), sizeof(int64_t) * nj1);
+    std::memcpy(oh + 2 * nj1, blk_off.data(), sizeof(int64_t) * nj1);
+    std::memcpy(oh + 3 * nj1, row_off.data(), sizeof(int64_t) * (n_sets + 1));
+    ljobs_dev_ = reinterpret_cast<Job *>(tb);
+    lblk_off_ = od + 2 * nj1;
+    lpermute_blocks_ = blk_off[n_ljobs_];
+    ListLaunch &L = ll_;
+    L.jobs = ljobs_dev_;
+    L.sets = reinterpret_cast<const ListSet *>(tb + t_jobs);
+    L.lane_off = od;
+    L.est_off = od + nj1;
+    L.row_off = od + 3 * nj1;
+    L.n_jobs = n_ljobs_;
+    L.n_sets = n_sets;
+    L.lanes = lane_off[n_ljobs_];
+    L.rows = row_off[n_sets];
+    L.ests = est_off[n_ljobs_];
+    L.failq = reinterpret_cast<uint64_t *>(sb + o_failq);
+    L.counters = lcounters_.as<uint32_t>();
+    L.kmax = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
+    L.dxm = dxm <= 1 ? 1 : kMaxDx;
+    L.fb_grid = std::max(1, c.n_cu) * 4;
+    if (L.lanes >= ((int64_t)1 << 40) || n_ljobs_ >= (1 << 23)) return fail(MTE_EINVAL, "batch too large");
+    n_est_pairs_ = L.lanes;
+    MTE_HIP(hipMemcpyAsync(tb, hs, tbytes, hipMemcpyHostToDevice, s));
+    MTE_HIP(hipStreamSynchronize(s));
+    return MTE_OK;
+}
+
+int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+    Ctx &c = ctx();
     TileCfg cfg;
     if (!kernel_variant(tc.variant, &cfg)) return fail(MTE_EINVAL, "bad tile variant");
     variant_ = tc.variant;
     n_jobs_ = (int)specs.size();
-    int64_t nmax = 0;
-    for (const auto &sp : specs) {
-        if (sp.n_est() < 1) return fail(MTE_EINVAL, "job without estimates");
+    for (const auto &sp : specs)
         if (sp.k > cfg.kmax || sp.dx > cfg.dxm || sp.dy > cfg.dym || sp.dz > cfg.dzm)
             return fail(MTE_EINVAL, "job does not fit the tile configuration");
-        if (sp.n < sp.k + 1) return fail(MTE_EINVAL, "N < k+1");
-        for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc)
-            if (!sp.cols[cc]) return fail(MTE_EINVAL, "null column pointer");
-        if (!sp.out) return fail(MTE_EINVAL, "null output pointer");
-        nmax = std::max<int64_t>(nmax, sp.n);
-    }
-    int rc = ensure_harm(nmax);
-    if (rc) return rc;
+    int rc;
     const int qt = kWaves * 64 * cfg.qp;
     const int bpc = variant_blocks_per_cu(variant_);
     const int64_t slots = (int64_t)c.n_cu * bpc;
@@ -466,7 +704,6 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     li_.grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, slots));
     permute_blocks_ = blk_off[n_jobs_];
     sync_total_ = sync_words_total;
-    n_est_total_ = n_keys;
 
     if ((rc = scratch_.ensure(std::max<size_t>(scratch_bytes, 256)))) return rc;
     if ((rc = sync_.ensure(sizeof(uint32_t) * (size_t)sync_total_))) return rc;
@@ -518,25 +755,58 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     return MTE_OK;
 }
 
-int Batch::launch_direct(hipStream_t s) {
-    if (launch_reset(sync_.as<uint32_t>(), sync_total_, s)) return hip_fail(hipGetLastError(), "reset launch");
-    if (launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, s))
-        return hip_fail(hipGetLastError(), "permute launch");
-    Ctx &c = ctx();
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c.timing) {
-        MTE_HIP(hipEventCreate(&e0));
-        MTE_HIP(hipEventCreate(&e1));
-        MTE_HIP(hipEventRecord(e0, s));
+// Launch sequence: the all-pairs part (reset, permute, main kernel), then
+// the list part (reset, permute into xt, build, scan, fallback, reduce).
+int Batch::launch_all(hipStream_t s, bool timed) {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto begin = [&]() -> int {
+        if (!timed) return MTE_OK;
+        MTE_HIP(hipEventCreate(&ev[0]));
+        MTE_HIP(hipEventCreate(&ev[1]));
+        MTE_HIP(hipEventRecord(ev[0], s));
+        return MTE_OK;
+    };
+    auto end = [&](int stage) -> int {
+        if (!timed) return MTE_OK;
+        MTE_HIP(hipEventRecord(ev[1], s));
+        record_timing_pair(stage, ev[0], ev[1]);
+        return MTE_OK;
+    };
+    int rc;
+    if (n_jobs_ > 0) {
+        if (launch_reset(sync_.as<uint32_t>(), sync_total_, s)) return hip_fail(hipGetLastError(), "reset launch");
+        if ((rc = begin())) return rc;
+        if (launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, s))
+            return hip_fail(hipGetLastError(), "permute launch");
+        if ((rc = end(kStagePermute))) return rc;
+        if ((rc = begin())) return rc;
+        if (launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), s))
+            return hip_fail(hipGetLastError(), "main kernel launch");
+        if ((rc = end(kStageAllPairs))) return rc;
     }
-    if (launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), s))
-        return hip_fail(hipGetLastError(), "main kernel launch");
-    if (c.timing) {
-        MTE_HIP(hipEventRecord(e1, s));
-        record_timing_pair(e0, e1);
+    if (n_ljobs_ > 0) {
+        if (launch_reset(lcounters_.as<uint32_t>(), 64, s)) return hip_fail(hipGetLastError(), "reset launch");
+        if ((rc = begin())) return rc;
+        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, s))
+            return hip_fail(hipGetLastError(), "permute launch");
+        if ((rc = end(kStagePermute))) return rc;
+        if ((rc = begin())) return rc;
+        if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
+        if ((rc = end(kStageBuild))) return rc;
+        if ((rc = begin())) return rc;
+        if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
+        if ((rc = end(kStageScan))) return rc;
+        if ((rc = begin())) return rc;
+        if (launch_list_fallback(ll_, s)) return hip_fail(hipGetLastError(), "list fallback launch");
+        if ((rc = end(kStageFallback))) return rc;
+        if ((rc = begin())) return rc;
+        if (launch_list_reduce(ll_, harm_table(), s)) return hip_fail(hipGetLastError(), "list reduce launch");
+        if ((rc = end(kStageReduce))) return rc;
     }
     return MTE_OK;
 }
+
+int Batch::launch_direct(hipStream_t s) { return launch_all(s, ctx().timing); }
 
 int Batch::capture() {
     Ctx &c = ctx();
@@ -546,9 +816,7 @@ int Batch::capture() {
         graph_failed_ = true;
         return MTE_OK;
     }
-    bool ok = launch_reset(sync_.as<uint32_t>(), sync_total_, cs) == 0 &&
-              launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, cs) == 0 &&
-              launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), cs) == 0;
+    bool ok = launch_all(cs, false) == MTE_OK;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (!ok || e != hipSuccess || !g) {
@@ -585,8 +853,20 @@ int Batch::enqueue(hipStream_t s, bool use_graph) {
 
 int Batch::check_error(hipStream_t s) {
     uint32_t flag = 0;
-    MTE_HIP(hipMemcpyAsync(&flag, work_ + 1, sizeof flag, hipMemcpyDeviceToHost, s));
+    uint32_t words[kListStatWord + 6] = {};
+    if (n_jobs_ > 0) MTE_HIP(hipMemcpyAsync(&flag, work_ + 1, sizeof flag, hipMemcpyDeviceToHost, s));
+    if (n_ljobs_ > 0)
+        MTE_HIP(hipMemcpyAsync(words, lcounters_.as<uint32_t>(), sizeof words, hipMemcpyDeviceToHost, s));
     MTE_HIP(hipStreamSynchronize(s));
+    if (n_ljobs_ > 0) {
+        uint64_t seen[3];
+        std::memcpy(seen, words + kListStatWord, sizeof seen);
+        Ctx &c = ctx();
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.list_pairs += n_est_pairs_;
+        c.list_undecided += words[0];
+        for (int t = 0; t < 3; ++t) c.list_seen[t] += (int64_t)seen[t];
+    }
     if (flag) return fail(MTE_EDEVICE, "a kernel exceeded its bounded wait");
     return MTE_OK;
 }

@@ -83,15 +83,29 @@ struct TileChoice {
     int rs_mult = 1;                   // multiplier on the heuristic split count
 };
 
+// Which path runs each job of a batch: -1 = all-pairs kernel, otherwise the
+// index of the job's neighbour-list set (jobs with the same N and the same Y
+// and Z columns share one set).  The list path is used for jobs with Z
+// columns whose set carries at least kListMinEstimates estimates; the
+// environment variable MTE_FORCE_MODE=brute|list overrides that (results are
+// the same either way).
+constexpr int kListMinEstimates = 8;
+int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, int *n_sets);
+
+// Timed stages (HIP events around each launch when timing is enabled).
+enum Stage { kStageAllPairs = 0, kStageBuild, kStageScan, kStageFallback, kStageReduce, kStagePermute,
+             kStages };
+
 // One launch: its tables, scratch and (optionally) a captured graph.
 class Batch {
 public:
     ~Batch();
-    // Lay out and upload everything for `specs` with the given tile choice.
+    // Lay out and upload everything for `specs` with the given tile choice
+    // (the tile choice only concerns the jobs of the all-pairs kernel).
     int prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s);
-    // Enqueue reset -> permute -> main kernel on s (graph replay if captured).
+    // Enqueue the launch sequence on s (graph replay if captured).
     int enqueue(hipStream_t s, bool use_graph);
-    // Non-zero when a kernel reported an error (reads a device word; syncs s).
+    // Non-zero when a kernel reported an error (reads device words; syncs s).
     int check_error(hipStream_t s);
     size_t device_bytes() const;
     int variant() const { return variant_; }
@@ -99,6 +113,19 @@ public:
 private:
     int capture();
     int launch_direct(hipStream_t s);
+    int launch_all(hipStream_t s, bool timed);
+    int prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s);
+    int prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
+                      hipStream_t s);
+    // neighbour-list part
+    int n_ljobs_ = 0;
+    ListLaunch ll_{};
+    int64_t lpermute_blocks_ = 0;
+    Job *ljobs_dev_ = nullptr;
+    int64_t *lblk_off_ = nullptr;
+    DevBuf ltables_, lscratch_, lcounters_;
+    int64_t n_est_pairs_ = 0;
+    // all-pairs part
     int variant_ = -1;
     int n_jobs_ = 0;
     int64_t n_est_total_ = 0;
@@ -129,11 +156,15 @@ struct Ctx {
     std::vector<double *> retired;
     // autotuner: shape key -> choice
     std::map<std::string, TileChoice> tuned;
-    // kernel timing
+    // kernel timing per stage
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
-    int64_t timed_launches = 0;
-    double timed_ms = 0.0;
+    struct Pending { int stage; hipEvent_t a, b; };
+    std::vector<Pending> pending_events;
+    int64_t timed_launches[kStages] = {};
+    double timed_ms[kStages] = {};
+    // list path statistics (from checked launches)
+    int64_t list_pairs = 0, list_undecided = 0;
+    int64_t list_seen[3] = {};
 };
 
 Ctx &ctx();
@@ -158,6 +189,6 @@ int validate_host_finite(const float *p, int64_t count, const char *name);
 // Host mirror of the device harmonic table (same summation order).
 double harmonic_host(int64_t n);
 
-void record_timing_pair(hipEvent_t a, hipEvent_t b);
+void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b);
 
 }  // namespace mte

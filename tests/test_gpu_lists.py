@@ -1,0 +1,89 @@
+"""The neighbour-list path against the oracle and against the all-pairs kernel.
+
+The list path decides each (row, estimate) pair from per-row neighbour lists
+in the (Y,Z) and Z subspaces and redoes the pairs the lists cannot decide over
+all rows.  Its radii and counts must equal the oracle's bit for bit, whatever
+the list capacities (tiny capacities force most pairs through the redo), and
+its CMI values must be bitwise those of the all-pairs kernel (same counts, same
+fixed summation order).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1902_06828_amd as mte
+import synth
+from test_gpu_parity import CASES, check_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+LIST_CASES = [c for c in CASES if c[1][2] > 0]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("caps", ["default", "16,40", "2,3"])
+@pytest.mark.parametrize("n,dims,k,kind,S", LIST_CASES)
+def test_list_path_parity(monkeypatch, caps, n, dims, k, kind, S):
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    if caps != "default":
+        monkeypatch.setenv("MTE_LIST_CAP", caps)
+    say("list case", n, dims, k, kind, S, "caps", caps)
+    X, Y, Z = synth.random_points(n, dims, seed=n * 7 + k, kind=kind)
+    mte.mte_list_stats(reset=True)
+    check_against_oracle(X, Y, Z, k, S + 8)
+    pairs, undecided = mte.mte_list_stats(reset=True)
+    assert pairs == n * (S + 9)
+    if caps == "2,3" and n > 4 * k:
+        assert undecided > 0          # the redo over all rows was exercised
+
+
+@pytest.mark.parametrize("n,dims,kind,seed", [(3000, (1, 1, 5), "normal", 1), (2048, (2, 1, 3), "dup", 2),
+                                              (1000, (1, 2, 7), "grid", 3), (4097, (1, 1, 1), "wide", 4)])
+def test_list_equals_all_pairs(monkeypatch, n, dims, kind, seed):
+    X, Y, Z = synth.random_points(n, dims, seed=seed, kind=kind)
+    out = {}
+    for mode in ("brute", "list"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("mode", mode, n, dims, kind)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, 4, 30, seed, 2)
+    for a, b in zip(out["brute"], out["list"]):
+        assert np.array_equal(a, b)
+
+
+def test_full_size_c2_list_equals_all_pairs(monkeypatch):
+    # the benchmark's workload (N = 10000, 201 estimates) on both paths
+    X, Y, Z, _ = synth.c2_te_inputs(10000, seed=2)
+    out = {}
+    for mode in ("brute", "list"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("C2 full size, mode", mode)
+        mte.mte_list_stats(reset=True)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, 4, 200, 2, 0)
+        if mode == "list":
+            pairs, undecided = mte.mte_list_stats(reset=True)
+            say("pairs", pairs, "redone over all rows", undecided)
+            assert pairs == 10000 * 201 and undecided < pairs // 100
+    for a, b in zip(out["brute"], out["list"]):
+        assert np.array_equal(a, b)
+
+
+def test_shared_lists_across_jobs(monkeypatch):
+    # several candidates with the same Y and Z (one list set) in one launch:
+    # the greedy driver's batches; each must equal its own single-job result
+    series, links = synth.var_network(6, 1500, seed=6)
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    target = min(i for (i, _, _, _) in links)
+    cands = [j for j in range(6) if j != target]
+    say("greedy with shared lists, target", target)
+    res = mte.mte_select_sources(series, target, cands, max_lag_sources=3, alpha=0.05, S=40, seed=6)
+    monkeypatch.setenv("MTE_FORCE_MODE", "brute")
+    ref = mte.mte_select_sources(series, target, cands, max_lag_sources=3, alpha=0.05, S=40, seed=6)
+    for key in ("target_past", "sources", "sources_before_omnibus"):
+        assert res[key] == ref[key]
+    assert res["omnibus_te"] == ref["omnibus_te"] and res["omnibus_p"] == ref["omnibus_p"]

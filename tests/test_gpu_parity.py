@@ -113,6 +113,7 @@ def test_overflowing_differences():
 
 
 def test_splits_do_not_change_results(monkeypatch):
+    monkeypatch.setenv("MTE_FORCE_MODE", "brute")
     X, Y, Z = synth.random_points(3000, (1, 1, 5), seed=9)
     res = []
     for split in ("0", "1", "4"):
@@ -125,6 +126,7 @@ def test_splits_do_not_change_results(monkeypatch):
 
 
 def test_every_tile_configuration(monkeypatch):
+    monkeypatch.setenv("MTE_FORCE_MODE", "brute")
     X, Y, Z = synth.random_points(700, (1, 1, 4), seed=21)
     ref = mte.cmi_ksg_diag(X, Y, Z, 4, 9, 2, 0)
     tested = 0
