@@ -59,11 +59,11 @@ def build_ops(n, dy, dz):
 
 def scan_ops(dx, entries):
     """Neighbour-list scan, from the list entries read: a k-NN entry costs
-    2*dx+1 ops (X subtract/|.|-max, max with d_yz, compare with the k-th), an
-    n_yz entry 2 (compare, add), a Z-list entry 2*dx+5 (X subtract/|.|-max, max
-    with d_z, two compares, two adds)."""
-    knn, yz, zl = entries
-    return knn * (2 * dx + 1) + yz * 2 + zl * (2 * dx + 5)
+    2*dx+1 ops (X subtract/|.|-max, max with d_yz, compare with the k-th), a
+    Z-list entry 2*dx+7 (X subtract/|.|-max, max with d_z, three compares,
+    three adds)."""
+    knn, zl = entries
+    return knn * (2 * dx + 1) + zl * (2 * dx + 7)
 
 
 def cpu_baseline(X, Y, Z, budget_s=15.0):
@@ -210,7 +210,9 @@ def main():
     value = E * args.steps / dt
     # the list path's entry counts for this input (one checked call, same data)
     mte.mte_list_stats(reset=True)
+    mte.mte_list_stats_enable(True)
     mte.cmi_ksg_surrogates(X, Y, Z, K_NN, S, SEED)
+    mte.mte_list_stats_enable(False)
     pairs, undecided, entries = mte.mte_list_stats(reset=True, entries=True)
     dominant = max(stage_ms, key=lambda k: stage_ms[k]["ms_per_launch"] * stage_ms[k]["launches_per_step"])
     if dominant == "all_pairs":

@@ -283,9 +283,13 @@ int mte_kernel_timing_stage(int stage, int64_t *launches_out, double *total_ms_o
  * library has checked (the host-pointer calls, the greedy driver and the
  * request loop): (row, estimate) pairs computed on the list path, how many of
  * them the lists could not decide and were redone over all rows, and (if
- * entries_out is not NULL) entries_out[0..2] = list entries read by the
- * k-NN scan, the n_yz scan and the Z-list scan.  reset = 1 clears them.
+ * entries_out is not NULL) entries_out[0..1] = list entries read by the
+ * k-NN scan of the (Y,Z) lists and by the count scan of the Z lists; the
+ * entry counts are only taken by launches made while
+ * mte_list_stats_enable(1) is in effect (directly launched or captured), as
+ * they cost atomics in the scan kernel.  reset = 1 clears them.
  * ------------------------------------------------------------------------ */
+int mte_list_stats_enable(int enable);
 int mte_list_stats(int64_t *pairs_out, int64_t *undecided_out, int64_t *entries_out, int reset);
 
 #ifdef __cplusplus

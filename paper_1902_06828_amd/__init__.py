@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     mte_kernel_timing_read,
     mte_kernel_timing_stage,
     mte_list_stats,
+    mte_list_stats_enable,
     mte_max_statistic,
     mte_min_statistic,
     mte_omnibus,

@@ -93,6 +93,7 @@ SIGNATURES = {
     "mte_kernel_timing_read": [_P, _P, _I],
     "mte_kernel_timing_stage": [_I, _P, _P, _I],
     "mte_list_stats": [_P, _P, _P, _I],
+    "mte_list_stats_enable": [_I],
 }
 
 _lib = None
@@ -386,11 +387,15 @@ def mte_kernel_timing_stage(stage, reset: bool = False):
     return n.value, ms.value
 
 
+def mte_list_stats_enable(enable: bool) -> None:
+    _check(lib().mte_list_stats_enable(int(enable)))
+
+
 def mte_list_stats(reset: bool = False, entries: bool = False):
     """Returns (pairs on the list path, pairs redone over all rows), plus the
     list entries read by the three scans when `entries` is set."""
     a, b = ctypes.c_int64(), ctypes.c_int64()
-    ent = np.zeros(3, np.int64)
+    ent = np.zeros(2, np.int64)
     _check(lib().mte_list_stats(ctypes.byref(a), ctypes.byref(b), _ptr(ent), int(reset)))
     if entries:
         return a.value, b.value, [int(v) for v in ent]

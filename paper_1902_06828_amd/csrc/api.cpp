@@ -317,16 +317,23 @@ int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int rese
     return mte_kernel_timing_stage(kStageAllPairs, launches_out, total_ms_out, reset);
 }
 
+int mte_list_stats_enable(int enable) {
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.list_stats = enable != 0;
+    return MTE_OK;
+}
+
 int mte_list_stats(int64_t *pairs_out, int64_t *undecided_out, int64_t *entries_out, int reset) {
     Ctx &c = ctx();
     std::lock_guard<std::mutex> lk(c.mu);
     if (pairs_out) *pairs_out = c.list_pairs;
     if (undecided_out) *undecided_out = c.list_undecided;
     if (entries_out)
-        for (int t = 0; t < 3; ++t) entries_out[t] = c.list_seen[t];
+        for (int t = 0; t < 2; ++t) entries_out[t] = c.list_seen[t];
     if (reset) {
         c.list_pairs = c.list_undecided = 0;
-        for (int t = 0; t < 3; ++t) c.list_seen[t] = 0;
+        for (int t = 0; t < 2; ++t) c.list_seen[t] = 0;
     }
     return MTE_OK;
 }

@@ -69,12 +69,20 @@ struct Job {
 // Y and Z columns are the same.  For row i, list 1 holds the other rows j with
 // the (Y,Z) max-norm distance d_yz(i,j) in the smallest key buckets that fit
 // m1 entries, list 2 the same for the Z distance d_z(i,j) and m2.  A key is
-// the top 12 bits of the distance's float encoding (exponent and 3 mantissa
-// bits), so a list is ordered by bucket, not fully sorted.  bound[i][w] is a
+// the top 12 bits of the distance's float encoding (8 exponent and 4
+// mantissa bits), so a list is ordered by bucket, not fully sorted.  List 2 entries
+// also carry d_yz (d_yz >= d_z, so every row with d_yz below a radius is in
+// the part of list 2 below that radius).  bound[i][w] is a
 // lower bound of every unlisted distance (+inf when nothing is left out), so
 // a radius r <= bound[i][w] is decided by the list alone.
 struct LEnt {
-    float d;                      // distance
+    float d;                      // d_yz
+    int32_t j;                    // row
+};
+
+struct LEnt2 {
+    float dz;                     // d_z (the list key)
+    float dyz;                    // d_yz, so that n_yz is counted from this list too
     int32_t j;                    // row
 };
 
@@ -83,12 +91,17 @@ struct ListSet {
     int n, dy, dz;
     int m1, m2;                   // entries reserved per row
     LEnt *l1;                     // [n][m1]  (Y,Z) list
-    LEnt *l2;                     // [n][m2]  Z list
+    LEnt2 *l2;                    // [n][m2]  Z list
     int32_t *len;                 // [n][2]
     float *bound;                 // [n][2]
 };
 
+constexpr int kBuildRows = 2;                // rows per build block when N <= 2^16
+constexpr int kBuildCopies = 1;              // histogram copies per row (spread LDS atomics)
 constexpr int kListStatWord = 16;
+constexpr int kListStatSlots = 64;            // spread so that the atomics do not queue on one address
+constexpr int kListStatStride = 16;           // words (64 bytes) per slot
+constexpr int kListCounterWords = kListStatWord + kListStatSlots * kListStatStride;
 constexpr int kKeyShift = 19;                 // 4096 key buckets
 constexpr int kKeyBins = 1 << (32 - kKeyShift - 1);
 
@@ -98,13 +111,20 @@ struct ListLaunch {
     const ListSet *sets;          // device
     const int64_t *lane_off;      // [n_jobs+1] prefix sums of n * n_est
     const int64_t *row_off;       // [n_sets+1] prefix sums of the sets' n
+    const int64_t *build_off;     // [n_sets+1] prefix sums of the build blocks per set
+    int64_t build_blocks;
+    int build_qb;                 // rows per build block: kBuildRows (N <= 2^16) or 1
+    int build_pack;               // 16-bit packed histograms (every set has N <= 2^16)
+    int stats;                    // non-zero: the scan accumulates its entry counts
     const int64_t *est_off;       // [n_jobs+1] prefix sums of n_est
     int n_jobs, n_sets;
     int64_t lanes, rows, ests;
     uint64_t *failq;              // [lanes] (job << 40 | i * n_est + e) of undecided pairs
-    uint32_t *counters;           // [0] undecided pairs; from word kListStatWord three
-                                  // uint64 totals of list entries read (k-NN scan,
-                                  // n_yz scan, Z-list scan); 64 words, zeroed per launch
+    uint32_t *counters;           // [0] undecided pairs; from word kListStatWord,
+                                  // kListStatSlots slots of kListStatStride words each
+                                  // holding two uint64 totals of list entries read (k-NN
+                                  // scan, Z-list scan); kListCounterWords words, zeroed
+                                  // per launch
     int kmax, dxm;                // compile-time classes of the scan kernel
     int fb_grid;                  // blocks of the fallback kernel
 };

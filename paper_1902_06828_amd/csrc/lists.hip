@@ -17,9 +17,9 @@
 //            estimate's permuted X; it stops at the first bucket whose floor
 //            reaches the current k-th distance (nothing later can enter).  The
 //            radius is exact when it stopped that way or when the k-th
-//            distance is at most the list's bound.  n_yz counts list 1 below
-//            eps; n_z and n_xz scan list 2 until its bucket floor reaches eps,
-//            exact when it stopped that way or eps <= the bound of list 2;
+//            distance is at most the list's bound.  n_z, n_yz and n_xz scan
+//            list 2 (whose entries also carry d_yz) until its bucket floor
+//            reaches eps, exact when it stopped that way or eps <= its bound;
 //   fallback the pairs the lists cannot decide (rare) are queued and redone
 //            by one wave each over all rows;
 //   reduce   the digamma sum per estimate in the same fixed order as the
@@ -98,132 +98,219 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint3
 }
 
 // ------------------------------------------------------------------ build
-// One block per (list set, row).  Pass 1 histograms the keys of d_yz and d_z
-// over the other rows; the largest key prefix of each histogram that fits the
-// capacity is kept and the histogram becomes the bucket write cursors; pass 2
-// recomputes the same distances and writes the kept rows bucket by bucket.
+// One block per (list set, QB consecutive rows).  Pass 1 histograms the keys
+// of d_yz and d_z over the other rows; for each row and list the largest key
+// prefix that fits the capacity is kept and the histogram becomes the bucket
+// write cursors; pass 2 recomputes the same distances and writes the kept
+// rows bucket by bucket.  Each reference row is loaded once for the QB rows of
+// the block.  The histogram of a row has C copies, lane l counting into copy
+// l mod C, so that lanes with equal keys mostly update different words (the
+// cursors of a bucket's copies follow each other, keeping bucket order).
+// PACK: both lists' counts of a bucket share one 32-bit word, 16 bits each
+// (counts stay below 2^16 when N <= 2^16).
+template <int QB>
+constexpr int row_batch() { return QB == 1 ? 8 : 4; }   // reference rows per thread per step
+
+// Bucket b of a histogram lives at word b + b/16: a thread's 16 consecutive
+// buckets then start 17 words after its neighbour's, so the selection's
+// per-thread walks fall into different LDS banks.
+constexpr int kHistWords = kKeyBins + kKeyBins / 16;
+
+__device__ __forceinline__ uint32_t hist_slot(uint32_t key) { return key + (key >> 4); }
+
+template <int QB, int C, bool PACK>
 struct BuildSmem {
-    uint32_t h[2][kKeyBins];
-    float q[kMaxDy + kMaxDz];
+    static constexpr int kCopy = PACK ? kHistWords : 2 * kHistWords;   // words of one copy
+    uint32_t h[QB][C][kCopy];
+    float q[QB][kMaxDy + kMaxDz];
     uint32_t wtot[kWaves];
     uint32_t red[2][kWaves];
+    uint32_t kept_bins[QB][2], kept_rows[QB][2];
     int set;
 };
 
-// Calls f(j, d_z, d_yz) for every row j != i, kRowBatch rows per thread at a
-// time so that the loads of a column for all of them are in flight together.
-constexpr int kRowBatch = 8;
+template <bool PACK>
+__device__ __forceinline__ uint32_t *bin_word(uint32_t *h, int w, uint32_t key) {
+    return PACK ? h + hist_slot(key) : h + w * kHistWords + hist_slot(key);
+}
 
-template <class F>
-__device__ __forceinline__ void for_each_row(const ListSet &S, const float *q, int i, int tid, F &&f) {
-    const int n = S.n;
-    for (int j0 = tid; j0 < n; j0 += kBlock * kRowBatch) {
-        float a[kRowBatch], b[kRowBatch];
+template <bool PACK>
+__device__ __forceinline__ uint32_t bin_inc(int w) {
+    return PACK ? (1u << (16 * w)) : 1u;
+}
+
+template <bool PACK>
+__device__ __forceinline__ uint32_t bin_get(uint32_t word, int w) {
+    return PACK ? (word >> (16 * w)) & 0xffffu : word;
+}
+
+template <bool PACK>
+__device__ __forceinline__ void bin_set(uint32_t *wd, int w, uint32_t v) {
+    if (PACK) *wd = (*wd & ~(0xffffu << (16 * w))) | (v << (16 * w));
+    else *wd = v;
+}
+
+// Max-norm over columns [c_lo, c_hi) of `cols` into acc[r][u] for the block
+// rows r and reference rows j0 + u*kBlock; the loads of up to kColChunk
+// columns are issued together before they are used.
+constexpr int kColChunk = 4;
+
+template <int QB, int R>
+__device__ __forceinline__ void acc_cols(const float *const *cols, const float (*q)[kMaxDy + kMaxDz], int qoff,
+                                         int ncols, int n, int i0, int j0, float (&acc)[QB][R]) {
+    for (int c0 = 0; c0 < ncols; c0 += kColChunk) {
+        float v[kColChunk][R];
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) a[u] = 0.f;
-        for (int c = 0; c < S.dz; ++c) {
-            const float *col = S.cols[S.dy + c];
-            const float qc = q[S.dy + c];
-            float v[kRowBatch];
+        for (int cc = 0; cc < kColChunk; ++cc) {
+            if (c0 + cc < ncols) {
+                const float *col = cols[c0 + cc];
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                const int j = j0 + u * kBlock;
-                v[u] = j < n ? col[j] : qc;
+                for (int u = 0; u < R; ++u) {
+                    const int j = j0 + u * kBlock;
+                    v[cc][u] = col[j < n ? j : i0];
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) a[u] = fmax_(a[u], absdiff(qc, v[u]));
         }
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) b[u] = a[u];
-        for (int c = 0; c < S.dy; ++c) {
-            const float *col = S.cols[c];
-            const float qc = q[c];
-            float v[kRowBatch];
+        for (int cc = 0; cc < kColChunk; ++cc) {
+            if (c0 + cc < ncols) {
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                const int j = j0 + u * kBlock;
-                v[u] = j < n ? col[j] : qc;
+                for (int r = 0; r < QB; ++r) {
+                    const float qc = q[r][qoff + c0 + cc];
+#pragma unroll
+                    for (int u = 0; u < R; ++u) acc[r][u] = fmax_(acc[r][u], absdiff(qc, v[cc][u]));
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) b[u] = fmax_(b[u], absdiff(qc, v[u]));
-        }
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) {
-            const int j = j0 + u * kBlock;
-            if (j < n && j != i) f(j, a[u], b[u]);
         }
     }
 }
 
+// Calls f(r, j, d_z, d_yz) for every block row r (valid rows only) and every
+// other row j, row_batch<QB>() reference rows per thread at a time.
+template <int QB, class F>
+__device__ __forceinline__ void for_each_pair(const ListSet &S, const float (*q)[kMaxDy + kMaxDz], int i0,
+                                              int nq, int tid, F &&f) {
+    constexpr int kRowBatch = row_batch<QB>();
+    const int n = S.n;
+    for (int j0 = tid; j0 < n; j0 += kBlock * kRowBatch) {
+        float a[QB][kRowBatch], b[QB][kRowBatch];
+#pragma unroll
+        for (int r = 0; r < QB; ++r)
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) a[r][u] = 0.f;
+        acc_cols<QB, kRowBatch>(S.cols + S.dy, q, S.dy, S.dz, n, i0, j0, a);
+#pragma unroll
+        for (int r = 0; r < QB; ++r)
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) b[r][u] = a[r][u];
+        acc_cols<QB, kRowBatch>(S.cols, q, 0, S.dy, n, i0, j0, b);
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+            const int j = j0 + u * kBlock;
+            if (j >= n) continue;
+#pragma unroll
+            for (int r = 0; r < QB; ++r)
+                if (r < nq && j != i0 + r) f(r, j, a[r][u], b[r][u]);
+        }
+    }
+}
+
+template <int QB, int C, bool PACK>
 __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__restrict__ sets, int n_sets,
-                                                           const int64_t *__restrict__ row_off) {
-    __shared__ BuildSmem sm;
+                                                           const int64_t *__restrict__ blk_off) {
+    using Sm = BuildSmem<QB, C, PACK>;
+    __shared__ Sm sm;
     const int tid = tid_x();
+    const int copy = tid & (C - 1);
     const int64_t b = bid_x();
-    if (tid == 0) sm.set = find_job(row_off, n_sets, b);
-    for (int x = tid; x < 2 * kKeyBins; x += kBlock) (&sm.h[0][0])[x] = 0u;
+    if (tid == 0) sm.set = find_job(blk_off, n_sets, b);
+    for (int x = tid; x < QB * C * Sm::kCopy; x += kBlock) (&sm.h[0][0][0])[x] = 0u;
     __syncthreads();
     const ListSet &S = sets[sm.set];
-    const int i = (int)(b - row_off[sm.set]);
     const int n = S.n;
-    if (tid < S.dy + S.dz) sm.q[tid] = S.cols[tid][i];
-    __syncthreads();
-
-    for_each_row(S, sm.q, i, tid, [&](int, float a, float c) {
-        atomicAdd(&sm.h[0][key_of(c)], 1u);
-        atomicAdd(&sm.h[1][key_of(a)], 1u);
-    });
-    __syncthreads();
-
-    // per list: keep the largest bucket prefix with at most m entries
-    constexpr int kPer = kKeyBins / kBlock;
-    uint32_t kept_bins[2], kept_rows[2];
-    for (int w = 0; w < 2; ++w) {
-        const uint32_t cap = (uint32_t)(w == 0 ? S.m1 : S.m2);
-        uint32_t local = 0;
-#pragma unroll
-        for (int x = 0; x < kPer; ++x) local += sm.h[w][tid * kPer + x];
-        uint32_t incl;
-        block_scan(local, incl, sm.wtot);
-        uint32_t run = incl - local, nb = 0, nr = 0;
-#pragma unroll
-        for (int x = 0; x < kPer; ++x) {
-            const uint32_t cnt = sm.h[w][tid * kPer + x];
-            sm.h[w][tid * kPer + x] = run;          // exclusive start = write cursor
-            run += cnt;
-            if (run <= cap) { ++nb; nr += cnt; }
-        }
-        nb = (uint32_t)wave_sum((int)nb);
-        nr = (uint32_t)wave_sum((int)nr);
-        if ((tid & 63) == 0) { sm.red[0][tid >> 6] = nb; sm.red[1][tid >> 6] = nr; }
-        __syncthreads();
-        kept_bins[w] = kept_rows[w] = 0;
-#pragma unroll
-        for (int v = 0; v < kWaves; ++v) { kept_bins[w] += sm.red[0][v]; kept_rows[w] += sm.red[1][v]; }
-        __syncthreads();
+    const int i0 = (int)(b - blk_off[sm.set]) * QB;
+    const int nq = min(QB, n - i0);
+    for (int x = tid; x < QB * (S.dy + S.dz); x += kBlock) {
+        const int r = x / (S.dy + S.dz), c = x - r * (S.dy + S.dz);
+        sm.q[r][c] = S.cols[c][min(i0 + r, n - 1)];
     }
-    // bucket keys below kept_bins[w] are listed (the prefix is contiguous
+    __syncthreads();
+
+    for_each_pair<QB>(S, sm.q, i0, nq, tid, [&](int r, int, float a, float c) {
+        atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, key_of(c)), bin_inc<PACK>(0));
+        atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, key_of(a)), bin_inc<PACK>(1));
+    });
+    __syncthreads();
+
+    // per row and list: keep the largest bucket prefix with at most m entries
+    // (bucket keys below kept_bins are listed: the prefix is contiguous
     // because the cumulative counts grow with the key)
-    LEnt *l1 = S.l1 + (int64_t)i * S.m1;
-    LEnt *l2 = S.l2 + (int64_t)i * S.m2;
-    for_each_row(S, sm.q, i, tid, [&](int j, float a, float c) {
-        const uint32_t k1 = key_of(c), k2 = key_of(a);
-        if (k1 < kept_bins[0]) {
-            const uint32_t pos = atomicAdd(&sm.h[0][k1], 1u);
-            if (pos < (uint32_t)S.m1) l1[pos] = LEnt{c, j};
+    constexpr int kPer = kKeyBins / kBlock;
+#pragma unroll
+    for (int r = 0; r < QB; ++r) {
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const uint32_t cap = (uint32_t)(w == 0 ? S.m1 : S.m2);
+            uint32_t local = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x)
+#pragma unroll
+                for (int cp = 0; cp < C; ++cp)
+                    local += bin_get<PACK>(*bin_word<PACK>(sm.h[r][cp], w, tid * kPer + x), w);
+            uint32_t incl;
+            block_scan(local, incl, sm.wtot);
+            uint32_t run = incl - local, nb = 0, nr = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) {
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int cp = 0; cp < C; ++cp) {
+                    // exclusive start of (bucket, copy) = write cursor
+                    uint32_t *wd = bin_word<PACK>(sm.h[r][cp], w, tid * kPer + x);
+                    const uint32_t v = bin_get<PACK>(*wd, w);
+                    bin_set<PACK>(wd, w, run + cnt);
+                    cnt += v;
+                }
+                run += cnt;
+                if (run <= cap) { ++nb; nr += cnt; }
+            }
+            nb = (uint32_t)wave_sum((int)nb);
+            nr = (uint32_t)wave_sum((int)nr);
+            if ((tid & 63) == 0) { sm.red[0][tid >> 6] = nb; sm.red[1][tid >> 6] = nr; }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t kb = 0, kr = 0;
+                for (int v = 0; v < kWaves; ++v) { kb += sm.red[0][v]; kr += sm.red[1][v]; }
+                sm.kept_bins[r][w] = kb;
+                sm.kept_rows[r][w] = kr;
+            }
+            __syncthreads();
         }
-        if (k2 < kept_bins[1]) {
-            const uint32_t pos = atomicAdd(&sm.h[1][k2], 1u);
-            if (pos < (uint32_t)S.m2) l2[pos] = LEnt{a, j};
+    }
+    for_each_pair<QB>(S, sm.q, i0, nq, tid, [&](int r, int j, float a, float c) {
+        const int64_t i = i0 + r;
+        const uint32_t k1 = key_of(c), k2 = key_of(a);
+        if (k1 < sm.kept_bins[r][0]) {
+            const uint32_t pos =
+                bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1), bin_inc<PACK>(0)), 0);
+            if (pos < (uint32_t)S.m1) S.l1[i * S.m1 + pos] = LEnt{c, j};
+        }
+        if (k2 < sm.kept_bins[r][1]) {
+            const uint32_t pos =
+                bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1)), 1);
+            if (pos < (uint32_t)S.m2) S.l2[i * S.m2 + pos] = LEnt2{a, c, j};
         }
     });
-    if (tid < 2) {
-        const uint32_t total = (uint32_t)(n - 1);
-        const float bound = kept_rows[tid] == total
-                                ? inf_f()
-                                : __uint_as_float(kept_bins[tid] << kKeyShift);
-        S.len[2 * (int64_t)i + tid] = (int32_t)kept_rows[tid];
-        S.bound[2 * (int64_t)i + tid] = bound;
+    if (tid < 2 * QB) {
+        const int r = tid >> 1, w = tid & 1;
+        if (r < nq) {
+            const int64_t i = i0 + r;
+            const uint32_t total = (uint32_t)(n - 1);
+            const uint32_t kb = sm.kept_bins[r][w], kr = sm.kept_rows[r][w];
+            const float bound = kr == total ? inf_f() : __uint_as_float(kb << kKeyShift);
+            S.len[2 * i + w] = (int32_t)kr;
+            S.bound[2 * i + w] = bound;
+        }
     }
 }
 
@@ -250,7 +337,8 @@ struct Lane {
 
     // max-norm over the X columns between this lane's row and the rows of a
     // step (under the estimate's permutation); all loads issued before use
-    __device__ __forceinline__ void xdist(const LEnt (&en)[kU], float (&d)[kU]) const {
+    template <class Ent>
+    __device__ __forceinline__ void xdist(const Ent (&en)[kU], float (&d)[kU]) const {
         float v[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) v[u] = xt[(int64_t)en[u].j * E + e];
@@ -272,12 +360,25 @@ __device__ __forceinline__ void load_step(const LEnt *l, int m, int len, int sel
     for (int u = 0; u < kU; ++u) en[u] = m + u < len ? l[m + u] : LEnt{inf_f(), self};
 }
 
-// distance of the last listed entry of a step (entries are in bucket order)
+__device__ __forceinline__ void load_step(const LEnt2 *l, int m, int len, int self, LEnt2 (&en)[kU]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) en[u] = m + u < len ? l[m + u] : LEnt2{inf_f(), inf_f(), self};
+}
+
+// key distance of the last listed entry of a step (entries are in bucket order)
 __device__ __forceinline__ float last_d(const LEnt (&en)[kU], int m, int len) {
     float last = 0.f;
 #pragma unroll
     for (int u = 0; u < kU; ++u)
         if (m + u < len) last = en[u].d;
+    return last;
+}
+
+__device__ __forceinline__ float last_d(const LEnt2 (&en)[kU], int m, int len) {
+    float last = 0.f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (m + u < len) last = en[u].dz;
     return last;
 }
 
@@ -302,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const LEnt *l1 = S.l1 + (int64_t)i * S.m1;
     const int len1 = S.len[2 * (int64_t)i];
     bool done = false;
-    int seen1 = 0, seen_yz = 0, seen2 = 0;     // list entries read (statistics)
+    int seen1 = 0, seen2 = 0;     // list entries read (statistics)
     {
         LEnt cur[kU];
         load_step(l1, 0, len1, i, cur);
@@ -322,38 +423,26 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const float eps = top[KMAX - 1];
     bool decided = done || eps <= S.bound[2 * (int64_t)i];
 
+    // n_z, n_yz and n_xz from list 2 below eps (every row with d_z < eps, and
+    // so every row with d_yz < eps, is listed when eps <= its bound)
     int cxz = 0, cyz = 0, cz = 0;
     if (decided) {
-        // n_yz: list 1 below eps (every row with d_yz < eps is listed)
-        for (int m = 0; m < len1; m += 2 * kU) {
-            seen_yz = min(m + 2 * kU, len1);
-            float d[2 * kU];
-#pragma unroll
-            for (int u = 0; u < 2 * kU; ++u) d[u] = m + u < len1 ? l1[m + u].d : inf_f();
-            float last = 0.f;
-#pragma unroll
-            for (int u = 0; u < 2 * kU; ++u) {
-                cyz += d[u] < eps;
-                if (m + u < len1) last = d[u];
-            }
-            if (bucket_floor(last) >= eps) break;
-        }
-        // n_z and n_xz: list 2 below eps
-        const LEnt *l2 = S.l2 + (int64_t)i * S.m2;
+        const LEnt2 *l2 = S.l2 + (int64_t)i * S.m2;
         const int len2 = S.len[2 * (int64_t)i + 1];
         bool stop = false;
-        LEnt cur[kU];
+        LEnt2 cur[kU];
         load_step(l2, 0, len2, i, cur);
         for (int m = 0; m < len2; m += kU) {
             seen2 = min(m + kU, len2);
-            LEnt nxt[kU];
+            LEnt2 nxt[kU];
             load_step(l2, m + kU, len2, i, nxt);
             float dx[kU];
             ln.xdist(cur, dx);
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                cz += cur[u].d < eps;
-                cxz += fmax_(dx[u], cur[u].d) < eps;
+                cz += cur[u].dz < eps;
+                cyz += cur[u].dyz < eps;
+                cxz += fmax_(dx[u], cur[u].dz) < eps;
             }
             if (bucket_floor(last_d(cur, m, len2)) >= eps) { stop = true; break; }
 #pragma unroll
@@ -370,10 +459,13 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
         J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
         J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
     }
-    unsigned long long *st = reinterpret_cast<unsigned long long *>(L.counters + kListStatWord);
-    atomicAdd(&st[0], (unsigned long long)seen1);
-    atomicAdd(&st[1], (unsigned long long)seen_yz);
-    atomicAdd(&st[2], (unsigned long long)seen2);
+    if (L.stats) {
+        const int slot = (int)((g >> 6) & (kListStatSlots - 1));
+        unsigned long long *st =
+            reinterpret_cast<unsigned long long *>(L.counters + kListStatWord + slot * kListStatStride);
+        atomicAdd(&st[0], (unsigned long long)seen1);
+        atomicAdd(&st[1], (unsigned long long)seen2);
+    }
 }
 
 // ------------------------------------------------------------------ fallback
@@ -561,9 +653,16 @@ void *scan_fn() {
 }  // namespace
 
 int launch_list_build(const ListLaunch &L, void *stream) {
-    if (L.rows <= 0) return 0;
-    hipLaunchKernelGGL(list_build_kernel, dim3((unsigned)L.rows), dim3(kBlock), 0, (hipStream_t)stream, L.sets,
-                       L.n_sets, L.row_off);
+    if (L.build_blocks <= 0) return 0;
+    const dim3 grid((unsigned)L.build_blocks), block(kBlock);
+    if (L.build_pack && L.build_qb == kBuildRows)
+        hipLaunchKernelGGL((list_build_kernel<kBuildRows, kBuildCopies, true>), grid, block, 0,
+                           (hipStream_t)stream, L.sets, L.n_sets, L.build_off);
+    else if (!L.build_pack && L.build_qb == 1)
+        hipLaunchKernelGGL((list_build_kernel<1, 1, false>), grid, block, 0, (hipStream_t)stream, L.sets,
+                           L.n_sets, L.build_off);
+    else
+        return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -492,7 +492,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     std::vector<ListSet> sets(n_sets);
     std::vector<int> set_rep(n_sets, -1);
     std::vector<int64_t> lane_off(n_ljobs_ + 1, 0), est_off(n_ljobs_ + 1, 0), blk_off(n_ljobs_ + 1, 0),
-        row_off(n_sets + 1, 0);
+        row_off(n_sets + 1, 0), build_off(n_sets + 1, 0);
     int kmax = 0, dxm = 0;
     int64_t n_keys = 0;
     for (int j = 0; j < n_ljobs_; ++j) {
@@ -507,6 +507,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     }
     // scratch layout: per set its lists, per job xt, eps, cnt; then the queue
     size_t bytes = 0;
+    int nmax_set = 0;
     std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets);
     for (int t = 0; t < n_sets; ++t) {
         const JobSpec &sp = specs[set_rep[t]];
@@ -519,11 +520,12 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.m1 = std::min(sp.n - 1, cap1);
         S.m2 = std::min(sp.n - 1, cap2);
         row_off[t + 1] = row_off[t] + sp.n;
+        nmax_set = std::max(nmax_set, sp.n);
         // 8 spare entries after each list array: the scan reads in groups of 4
         o_l1[t] = bytes;
         bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.m1 + 8), 256);
         o_l2[t] = bytes;
-        bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.m2 + 8), 256);
+        bytes = align_up(bytes + sizeof(LEnt2) * ((size_t)sp.n * S.m2 + 8), 256);
         o_len[t] = bytes;
         bytes = align_up(bytes + sizeof(int32_t) * 2 * (size_t)sp.n, 256);
         o_bound[t] = bytes;
@@ -549,12 +551,12 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     bytes = align_up(bytes + sizeof(uint64_t) * (size_t)lane_off[n_ljobs_], 256);
     int rc;
     if ((rc = lscratch_.ensure(bytes))) return rc;
-    if ((rc = lcounters_.ensure(256))) return rc;
+    if ((rc = lcounters_.ensure(sizeof(uint32_t) * kListCounterWords))) return rc;
     uint8_t *sb = lscratch_.as<uint8_t>();
     for (int t = 0; t < n_sets; ++t) {
         ListSet &S = sets[t];
         S.l1 = reinterpret_cast<LEnt *>(sb + o_l1[t]);
-        S.l2 = reinterpret_cast<LEnt *>(sb + o_l2[t]);
+        S.l2 = reinterpret_cast<LEnt2 *>(sb + o_l2[t]);
         S.len = reinterpret_cast<int32_t *>(sb + o_len[t]);
         S.bound = reinterpret_cast<float *>(sb + o_bound[t]);
     }
@@ -562,7 +564,12 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
     const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
     const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
-    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + n_sets + 1), 256);
+    // build blocks: kBuildRows rows each with packed 16-bit histograms when
+    // every set has N <= 2^16, one row each with 32-bit histograms otherwise
+    const bool pack = nmax_set <= 65536;
+    const int qb = pack ? kBuildRows : 1;
+    for (int t = 0; t < n_sets; ++t) build_off[t + 1] = build_off[t] + (row_off[t + 1] - row_off[t] + qb - 1) / qb;
+    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
     const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
     if ((rc = ltables_.ensure(tbytes))) return rc;
     static thread_local HostBuf *staging = new HostBuf;
@@ -598,6 +605,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     std::memcpy(oh + nj1, est_off.data(), sizeof(int64_t) * nj1);
     std::memcpy(oh + 2 * nj1, blk_off.data(), sizeof(int64_t) * nj1);
     std::memcpy(oh + 3 * nj1, row_off.data(), sizeof(int64_t) * (n_sets + 1));
+    std::memcpy(oh + 3 * nj1 + (n_sets + 1), build_off.data(), sizeof(int64_t) * (n_sets + 1));
     ljobs_dev_ = reinterpret_cast<Job *>(tb);
     lblk_off_ = od + 2 * nj1;
     lpermute_blocks_ = blk_off[n_ljobs_];
@@ -607,6 +615,11 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.lane_off = od;
     L.est_off = od + nj1;
     L.row_off = od + 3 * nj1;
+    L.build_off = od + 3 * nj1 + (n_sets + 1);
+    L.build_blocks = build_off[n_sets];
+    L.build_qb = qb;
+    L.build_pack = pack ? 1 : 0;
+    L.stats = 0;
     L.n_jobs = n_ljobs_;
     L.n_sets = n_sets;
     L.lanes = lane_off[n_ljobs_];
@@ -785,11 +798,13 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if ((rc = end(kStageAllPairs))) return rc;
     }
     if (n_ljobs_ > 0) {
-        if (launch_reset(lcounters_.as<uint32_t>(), 64, s)) return hip_fail(hipGetLastError(), "reset launch");
+        if (launch_reset(lcounters_.as<uint32_t>(), kListCounterWords, s))
+            return hip_fail(hipGetLastError(), "reset launch");
         if ((rc = begin())) return rc;
         if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, s))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute))) return rc;
+        ll_.stats = ctx().list_stats ? 1 : 0;
         if ((rc = begin())) return rc;
         if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
         if ((rc = end(kStageBuild))) return rc;
@@ -853,19 +868,25 @@ int Batch::enqueue(hipStream_t s, bool use_graph) {
 
 int Batch::check_error(hipStream_t s) {
     uint32_t flag = 0;
-    uint32_t words[kListStatWord + 6] = {};
+    static thread_local std::vector<uint32_t> words(kListCounterWords);
     if (n_jobs_ > 0) MTE_HIP(hipMemcpyAsync(&flag, work_ + 1, sizeof flag, hipMemcpyDeviceToHost, s));
     if (n_ljobs_ > 0)
-        MTE_HIP(hipMemcpyAsync(words, lcounters_.as<uint32_t>(), sizeof words, hipMemcpyDeviceToHost, s));
+        MTE_HIP(hipMemcpyAsync(words.data(), lcounters_.as<uint32_t>(), sizeof(uint32_t) * kListCounterWords,
+                               hipMemcpyDeviceToHost, s));
     MTE_HIP(hipStreamSynchronize(s));
     if (n_ljobs_ > 0) {
-        uint64_t seen[3];
-        std::memcpy(seen, words + kListStatWord, sizeof seen);
+        uint64_t seen[2] = {0, 0};
+        for (int slot = 0; slot < kListStatSlots; ++slot) {
+            uint64_t v[2];
+            std::memcpy(v, words.data() + kListStatWord + slot * kListStatStride, sizeof v);
+            seen[0] += v[0];
+            seen[1] += v[1];
+        }
         Ctx &c = ctx();
         std::lock_guard<std::mutex> lk(c.mu);
         c.list_pairs += n_est_pairs_;
         c.list_undecided += words[0];
-        for (int t = 0; t < 3; ++t) c.list_seen[t] += (int64_t)seen[t];
+        for (int t = 0; t < 2; ++t) c.list_seen[t] += (int64_t)seen[t];
     }
     if (flag) return fail(MTE_EDEVICE, "a kernel exceeded its bounded wait");
     return MTE_OK;

@@ -164,7 +164,8 @@ struct Ctx {
     double timed_ms[kStages] = {};
     // list path statistics (from checked launches)
     int64_t list_pairs = 0, list_undecided = 0;
-    int64_t list_seen[3] = {};
+    int64_t list_seen[2] = {};
+    bool list_stats = false;           // scan kernels count the list entries they read
 };
 
 Ctx &ctx();

@@ -87,3 +87,25 @@ def test_shared_lists_across_jobs(monkeypatch):
     for key in ("target_past", "sources", "sources_before_omnibus"):
         assert res[key] == ref[key]
     assert res["omnibus_te"] == ref["omnibus_te"] and res["omnibus_p"] == ref["omnibus_p"]
+
+
+def test_large_n_unpacked_histograms(monkeypatch):
+    # N above 2^16 takes the build variant with 32-bit histograms; rows sampled
+    # against the oracle, and the whole output against the all-pairs kernel
+    from oracle import cksg, ksg, perm
+    n, S, seed = 70000, 8, 12
+    X, Y, Z = synth.random_points(n, (1, 1, 2), seed=seed)
+    out = {}
+    for mode in ("brute", "list"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("N = 70000, mode", mode)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, 4, S, seed, 1)
+    for a, b in zip(out["brute"], out["list"]):
+        assert np.array_equal(a, b)
+    cmi, eps, cx, cy, cz = out["list"]
+    rows = np.array([0, 1, 65535, 65536, 65537, n - 1] + list(np.random.default_rng(3).choice(n, 10, replace=False)))
+    for e in (0, S):
+        Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(seed, 1, e - 1, n))
+        re, ra, rb, rc, _ = cksg.eps_and_counts(Xe, Y, Z, 4, queries=rows)
+        assert np.array_equal(eps[e, rows], re) and np.array_equal(cx[e, rows], ra)
+        assert np.array_equal(cy[e, rows], rb) and np.array_equal(cz[e, rows], rc)
