@@ -86,12 +86,15 @@ struct LEnt2 {
     int32_t j;                    // row
 };
 
+constexpr int kListPad = 8;                   // sentinel entries after each row's list
+
 struct ListSet {
     const float *cols[kMaxDy + kMaxDz];   // Y columns, then Z columns
     int n, dy, dz;
-    int m1, m2;                   // entries reserved per row
-    LEnt *l1;                     // [n][m1]  (Y,Z) list
-    LEnt2 *l2;                    // [n][m2]  Z list
+    int m1, m2;                   // list capacities per row
+    int s1, s2;                   // row strides: capacity + kListPad sentinels
+    LEnt *l1;                     // [n][s1]  (Y,Z) list
+    LEnt2 *l2;                    // [n][s2]  Z list
     int32_t *len;                 // [n][2]
     float *bound;                 // [n][2]
 };

@@ -293,21 +293,26 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
         if (k1 < sm.kept_bins[r][0]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1), bin_inc<PACK>(0)), 0);
-            if (pos < (uint32_t)S.m1) S.l1[i * S.m1 + pos] = LEnt{c, j};
+            if (pos < (uint32_t)S.m1) S.l1[i * S.s1 + pos] = LEnt{c, j};
         }
         if (k2 < sm.kept_bins[r][1]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1)), 1);
-            if (pos < (uint32_t)S.m2) S.l2[i * S.m2 + pos] = LEnt2{a, c, j};
+            if (pos < (uint32_t)S.m2) S.l2[i * S.s2 + pos] = LEnt2{a, c, j};
         }
     });
-    if (tid < 2 * QB) {
-        const int r = tid >> 1, w = tid & 1;
-        if (r < nq) {
-            const int64_t i = i0 + r;
-            const uint32_t total = (uint32_t)(n - 1);
-            const uint32_t kb = sm.kept_bins[r][w], kr = sm.kept_rows[r][w];
-            const float bound = kr == total ? inf_f() : __uint_as_float(kb << kKeyShift);
+    // lengths, bounds and the sentinels after each list
+    for (int x = tid; x < QB * 2 * kListPad; x += kBlock) {
+        const int r = x / (2 * kListPad), w = (x / kListPad) & 1, u = x % kListPad;
+        if (r >= nq) continue;
+        const int64_t i = i0 + r;
+        const uint32_t total = (uint32_t)(n - 1);
+        const uint32_t kb = sm.kept_bins[r][w], kr = sm.kept_rows[r][w];
+        const float bound = kr == total ? inf_f() : __uint_as_float(kb << kKeyShift);
+        const float sent = kr == total ? inf_f() : __uint_as_float((kb << kKeyShift) + 1u);
+        if (w == 0) S.l1[i * S.s1 + kr + u] = LEnt{sent, (int32_t)i};
+        else S.l2[i * S.s2 + kr + u] = LEnt2{sent, inf_f(), (int32_t)i};
+        if (u == 0) {
             S.len[2 * i + w] = (int32_t)kr;
             S.bound[2 * i + w] = bound;
         }
@@ -315,23 +320,34 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
 }
 
 // ------------------------------------------------------------------ scan
+// Each list row is followed by kListPad sentinel entries (row = self, d_yz =
+// +inf) whose key distance lies in the bucket that starts at the row's bound:
+// the bound plus one unit in the last place (+inf when nothing was left out).
+// A step of kU <= kListPad entries that starts at or before the list's end
+// then needs no bounds checks, and the last step of a list always ends on a
+// sentinel, whose bucket-floor test (floor = bound >= radius) is exactly the
+// condition under which the list decides the pair.  A sentinel that enters
+// the k-NN list (bound + 1 ulp < k-th distance) leaves a radius above the
+// bound, i.e. an undecided pair, as it should.
 constexpr int kU = 8;   // list entries per step; the next step's are loaded ahead
+static_assert(kU <= kListPad, "a step must stay within the sentinels");
 
 template <int KMAX, int DXM>
 struct Lane {
-    const Job &J;
     const float *xt;
-    int64_t cs;     // xt column stride n * n_est
-    int E, e, i;
+    uint32_t cs;    // xt column stride n * n_est (xt has fewer than 2^31 elements)
+    uint32_t E, e;
+    int dx;
     float xq[DXM];
 
-    __device__ Lane(const Job &j, int i_, int e_) : J(j), i(i_), e(e_) {
+    __device__ Lane(const Job &J, int i, int e_) : e((uint32_t)e_) {
         xt = J.xt;
-        E = J.n_est;
-        cs = (int64_t)J.n * E;
-        Unroll<0, DXM>::upto(J.dx, [&](auto cc) {
+        E = (uint32_t)J.n_est;
+        cs = (uint32_t)J.n * E;
+        dx = J.dx;
+        Unroll<0, DXM>::upto(dx, [&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            xq[c] = xt[c * cs + (int64_t)i * E + e];
+            xq[c] = xt[c * cs + (uint32_t)i * E + e];
         });
     }
 
@@ -339,47 +355,29 @@ struct Lane {
     // step (under the estimate's permutation); all loads issued before use
     template <class Ent>
     __device__ __forceinline__ void xdist(const Ent (&en)[kU], float (&d)[kU]) const {
+        uint32_t o[kU];
         float v[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = xt[(int64_t)en[u].j * E + e];
+        for (int u = 0; u < kU; ++u) {
+            o[u] = (uint32_t)en[u].j * E + e;
+            v[u] = xt[o[u]];
+        }
 #pragma unroll
         for (int u = 0; u < kU; ++u) d[u] = absdiff(xq[0], v[u]);
-        Unroll<1, DXM>::upto(J.dx, [&](auto cc) {
+        Unroll<1, DXM>::upto(dx, [&](auto cc) {
             constexpr int c = decltype(cc)::value;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = xt[c * cs + (int64_t)en[u].j * E + e];
+            for (int u = 0; u < kU; ++u) v[u] = xt[c * cs + o[u]];
 #pragma unroll
             for (int u = 0; u < kU; ++u) d[u] = fmax_(d[u], absdiff(xq[c], v[u]));
         });
     }
 };
 
-// entries [m, m+kU) of a list of length len; past the end: (+inf, self)
-__device__ __forceinline__ void load_step(const LEnt *l, int m, int len, int self, LEnt (&en)[kU]) {
+template <class Ent>
+__device__ __forceinline__ void load_step(const Ent *l, Ent (&en)[kU]) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) en[u] = m + u < len ? l[m + u] : LEnt{inf_f(), self};
-}
-
-__device__ __forceinline__ void load_step(const LEnt2 *l, int m, int len, int self, LEnt2 (&en)[kU]) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) en[u] = m + u < len ? l[m + u] : LEnt2{inf_f(), inf_f(), self};
-}
-
-// key distance of the last listed entry of a step (entries are in bucket order)
-__device__ __forceinline__ float last_d(const LEnt (&en)[kU], int m, int len) {
-    float last = 0.f;
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-        if (m + u < len) last = en[u].d;
-    return last;
-}
-
-__device__ __forceinline__ float last_d(const LEnt2 (&en)[kU], int m, int len) {
-    float last = 0.f;
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-        if (m + u < len) last = en[u].dz;
-    return last;
+    for (int u = 0; u < kU; ++u) en[u] = l[u];
 }
 
 template <int KMAX, int DXM>
@@ -400,42 +398,49 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const int pad_front = KMAX - J.k;
 #pragma unroll
     for (int m = 0; m < KMAX; ++m) top[m] = m < pad_front ? -inf_f() : inf_f();
-    const LEnt *l1 = S.l1 + (int64_t)i * S.m1;
+    const LEnt *l1 = S.l1 + (int64_t)i * S.s1;
     const int len1 = S.len[2 * (int64_t)i];
-    bool done = false;
+    bool decided = false;
     int seen1 = 0, seen2 = 0;     // list entries read (statistics)
     {
         LEnt cur[kU];
-        load_step(l1, 0, len1, i, cur);
-        for (int m = 0; m < len1; m += kU) {
-            seen1 = min(m + kU, len1);
+        load_step(l1, cur);
+        for (int m = 0; m <= len1; m += kU) {
+            seen1 = m + kU;
             LEnt nxt[kU];
-            load_step(l1, m + kU, len1, i, nxt);
-            float dx[kU];
-            ln.xdist(cur, dx);
+            load_step(l1 + m + kU, nxt);
+            float d[kU];
+            ln.xdist(cur, d);
+            float lo = inf_f();
 #pragma unroll
-            for (int u = 0; u < kU; ++u) topk_insert<KMAX>(top, fmax_(dx[u], cur[u].d));
-            if (bucket_floor(last_d(cur, m, len1)) >= top[KMAX - 1]) { done = true; break; }
+            for (int u = 0; u < kU; ++u) {
+                d[u] = fmax_(d[u], cur[u].d);
+                lo = __builtin_fminf(lo, d[u]);
+            }
+            if (lo < top[KMAX - 1]) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) topk_insert<KMAX>(top, d[u]);
+            }
+            if (bucket_floor(cur[kU - 1].d) >= top[KMAX - 1]) { decided = true; break; }
 #pragma unroll
             for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
         }
     }
     const float eps = top[KMAX - 1];
-    bool decided = done || eps <= S.bound[2 * (int64_t)i];
 
     // n_z, n_yz and n_xz from list 2 below eps (every row with d_z < eps, and
     // so every row with d_yz < eps, is listed when eps <= its bound)
     int cxz = 0, cyz = 0, cz = 0;
     if (decided) {
-        const LEnt2 *l2 = S.l2 + (int64_t)i * S.m2;
+        decided = false;
+        const LEnt2 *l2 = S.l2 + (int64_t)i * S.s2;
         const int len2 = S.len[2 * (int64_t)i + 1];
-        bool stop = false;
         LEnt2 cur[kU];
-        load_step(l2, 0, len2, i, cur);
-        for (int m = 0; m < len2; m += kU) {
-            seen2 = min(m + kU, len2);
+        load_step(l2, cur);
+        for (int m = 0; m <= len2; m += kU) {
+            seen2 = m + kU;
             LEnt2 nxt[kU];
-            load_step(l2, m + kU, len2, i, nxt);
+            load_step(l2 + m + kU, nxt);
             float dx[kU];
             ln.xdist(cur, dx);
 #pragma unroll
@@ -444,11 +449,10 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
                 cyz += cur[u].dyz < eps;
                 cxz += fmax_(dx[u], cur[u].dz) < eps;
             }
-            if (bucket_floor(last_d(cur, m, len2)) >= eps) { stop = true; break; }
+            if (bucket_floor(cur[kU - 1].dz) >= eps) { decided = true; break; }
 #pragma unroll
             for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
         }
-        decided = stop || eps <= S.bound[2 * (int64_t)i + 1];
     }
     if (!decided) {
         const uint32_t pos = atomicAdd(&L.counters[0], 1u);

@@ -246,7 +246,8 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
     std::vector<int> gid(specs.size(), -1);
     for (size_t j = 0; j < specs.size(); ++j) {
         const JobSpec &sp = specs[j];
-        if (sp.dz <= 0 || force == 0) continue;
+        // the list kernels index the transposed X columns with 32-bit offsets
+        if (sp.dz <= 0 || force == 0 || (int64_t)sp.dx * sp.n * sp.n_est() >= ((int64_t)1 << 31)) continue;
         std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz};
         for (int c = 0; c < sp.dy + sp.dz; ++c) key.push_back((uintptr_t)sp.cols[sp.dx + c]);
         auto it = groups.emplace(key, (int)group_est.size()).first;
@@ -519,13 +520,16 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.dz = sp.dz;
         S.m1 = std::min(sp.n - 1, cap1);
         S.m2 = std::min(sp.n - 1, cap2);
+        S.s1 = S.m1 + kListPad;
+        S.s2 = S.m2 + kListPad;
         row_off[t + 1] = row_off[t] + sp.n;
         nmax_set = std::max(nmax_set, sp.n);
-        // 8 spare entries after each list array: the scan reads in groups of 4
+        // kListPad spare entries after each array: the scan loads one step
+        // ahead, up to kListPad entries past the last row's sentinels
         o_l1[t] = bytes;
-        bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.m1 + 8), 256);
+        bytes = align_up(bytes + sizeof(LEnt) * ((size_t)sp.n * S.s1 + kListPad), 256);
         o_l2[t] = bytes;
-        bytes = align_up(bytes + sizeof(LEnt2) * ((size_t)sp.n * S.m2 + 8), 256);
+        bytes = align_up(bytes + sizeof(LEnt2) * ((size_t)sp.n * S.s2 + kListPad), 256);
         o_len[t] = bytes;
         bytes = align_up(bytes + sizeof(int32_t) * 2 * (size_t)sp.n, 256);
         o_bound[t] = bytes;
