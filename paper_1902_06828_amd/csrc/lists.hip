@@ -473,16 +473,19 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
 }
 
 // ------------------------------------------------------------------ fallback
-// One block per undecided (row, estimate): every other row, as in the
-// definition.  Each thread keeps the KMAX smallest distances of its rows; k
-// pops of the wave-wide minimum give each wave's k smallest, and the k-th
-// smallest of the four waves' lists is the radius.
+// One block of kFbThreads per undecided (row, estimate): every other row, as
+// in the definition.  Each thread keeps the KMAX smallest distances of its
+// rows; k pops of the wave-wide minimum give each wave's k smallest, and the
+// k-th smallest of the waves' lists is the radius.  Large blocks keep the
+// per-item latency short (the items are few and run side by side).
 constexpr int kFbBatch = 4;
+constexpr int kFbThreads = 1024;
+constexpr int kFbWaves = kFbThreads / 64;
 
 template <int KMAX>
-__global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch L) {
-    __shared__ float wtop[kWaves][KMAX];
-    __shared__ int wcnt[kWaves][3];
+__global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLaunch L) {
+    __shared__ float wtop[kFbWaves][KMAX];
+    __shared__ int wcnt[kFbWaves][3];
     __shared__ float s_eps;
     const int tid = tid_x();
     const int lane = tid & 63;
@@ -501,13 +504,13 @@ __global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch 
         const int64_t cs = (int64_t)n * E;
         const float *const *yc = J.cols + dx;
         const float *const *zc = J.cols + dx + dy;
-        // distances of kFbBatch rows j0, j0 + kBlock, ... (row i and rows past
+        // distances of kFbBatch rows j0, j0 + kFbThreads, ... (row i and rows past
         // the end get +inf in every subspace)
         auto dists = [&](int j0, float (&ax)[kFbBatch], float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
             int jj[kFbBatch];
 #pragma unroll
             for (int u = 0; u < kFbBatch; ++u) {
-                const int j = j0 + u * kBlock;
+                const int j = j0 + u * kFbThreads;
                 jj[u] = j < n ? j : i;
                 ax[u] = ay[u] = az[u] = 0.f;
             }
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch 
         float top[KMAX];
 #pragma unroll
         for (int m = 0; m < KMAX; ++m) top[m] = inf_f();
-        for (int j0 = tid; j0 < n; j0 += kBlock * kFbBatch) {
+        for (int j0 = tid; j0 < n; j0 += kFbThreads * kFbBatch) {
             float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
             dists(j0, ax, ay, az);
 #pragma unroll
@@ -561,12 +564,12 @@ __global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch 
         }
         __syncthreads();
         if (tid == 0) {
-            int pos[kWaves] = {0, 0, 0, 0};
+            int pos[kFbWaves] = {};
             float kth = inf_f();
             for (int t = 0; t < J.k; ++t) {
                 int best = 0;
                 float bv = inf_f();
-                for (int w = 0; w < kWaves; ++w)
+                for (int w = 0; w < kFbWaves; ++w)
                     if (pos[w] < J.k && wtop[w][pos[w]] < bv) { bv = wtop[w][pos[w]]; best = w; }
                 ++pos[best];
                 kth = bv;
@@ -576,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch 
         __syncthreads();
         const float eps = s_eps;
         int cxz = 0, cyz = 0, cz = 0;
-        for (int j0 = tid; j0 < n; j0 += kBlock * kFbBatch) {
+        for (int j0 = tid; j0 < n; j0 += kFbThreads * kFbBatch) {
             float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
             dists(j0, ax, ay, az);
 #pragma unroll
@@ -593,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void list_fallback_kernel(const ListLaunch 
         __syncthreads();
         if (tid == 0) {
             int c3[3] = {0, 0, 0};
-            for (int w = 0; w < kWaves; ++w)
+            for (int w = 0; w < kFbWaves; ++w)
                 for (int t = 0; t < 3; ++t) c3[t] += wcnt[w][t];
             J.eps[(int64_t)e * n + i] = eps;
             for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
@@ -688,7 +691,7 @@ int launch_list_scan(const ListLaunch &L, void *stream) {
 
 int launch_list_fallback(const ListLaunch &L, void *stream) {
     if (L.lanes <= 0) return 0;
-    const dim3 grid((unsigned)L.fb_grid), block(kBlock);
+    const dim3 grid((unsigned)L.fb_grid), block(kFbThreads);
     if (L.kmax == 4) hipLaunchKernelGGL(list_fallback_kernel<4>, grid, block, 0, (hipStream_t)stream, L);
     else if (L.kmax == 8) hipLaunchKernelGGL(list_fallback_kernel<8>, grid, block, 0, (hipStream_t)stream, L);
     else if (L.kmax == 16) hipLaunchKernelGGL(list_fallback_kernel<16>, grid, block, 0, (hipStream_t)stream, L);

@@ -633,7 +633,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.counters = lcounters_.as<uint32_t>();
     L.kmax = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
     L.dxm = dxm <= 1 ? 1 : kMaxDx;
-    L.fb_grid = std::max(1, c.n_cu) * 4;
+    L.fb_grid = std::max(1, c.n_cu);
     if (L.lanes >= ((int64_t)1 << 40) || n_ljobs_ >= (1 << 23)) return fail(MTE_EINVAL, "batch too large");
     n_est_pairs_ = L.lanes;
     MTE_HIP(hipMemcpyAsync(tb, hs, tbytes, hipMemcpyHostToDevice, s));
