@@ -70,6 +70,11 @@ int mte_shutdown(void);
  *            the joint (X,Y,Z) space, distances |fl32(a_i - a_j)|;
  *   counts = strict (< eps_i) neighbour counts in the (X,Z), (Y,Z) and Z
  *            subspaces (N-1 for Z when dz = 0);
+ *   with a Theiler window w (the *_ex calls, mte_opts, mte_request), the rows
+ *   j with |i - j| <= w are left out of row i's neighbours and counts (the
+ *   dynamic correlation exclusion of the section on autocorrelation in real
+ *   data); w = 0 leaves out row i only, and without Z n_z is the number of
+ *   rows outside the window.  Needs N >= k + 1 + 2w;
  *   I      = psi(k) - mean_i[psi(n_xz+1) + psi(n_yz+1) - psi(n_z+1)].
  * The value may be negative (Statistical tests section).  eps and counts are
  * exact; the mean is a float64 sum in a fixed order that does not depend on
@@ -101,6 +106,11 @@ int cmi_ksg_surrogates(const float *X, int dx, const float *Y, int dy, const flo
 int cmi_ksg_diag(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
                  int64_t N, int k, int S, uint64_t seed, uint32_t cand, double *cmi_out,
                  float *eps_out, int32_t *nxz_out, int32_t *nyz_out, int32_t *nz_out);
+/* cmi_ksg_diag with a Theiler window w = theiler >= 0 (cmi_ksg_diag is w = 0). */
+int cmi_ksg_diag_ex(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
+                    int64_t N, int k, int theiler, int S, uint64_t seed, uint32_t cand,
+                    double *cmi_out, float *eps_out, int32_t *nxz_out, int32_t *nyz_out,
+                    int32_t *nz_out);
 
 /*
  * Device-resident forms (asynchronous on `stream`, no host synchronisation).
@@ -115,6 +125,21 @@ int cmi_ksg_dev(const float *dX, int dx, const float *dY, int dy, const float *d
 int cmi_ksg_surrogates_dev(const float *dX, int dx, const float *dY, int dy, const float *dZ,
                            int dz, int64_t N, int64_t ld, int k, int S, uint64_t seed,
                            uint32_t cand, double *d_out, void *stream);
+/* cmi_ksg_surrogates_dev with a Theiler window w = theiler >= 0. */
+int cmi_ksg_surrogates_dev_ex(const float *dX, int dx, const float *dY, int dy, const float *dZ,
+                              int dz, int64_t N, int64_t ld, int k, int theiler, int S,
+                              uint64_t seed, uint32_t cand, double *d_out, void *stream);
+
+/*
+ * Autocorrelation decay time of a series x[T] (host), the heuristic the
+ * paper uses to size the Theiler window (section on autocorrelation in real
+ * data): the shortest lag L >= 1 at which the autocorrelation function has
+ * dropped below 1/e of its zero-lag value, r(L) < r(0)/e, with
+ * r(L) = (1/T) sum_{t<T-L} (x_t - mean)(x_{t+L} - mean) summed in float64 in
+ * time order; max_lag if no lag up to max_lag qualifies.  T >= 2,
+ * max_lag >= 1, x finite (MTE_EINVAL otherwise).
+ */
+int mte_autocorr_decay_time(const float *x, int64_t T, int max_lag, int *act_out);
 
 /*
  * The surrogate permutation pi_{seed,cand,s} of {0..N-1} (host computation of
@@ -157,6 +182,7 @@ typedef struct {
     int S;              /* surrogates per candidate test (default 200) */
     int max_lag_target; /* target-past candidate lags 1..max_lag_target (default 5) */
     uint64_t seed;      /* surrogate key seed (default 0) */
+    int theiler;        /* Theiler window of every estimate (default 0) */
 } mte_opts;
 
 typedef struct {
@@ -220,6 +246,7 @@ typedef struct {
     int S;                    /* surrogates (>= 0) */
     uint64_t seed;            /* surrogate keys pi_{seed,cand,s} */
     uint32_t cand;
+    int theiler;              /* Theiler window (>= 0) */
 } mte_request;
 
 /* Queue a request without blocking; copies nodes and lags. */

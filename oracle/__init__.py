@@ -6,13 +6,15 @@ CPU baseline do.  It shares no code with the HIP library: it re-derives every
 step from the paper and from the estimator definition the paper cites.
 
 Modules
-  ksg     brute-force KSG CMI estimator (numpy, float32 subtraction, float64 sums)
-  perm    keyed surrogate permutation (SplitMix64 + Feistel cycle walking)
+  ksg     brute-force KSG CMI estimator (numpy, float32 subtraction, float64 sums),
+          with an optional Theiler window
+  perm    keyed surrogate permutation (swap-or-not shuffle keyed by SplitMix64)
   stats   maximum-statistic, minimum-statistic and omnibus tests
+  act     autocorrelation decay time (the Theiler window heuristic)
   greedy  the four-step greedy multivariate TE inference for one target
   cksg    ctypes loader for ksg_oracle.c, the same brute force in plain C (timed)
 
-Parity status: ksg, perm and stats are pinned by tests/test_oracle_*.py against
+Parity status: ksg, perm, stats and act are pinned by tests/test_oracle_*.py against
 closed forms, hand-counted cases, invariances and published generator outputs.
 greedy's selections on real data are pinned only statistically (recovery of
 known parents, no selection on independent data): beyond that, parity

@@ -34,7 +34,7 @@ def lib():
         f = L.oracle_ksg
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
-                      ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                       ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_max_threads.restype = ctypes.c_int
@@ -46,7 +46,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def eps_and_counts(x, y, z, k: int, queries=None, threads: int = 0):
+def eps_and_counts(x, y, z, k: int, queries=None, threads: int = 0, theiler: int = 0):
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
     x = x[None, :] if x.ndim == 1 else x
@@ -61,7 +61,7 @@ def eps_and_counts(x, y, z, k: int, queries=None, threads: int = 0):
     eps = np.empty(m, np.float32)
     cx, cy, cz = (np.empty(m, np.int32) for _ in range(3))
     cmi = ctypes.c_double(0.0)
-    rc = lib().oracle_ksg(_ptr(x), x.shape[0], _ptr(y), y.shape[0], _ptr(z), dz, n, k, threads,
+    rc = lib().oracle_ksg(_ptr(x), x.shape[0], _ptr(y), y.shape[0], _ptr(z), dz, n, k, theiler, threads,
                           _ptr(q), m, _ptr(eps), _ptr(cx), _ptr(cy), _ptr(cz),
                           ctypes.byref(cmi))
     if rc != 0:
@@ -69,8 +69,8 @@ def eps_and_counts(x, y, z, k: int, queries=None, threads: int = 0):
     return eps, cx, cy, cz, (cmi.value if q is None else None)
 
 
-def cmi_ksg(x, y, z, k: int = 4, threads: int = 0):
-    return eps_and_counts(x, y, z, k, None, threads)[4]
+def cmi_ksg(x, y, z, k: int = 4, threads: int = 0, theiler: int = 0):
+    return eps_and_counts(x, y, z, k, None, threads, theiler)[4]
 
 
 def max_threads() -> int:

@@ -77,13 +77,13 @@ class _Run:
         return real, surr
 
 
-def _numpy_estimator(x, y, z, k):
-    return ksg.cmi_ksg(x, y, z, k)
+def _numpy_estimator(x, y, z, k, theiler=0):
+    return ksg.cmi_ksg(x, y, z, k, theiler=theiler)
 
 
 def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
                    max_lag_target: int = 5, alpha: float = 0.05, k: int = 4,
-                   n_surr: int = 200, seed: int = 0, estimator=None):
+                   n_surr: int = 200, seed: int = 0, estimator=None, theiler: int = 0):
     series = np.asarray(series)
     if series.dtype != np.float32:
         raise TypeError("series must be float32")
@@ -91,7 +91,9 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
     if target in candidates:
         raise ValueError("target among candidates")
     l_m = max(max_lag_target, max_lag_sources)
-    run = _Run(series, target, k, n_surr, seed, l_m, estimator or _numpy_estimator)
+    est = estimator or _numpy_estimator
+    run = _Run(series, target, k, n_surr, seed, l_m,
+               (lambda x, y, z, kk: est(x, y, z, kk, theiler=theiler)) if theiler else est)
 
     # Step 1: target past
     ycand = [(target, lag) for lag in range(1, max_lag_target + 1)]

@@ -10,9 +10,12 @@ prints no formula.  This module writes out that cited definition:
      round to nearest even, denormals kept; the absolute value is exact.
   3. Subspace max-norms d_X, d_Y, d_Z (maxima over that subspace's columns;
      d_Z = 0 when there is no conditioning set) and d = max(d_X, d_Y, d_Z).
-  4. eps_i = k-th smallest of the multiset {d(i,j) : j != i}.
-  5. Strict counts n_xz(i) = #{j != i : max(d_X, d_Z) < eps_i}, n_yz likewise,
-     n_z(i) = #{j != i : d_Z < eps_i} (= N-1 when dz = 0).
+  4. eps_i = k-th smallest of the multiset {d(i,j) : j in R_i}, where R_i is
+     the set of rows outside row i's Theiler window: |i - j| > w (the paper's
+     dynamic correlation exclusion, section on autocorrelation in real data;
+     w = 0 leaves R_i = {j != i}).
+  5. Strict counts n_xz(i) = #{j in R_i : max(d_X, d_Z) < eps_i}, n_yz
+     likewise, n_z(i) = #{j in R_i : d_Z < eps_i} (= |R_i| when dz = 0).
   6. I = psi(k) - (1/N) sum_i [psi(n_xz+1) + psi(n_yz+1) - psi(n_z+1)] in nats,
      float64, with scipy's digamma and an exactly rounded sum (math.fsum).
      Negative values are returned as they are (Statistical tests section: the
@@ -54,16 +57,19 @@ def subspace_dist(cols: np.ndarray, qidx: np.ndarray) -> np.ndarray:
     return out
 
 
-def eps_and_counts(x, y, z, k: int, queries=None, block: int = 256):
-    """Steps 1-5 for the given query indices (all by default).
+def eps_and_counts(x, y, z, k: int, queries=None, block: int = 256, theiler: int = 0):
+    """Steps 1-5 for the given query indices (all by default), with Theiler
+    window w = theiler.
 
     Returns (eps float32, n_xz int64, n_yz int64, n_z int64), one entry per query.
     """
     x = np.asarray(x)
     n = x.shape[-1]
     X, Y, Z = _cols(x, n), _cols(y, n), _cols(z, n)
-    if not (1 <= k <= n - 1):
-        raise ValueError("need 1 <= k <= N-1")
+    if theiler < 0:
+        raise ValueError("Theiler window must be >= 0")
+    if not (1 <= k <= n - 1 - 2 * theiler):
+        raise ValueError("need 1 <= k <= N-1-2w")
     qs = np.arange(n) if queries is None else np.asarray(queries, dtype=np.int64)
     eps = np.empty(len(qs), dtype=np.float32)
     nxz = np.empty(len(qs), dtype=np.int64)
@@ -75,9 +81,8 @@ def eps_and_counts(x, y, z, k: int, queries=None, block: int = 256):
         dy = subspace_dist(Y, q)
         dz = subspace_dist(Z, q)
         d = np.maximum(np.maximum(dx, dy), dz)
-        rows = np.arange(len(q))
-        self_mask = np.zeros_like(d, dtype=bool)
-        self_mask[rows, q] = True
+        # rows inside row q's Theiler window (q itself when w = 0)
+        self_mask = np.abs(q[:, None] - np.arange(n)[None, :]) <= theiler
         d_noself = np.where(self_mask, np.float32(np.inf), d)
         e = np.partition(d_noself, k - 1, axis=1)[:, k - 1]
         eps[b0:b0 + len(q)] = e
@@ -85,7 +90,7 @@ def eps_and_counts(x, y, z, k: int, queries=None, block: int = 256):
         nxz[b0:b0 + len(q)] = ((np.maximum(dx, dz) < et) & ~self_mask).sum(1)
         nyz[b0:b0 + len(q)] = ((np.maximum(dy, dz) < et) & ~self_mask).sum(1)
         if Z.shape[0] == 0:
-            nz[b0:b0 + len(q)] = n - 1
+            nz[b0:b0 + len(q)] = (~self_mask).sum(1)
         else:
             nz[b0:b0 + len(q)] = ((dz < et) & ~self_mask).sum(1)
     return eps, nxz, nyz, nz
@@ -100,10 +105,10 @@ def cmi_from_counts(k: int, nxz, nyz, nz) -> float:
     return float(digamma(float(k)) - math.fsum(terms.tolist()) / len(terms))
 
 
-def cmi_ksg(x, y, z, k: int = 4, diag: bool = False):
+def cmi_ksg(x, y, z, k: int = 4, diag: bool = False, theiler: int = 0):
     """I(X;Y|Z) in nats.  x, y: float32 [dx][N], [dy][N]; z: float32 [dz][N] or
     None.  With diag=True also returns (eps, n_xz, n_yz, n_z)."""
-    eps, nxz, nyz, nz = eps_and_counts(x, y, z, k)
+    eps, nxz, nyz, nz = eps_and_counts(x, y, z, k, theiler=theiler)
     val = cmi_from_counts(k, nxz, nyz, nz)
     if diag:
         return val, (eps, nxz, nyz, nz)

@@ -7,7 +7,8 @@
  * It computes exactly what oracle/ksg.py computes (the estimator the paper
  * cites in its CLM section, written out there), by the same definition:
  *   d(i,j) = max over all columns of |fl32(a_i - a_j)| (subspace maxima for
- *   the counts), eps_i = k-th smallest d(i,j) over j != i, strict counts
+ *   the counts), eps_i = k-th smallest d(i,j) over the rows j outside row i's
+ *   Theiler window |i - j| <= w (w = 0: j != i), strict counts over the same rows
  *   n_xz, n_yz, n_z, and I = psi(k) - mean_i[psi(n_xz+1)+psi(n_yz+1)-psi(n_z+1)]
  *   with psi(m+1) + gamma = H_m, the harmonic number, so that
  *   I = H_{k-1} - (1/N) sum_i (H_{n_xz} + H_{n_yz} - H_{n_z}).
@@ -34,12 +35,12 @@ static float group_dist(const float *cols, int d, long n, long i, long j)
 
 /* eps and strict counts for one query i. */
 static void one_query(const float *X, int dx, const float *Y, int dy,
-                      const float *Z, int dz, long n, int k, long i,
+                      const float *Z, int dz, long n, int k, long w, long i,
                       float *top, float *eps, int *nxz, int *nyz, int *nz)
 {
     for (int m = 0; m < k; ++m) top[m] = INFINITY;
     for (long j = 0; j < n; ++j) {
-        if (j == i) continue;
+        if (labs(j - i) <= w) continue;
         float a = group_dist(X, dx, n, i, j);
         float b = group_dist(Y, dy, n, i, j);
         float c = group_dist(Z, dz, n, i, j);
@@ -52,9 +53,10 @@ static void one_query(const float *X, int dx, const float *Y, int dy,
         }
     }
     float e = top[k - 1];
-    int cx = 0, cy = 0, cz = 0;
+    int cx = 0, cy = 0, cz = 0, valid = 0;
     for (long j = 0; j < n; ++j) {
-        if (j == i) continue;
+        if (labs(j - i) <= w) continue;
+        ++valid;
         float a = group_dist(X, dx, n, i, j);
         float b = group_dist(Y, dy, n, i, j);
         float c = group_dist(Z, dz, n, i, j);
@@ -64,20 +66,22 @@ static void one_query(const float *X, int dx, const float *Y, int dy,
         if (bc < e) ++cy;
         if (c < e) ++cz;
     }
-    if (dz == 0) cz = (int)(n - 1);
+    if (dz == 0) cz = valid;
     *eps = e; *nxz = cx; *nyz = cy; *nz = cz;
 }
 
 /*
- * X, Y, Z: column-major sample matrices [d][n] (Z may be NULL when dz == 0).
+ * X, Y, Z: column-major sample matrices [d][n] (Z may be NULL when dz == 0);
+ * theiler: Theiler window w >= 0.
  * queries: NULL for all rows (then *cmi_out is written), else nq row indices.
  * Outputs per query: eps, nxz, nyz, nz.  Returns 0, or -1 on bad arguments.
  */
 int oracle_ksg(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
-               long n, int k, int nthreads, const long *queries, long nq,
+               long n, int k, int theiler, int nthreads, const long *queries, long nq,
                float *eps, int *nxz, int *nyz, int *nz, double *cmi_out)
 {
-    if (!X || !Y || dx < 1 || dy < 1 || dz < 0 || (dz > 0 && !Z) || k < 1 || n < k + 1)
+    if (!X || !Y || dx < 1 || dy < 1 || dz < 0 || (dz > 0 && !Z) || k < 1 || theiler < 0 ||
+        n < k + 1 + 2 * (long)theiler)
         return -1;
     long total = queries ? nq : n;
 #ifdef _OPENMP
@@ -91,7 +95,7 @@ int oracle_ksg(const float *X, int dx, const float *Y, int dy, const float *Z, i
 #pragma omp for schedule(dynamic, 16)
         for (long q = 0; q < total; ++q) {
             long i = queries ? queries[q] : q;
-            one_query(X, dx, Y, dy, Z, dz, n, k, i, top, &eps[q], &nxz[q], &nyz[q], &nz[q]);
+            one_query(X, dx, Y, dy, Z, dz, n, k, theiler, i, top, &eps[q], &nxz[q], &nyz[q], &nz[q]);
         }
         free(top);
     }

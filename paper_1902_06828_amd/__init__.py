@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     cmi_ksg_surrogates,
     cmi_ksg_surrogates_dev,
     lib,
+    mte_autocorr_decay_time,
     mte_init,
     mte_kernel_timing,
     mte_kernel_timing_read,

@@ -28,7 +28,7 @@ class MteError(RuntimeError):
 
 class mte_opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("S", ctypes.c_int), ("max_lag_target", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int)]
 
 
 class mte_var(ctypes.Structure):
@@ -48,7 +48,7 @@ class mte_request(ctypes.Structure):
     _fields_ = [("sid", ctypes.c_int32), ("dx", ctypes.c_int), ("dy", ctypes.c_int), ("dz", ctypes.c_int),
                 ("nodes", ctypes.POINTER(ctypes.c_int32)), ("lags", ctypes.POINTER(ctypes.c_int32)),
                 ("t0", ctypes.c_int64), ("N", ctypes.c_int64), ("k", ctypes.c_int), ("S", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("cand", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint64), ("cand", ctypes.c_uint32), ("theiler", ctypes.c_int)]
 
 
 class mte_serve_stats(ctypes.Structure):
@@ -75,8 +75,11 @@ SIGNATURES = {
     "cmi_ksg": [_P, _I, _P, _I, _P, _I, _I64, _I, _P],
     "cmi_ksg_surrogates": [_P, _I, _P, _I, _P, _I, _I64, _I, _I, _U64, _P, _P],
     "cmi_ksg_diag": [_P, _I, _P, _I, _P, _I, _I64, _I, _I, _U64, _U32, _P, _P, _P, _P, _P],
+    "cmi_ksg_diag_ex": [_P, _I, _P, _I, _P, _I, _I64, _I, _I, _I, _U64, _U32, _P, _P, _P, _P, _P],
     "cmi_ksg_dev": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _P, _P],
     "cmi_ksg_surrogates_dev": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _U64, _U32, _P, _P],
+    "cmi_ksg_surrogates_dev_ex": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _I, _U64, _U32, _P, _P],
+    "mte_autocorr_decay_time": [_P, _I64, _I, _P],
     "mte_permutation": [_U64, _U32, _U32, _I64, _P],
     "mte_max_statistic": [_P, _P, _I, _I, _D, _P, _P, _P],
     "mte_min_statistic": [_P, _P, _I, _I, _D, _P, _P, _P],
@@ -179,16 +182,28 @@ def cmi_ksg_surrogates(X, Y, Z=None, k: int = 4, S: int = 200, seed: int = 0):
     return out.value, surr
 
 
-def cmi_ksg_diag(X, Y, Z=None, k: int = 4, S: int = 0, seed: int = 0, cand: int = 0):
+def cmi_ksg_diag(X, Y, Z=None, k: int = 4, S: int = 0, seed: int = 0, cand: int = 0, theiler: int = 0):
     """Returns (cmi[1+S], eps[1+S][N], n_xz, n_yz, n_z) (counts int32 [1+S][N])."""
     X, dx, Y, dy, Z, dz, n = _xyz(X, Y, Z)
     E = S + 1
     cmi = np.empty(E, np.float64)
     eps = np.empty((E, n), np.float32)
     cx, cy, cz = (np.empty((E, n), np.int32) for _ in range(3))
-    _check(lib().cmi_ksg_diag(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, k, S, seed, cand, _ptr(cmi),
-                              _ptr(eps), _ptr(cx), _ptr(cy), _ptr(cz)))
+    if theiler:
+        _check(lib().cmi_ksg_diag_ex(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, k, theiler, S, seed, cand,
+                                     _ptr(cmi), _ptr(eps), _ptr(cx), _ptr(cy), _ptr(cz)))
+    else:
+        _check(lib().cmi_ksg_diag(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, k, S, seed, cand, _ptr(cmi),
+                                  _ptr(eps), _ptr(cx), _ptr(cy), _ptr(cz)))
     return cmi, eps, cx, cy, cz
+
+
+def mte_autocorr_decay_time(x, max_lag: int) -> int:
+    """Autocorrelation decay time of a float32 series (Theiler window heuristic)."""
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    out = ctypes.c_int()
+    _check(lib().mte_autocorr_decay_time(_ptr(x), len(x), max_lag, ctypes.byref(out)))
+    return out.value
 
 
 def _stream_ptr(stream):
@@ -205,7 +220,7 @@ def cmi_ksg_dev(X, Y, Z, k: int, out, stream=None) -> None:
 
 
 def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, stream=None,
-                           n: int | None = None) -> None:
+                           n: int | None = None, theiler: int = 0) -> None:
     """Device-resident estimate and S surrogates into out[0..S] (float64 CUDA
     tensor), asynchronous on `stream` (torch's current stream by default)."""
     import torch
@@ -227,10 +242,10 @@ def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, s
         raise ValueError("X, Y and Z must share the leading dimension")
     if any(t is not None and t.shape[1] < rows for t in (X, Y, Z)) or rows > ld:
         raise ValueError("fewer columns than rows requested")
-    _check(lib().cmi_ksg_surrogates_dev(
+    _check(lib().cmi_ksg_surrogates_dev_ex(
         ctypes.c_void_p(X.data_ptr()), X.shape[0], ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
         None if Z is None else ctypes.c_void_p(Z.data_ptr()), 0 if Z is None else Z.shape[0],
-        rows, ld, k, S, seed, cand, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        rows, ld, k, theiler, S, seed, cand, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
 
 
 def mte_permutation(seed: int, cand: int, s: int, n: int) -> np.ndarray:
@@ -279,12 +294,12 @@ def _result_dict(res, tp, src):
     }
 
 
-def _opts(k, S, max_lag_target, seed):
-    return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed)
+def _opts(k, S, max_lag_target, seed, theiler=0):
+    return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed, theiler=theiler)
 
 
 def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, alpha: float = 0.05,
-                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0):
+                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0):
     data = np.ascontiguousarray(data)
     if data.dtype != np.float32 or data.ndim != 2:
         raise TypeError("data must be float32 [P][T]")
@@ -292,7 +307,7 @@ def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, 
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed)
+    o = _opts(k, S, max_lag_target, seed, theiler)
     _check(lib().mte_select_sources(_ptr(data), data.shape[0], data.shape[1], target, _ptr(cands),
                                     len(cands), max_lag_sources, alpha, ctypes.byref(o),
                                     ctypes.byref(res)))
@@ -301,12 +316,12 @@ def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, 
 
 def mte_select_sources_sid(sid: int, target: int, candidates, max_lag_sources: int = 5,
                            alpha: float = 0.05, k: int = 4, S: int = 200, max_lag_target: int = 5,
-                           seed: int = 0):
+                           seed: int = 0, theiler: int = 0):
     cands = np.ascontiguousarray(candidates, dtype=np.int32)
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed)
+    o = _opts(k, S, max_lag_target, seed, theiler)
     _check(lib().mte_select_sources_sid(sid, target, _ptr(cands), len(cands), max_lag_sources, alpha,
                                         ctypes.byref(o), ctypes.byref(res)))
     return _result_dict(res, tp, src)
@@ -327,7 +342,7 @@ def mte_series_release(sid: int) -> None:
 
 
 def mte_submit(sid: int, nodes, lags, dx: int, dy: int, dz: int, t0: int, n: int, k: int = 4,
-               S: int = 0, seed: int = 0, cand: int = 0) -> int:
+               S: int = 0, seed: int = 0, cand: int = 0, theiler: int = 0) -> int:
     nodes = np.ascontiguousarray(nodes, dtype=np.int32)
     lags = np.ascontiguousarray(lags, dtype=np.int32)
     if len(nodes) != dx + dy + dz or len(lags) != len(nodes):
@@ -335,7 +350,7 @@ def mte_submit(sid: int, nodes, lags, dx: int, dy: int, dz: int, t0: int, n: int
     req = mte_request(sid=sid, dx=dx, dy=dy, dz=dz,
                       nodes=nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                       lags=lags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                      t0=t0, N=n, k=k, S=S, seed=seed, cand=cand)
+                      t0=t0, N=n, k=k, S=S, seed=seed, cand=cand, theiler=theiler)
     ticket = ctypes.c_uint64()
     _check(lib().mte_submit(ctypes.byref(req), ctypes.byref(ticket)))
     return ticket.value

@@ -71,10 +71,11 @@ static void fill_keys(JobSpec &sp, int S, uint64_t seed, uint32_t cand) {
 
 // Host-buffer estimate with S surrogates; optional diagnostics.
 static int host_estimate(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
-                         int64_t N, int k, int S, uint64_t seed, uint32_t cand, double *cmi_out,
-                         float *eps_out, int32_t *nxz, int32_t *nyz, int32_t *nz) {
+                         int64_t N, int k, int theiler, int S, uint64_t seed, uint32_t cand,
+                         double *cmi_out, float *eps_out, int32_t *nxz, int32_t *nyz, int32_t *nz) {
     int rc;
     if ((rc = validate_dims(dx, dy, dz, N, k))) return rc;
+    if ((rc = validate_theiler(N, k, theiler))) return rc;
     if (S < 0) return fail(MTE_EINVAL, "S=%d must be >= 0", S);
     if (!X || !Y || (dz > 0 && !Z) || !cmi_out) return fail(MTE_EINVAL, "null pointer argument");
     if (dz == 0 && Z) return fail(MTE_EINVAL, "Z must be NULL when dz == 0");
@@ -100,7 +101,7 @@ static int host_estimate(const float *X, int dx, const float *Y, int dy, const f
     if (dz) MTE_HIP(hipMemcpyAsync(d + (size_t)(dx + dy) * N, Z, sizeof(float) * dz * N, hipMemcpyHostToDevice, s));
     JobSpec sp;
     for (int c = 0; c < dx + dy + dz; ++c) sp.cols[c] = d + (size_t)c * N;
-    sp.n = (int)N; sp.dx = dx; sp.dy = dy; sp.dz = dz; sp.k = k;
+    sp.n = (int)N; sp.dx = dx; sp.dy = dy; sp.dz = dz; sp.k = k; sp.theiler = theiler;
     fill_keys(sp, S, seed, cand);
     sp.out = out.as<double>();
     if (diag) {
@@ -134,13 +135,14 @@ struct DevKey {
     const float *x, *y, *z;
     int dx, dy, dz;
     int64_t n, ld;
-    int k, S;
+    int k, theiler, S;
     uint64_t seed;
     uint32_t cand;
     double *out;
     bool operator==(const DevKey &o) const {
-        return std::tie(x, y, z, dx, dy, dz, n, ld, k, S, seed, cand, out) ==
-               std::tie(o.x, o.y, o.z, o.dx, o.dy, o.dz, o.n, o.ld, o.k, o.S, o.seed, o.cand, o.out);
+        return std::tie(x, y, z, dx, dy, dz, n, ld, k, theiler, S, seed, cand, out) ==
+               std::tie(o.x, o.y, o.z, o.dx, o.dy, o.dz, o.n, o.ld, o.k, o.theiler, o.S, o.seed, o.cand,
+                        o.out);
     }
 };
 
@@ -151,21 +153,25 @@ struct DevEntry {
 
 static std::mutex g_dev_mu;
 // most recent first; never destroyed, so no HIP call runs during static
-// destruction at exit (mte_shutdown clears it)
+// destruction at exit (mte_shutdown clears it).  Bounded in entries and in
+// the device memory the cached launches hold.
 static std::list<DevEntry> &g_dev_cache = *new std::list<DevEntry>;
+static size_t g_dev_bytes = 0;
 static constexpr size_t kDevCacheMax = 512;
+static constexpr size_t kDevCacheBytes = (size_t)16 << 30;
 
 static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz,
-                        int64_t N, int64_t ld, int k, int S, uint64_t seed, uint32_t cand,
+                        int64_t N, int64_t ld, int k, int theiler, int S, uint64_t seed, uint32_t cand,
                         double *d_out, void *stream) {
     int rc;
     if ((rc = validate_dims(dx, dy, dz, N, k))) return rc;
+    if ((rc = validate_theiler(N, k, theiler))) return rc;
     if (S < 0) return fail(MTE_EINVAL, "S=%d must be >= 0", S);
     if (!dX || !dY || (dz > 0 && !dZ) || !d_out) return fail(MTE_EINVAL, "null pointer argument");
     if (ld < N) return fail(MTE_EINVAL, "ld=%lld < N", (long long)ld);
     if ((rc = ensure_init())) return rc;
     hipStream_t s = (hipStream_t)stream;
-    DevKey key{dX, dY, dZ, dx, dy, dz, N, ld, k, S, seed, cand, d_out};
+    DevKey key{dX, dY, dZ, dx, dy, dz, N, ld, k, theiler, S, seed, cand, d_out};
     std::lock_guard<std::mutex> lk(g_dev_mu);
     for (auto it = g_dev_cache.begin(); it != g_dev_cache.end(); ++it) {
         if (it->key == key) {
@@ -177,7 +183,7 @@ static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const 
     for (int c = 0; c < dx; ++c) sp.cols[c] = dX + (size_t)c * ld;
     for (int c = 0; c < dy; ++c) sp.cols[dx + c] = dY + (size_t)c * ld;
     for (int c = 0; c < dz; ++c) sp.cols[dx + dy + c] = dZ + (size_t)c * ld;
-    sp.n = (int)N; sp.dx = dx; sp.dy = dy; sp.dz = dz; sp.k = k;
+    sp.n = (int)N; sp.dx = dx; sp.dy = dy; sp.dz = dz; sp.k = k; sp.theiler = theiler;
     fill_keys(sp, S, seed, cand);
     sp.out = d_out;
     std::vector<JobSpec> specs{sp};
@@ -185,10 +191,15 @@ static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const 
     if ((rc = choose_tiles(specs, s, true, &tc))) return rc;
     auto b = std::make_unique<Batch>();
     if ((rc = b->prepare(specs, tc, s))) return rc;
+    g_dev_bytes += b->device_bytes();
     g_dev_cache.push_front(DevEntry{key, std::move(b)});
-    if (g_dev_cache.size() > kDevCacheMax) {
+    if (g_dev_cache.size() > kDevCacheMax || (g_dev_bytes > kDevCacheBytes && g_dev_cache.size() > 1)) {
+        // the evicted launches may still be queued on some stream
         MTE_HIP(hipDeviceSynchronize());
-        g_dev_cache.pop_back();
+        while (g_dev_cache.size() > 1 && (g_dev_cache.size() > kDevCacheMax || g_dev_bytes > kDevCacheBytes)) {
+            g_dev_bytes -= g_dev_cache.back().batch->device_bytes();
+            g_dev_cache.pop_back();
+        }
     }
     return g_dev_cache.front().batch->enqueue(s, true);
 }
@@ -196,6 +207,7 @@ static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const 
 void clear_dev_cache() {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_dev_cache.clear();
+    g_dev_bytes = 0;
 }
 
 }  // namespace mte
@@ -206,7 +218,7 @@ extern "C" {
 
 const char *mte_last_error(void) { return mte::last_error(); }
 
-int mte_abi_version(void) { return 1; }
+int mte_abi_version(void) { return 2; }
 
 int mte_init(int device, size_t hbm_budget_bytes) { return init_device(device, hbm_budget_bytes); }
 
@@ -218,7 +230,7 @@ int mte_shutdown(void) {
 
 int cmi_ksg(const float *X, int dx, const float *Y, int dy, const float *Z, int dz, int64_t N, int k,
             double *cmi_out) {
-    return host_estimate(X, dx, Y, dy, Z, dz, N, k, 0, 0, 0, cmi_out, nullptr, nullptr, nullptr, nullptr);
+    return host_estimate(X, dx, Y, dy, Z, dz, N, k, 0, 0, 0, 0, cmi_out, nullptr, nullptr, nullptr, nullptr);
 }
 
 int cmi_ksg_surrogates(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
@@ -226,7 +238,7 @@ int cmi_ksg_surrogates(const float *X, int dx, const float *Y, int dy, const flo
     if (S < 1) return fail(MTE_EINVAL, "S=%d must be >= 1", S);
     if (!surr_out || !cmi_out) return fail(MTE_EINVAL, "null output pointer");
     std::vector<double> all((size_t)S + 1);
-    int rc = host_estimate(X, dx, Y, dy, Z, dz, N, k, S, seed, 0, all.data(), nullptr, nullptr,
+    int rc = host_estimate(X, dx, Y, dy, Z, dz, N, k, 0, S, seed, 0, all.data(), nullptr, nullptr,
                            nullptr, nullptr);
     if (rc) return rc;
     *cmi_out = all[0];
@@ -237,20 +249,42 @@ int cmi_ksg_surrogates(const float *X, int dx, const float *Y, int dy, const flo
 int cmi_ksg_diag(const float *X, int dx, const float *Y, int dy, const float *Z, int dz, int64_t N,
                  int k, int S, uint64_t seed, uint32_t cand, double *cmi_out, float *eps_out,
                  int32_t *nxz_out, int32_t *nyz_out, int32_t *nz_out) {
+    return cmi_ksg_diag_ex(X, dx, Y, dy, Z, dz, N, k, 0, S, seed, cand, cmi_out, eps_out, nxz_out, nyz_out,
+                           nz_out);
+}
+
+int cmi_ksg_diag_ex(const float *X, int dx, const float *Y, int dy, const float *Z, int dz, int64_t N,
+                    int k, int theiler, int S, uint64_t seed, uint32_t cand, double *cmi_out,
+                    float *eps_out, int32_t *nxz_out, int32_t *nyz_out, int32_t *nz_out) {
     if (!eps_out || !nxz_out || !nyz_out || !nz_out) return fail(MTE_EINVAL, "null output pointer");
-    return host_estimate(X, dx, Y, dy, Z, dz, N, k, S, seed, cand, cmi_out, eps_out, nxz_out,
+    return host_estimate(X, dx, Y, dy, Z, dz, N, k, theiler, S, seed, cand, cmi_out, eps_out, nxz_out,
                          nyz_out, nz_out);
 }
 
 int cmi_ksg_dev(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz, int64_t N,
                 int64_t ld, int k, double *d_out, void *stream) {
-    return dev_estimate(dX, dx, dY, dy, dZ, dz, N, ld, k, 0, 0, 0, d_out, stream);
+    return dev_estimate(dX, dx, dY, dy, dZ, dz, N, ld, k, 0, 0, 0, 0, d_out, stream);
 }
 
 int cmi_ksg_surrogates_dev(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz,
                            int64_t N, int64_t ld, int k, int S, uint64_t seed, uint32_t cand,
                            double *d_out, void *stream) {
-    return dev_estimate(dX, dx, dY, dy, dZ, dz, N, ld, k, S, seed, cand, d_out, stream);
+    return dev_estimate(dX, dx, dY, dy, dZ, dz, N, ld, k, 0, S, seed, cand, d_out, stream);
+}
+
+int cmi_ksg_surrogates_dev_ex(const float *dX, int dx, const float *dY, int dy, const float *dZ, int dz,
+                              int64_t N, int64_t ld, int k, int theiler, int S, uint64_t seed,
+                              uint32_t cand, double *d_out, void *stream) {
+    return dev_estimate(dX, dx, dY, dy, dZ, dz, N, ld, k, theiler, S, seed, cand, d_out, stream);
+}
+
+int mte_autocorr_decay_time(const float *x, int64_t T, int max_lag, int *act_out) {
+    if (!x || !act_out) return fail(MTE_EINVAL, "null pointer argument");
+    if (T < 2 || max_lag < 1) return fail(MTE_EINVAL, "need T >= 2 and max_lag >= 1");
+    int rc;
+    if ((rc = validate_host_finite(x, T, "x"))) return rc;
+    *act_out = autocorr_decay_time(x, T, max_lag);
+    return MTE_OK;
 }
 
 int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_t *out) {

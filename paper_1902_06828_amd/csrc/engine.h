@@ -63,6 +63,7 @@ struct Job {
     // hold the per-row radii and counts ([n_est][n], [n_est][3][n]).
     int set;
     float *xt;
+    int theiler;                  // Theiler window w: pairs with |i - j| <= w are left out
 };
 
 // Neighbour lists of one (Y, Z) sample, shared by every job of a launch whose
@@ -91,6 +92,7 @@ constexpr int kListPad = 8;                   // sentinel entries after each row
 struct ListSet {
     const float *cols[kMaxDy + kMaxDz];   // Y columns, then Z columns
     int n, dy, dz;
+    int theiler;                  // Theiler window of the rows (|i - j| <= w left out)
     int m1, m2;                   // list capacities per row
     int s1, s2;                   // row strides: capacity + kListPad sentinels
     LEnt *l1;                     // [n][s1]  (Y,Z) list

@@ -96,8 +96,8 @@ public:
 class DirectExec : public RoundExec {
 public:
     DirectExec(const float *dev_series, int64_t T, int l_m, int64_t N, int target, int k, int S,
-               uint64_t seed)
-        : d_(dev_series), T_(T), lm_(l_m), N_(N), target_(target), k_(k), S_(S), seed_(seed) {}
+               uint64_t seed, int theiler)
+        : d_(dev_series), T_(T), lm_(l_m), N_(N), target_(target), k_(k), S_(S), w_(theiler), seed_(seed) {}
     int run(const Round &r, uint32_t tid0, std::vector<double> *real, std::vector<double> *surr) override {
         const int n = (int)r.xs.size();
         const int E = S_ + 1;
@@ -115,6 +115,7 @@ public:
             sp.dy = 1;
             sp.dz = (int)r.zs[j].size();
             sp.k = k_;
+            sp.theiler = w_;
             sp.keys.resize((size_t)E);
             sp.keys[0] = EstKey{0, 1, 0};
             for (int s = 0; s < S_; ++s)
@@ -151,7 +152,7 @@ private:
     int64_t T_;
     int lm_;
     int64_t N_;
-    int target_, k_, S_;
+    int target_, k_, S_, w_;
     uint64_t seed_;
     DevBuf out_;
     hipStream_t s_ = nullptr;
@@ -160,8 +161,8 @@ private:
 // Served executor: every candidate test is one request of the request loop.
 class ServedExec : public RoundExec {
 public:
-    ServedExec(int32_t sid, int l_m, int64_t N, int target, int k, int S, uint64_t seed)
-        : sid_(sid), lm_(l_m), N_(N), target_(target), k_(k), S_(S), seed_(seed) {}
+    ServedExec(int32_t sid, int l_m, int64_t N, int target, int k, int S, uint64_t seed, int theiler)
+        : sid_(sid), lm_(l_m), N_(N), target_(target), k_(k), S_(S), w_(theiler), seed_(seed) {}
     int run(const Round &r, uint32_t tid0, std::vector<double> *real, std::vector<double> *surr) override {
         const int n = (int)r.xs.size();
         std::vector<uint64_t> tickets((size_t)n);
@@ -186,6 +187,7 @@ public:
             q.S = S_;
             q.seed = seed_;
             q.cand = tid0 + (uint32_t)j;
+            q.theiler = w_;
             int rc = mte_submit(&q, &tickets[(size_t)j]);
             if (rc) return rc;
         }
@@ -203,7 +205,7 @@ private:
     int32_t sid_;
     int lm_;
     int64_t N_;
-    int target_, k_, S_;
+    int target_, k_, S_, w_;
     uint64_t seed_;
 };
 
@@ -320,6 +322,8 @@ static int check_greedy_args(int P, int64_t T, int target, const int32_t *cands,
     }
     const int l_m = std::max(l_s, o.max_lag_target);
     if (T <= (int64_t)l_m + o.k) return fail(MTE_EINVAL, "T=%lld too short", (long long)T);
+    int rc = validate_theiler(T - l_m, o.k, o.theiler);
+    if (rc) return rc;
     if (T - l_m > 0x7fffffffLL) return fail(MTE_EINVAL, "T too long");
     if (!out->target_past || (n_cands > 0 && !out->sources))
         return fail(MTE_EINVAL, "result arrays must be allocated by the caller");
@@ -332,6 +336,7 @@ static mte_opts opts_or_default(const mte_opts *o) {
     d.S = 200;
     d.max_lag_target = 5;
     d.seed = 0;
+    d.theiler = 0;
     return o ? *o : d;
 }
 
@@ -342,7 +347,7 @@ int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32
     int rc = check_greedy_args(P, T, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
     if (rc) return rc;
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
-    ServedExec ex(sid, l_m, T - l_m, target, o.k, o.S, o.seed);
+    ServedExec ex(sid, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
     return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
 }
 
@@ -382,7 +387,7 @@ int mte_select_sources(const float *data, int P, int64_t T, int target, const in
     DevBuf series;
     if ((rc = series.ensure(sizeof(float) * (size_t)P * T))) return rc;
     MTE_HIP(hipMemcpy(series.p, data, sizeof(float) * (size_t)P * T, hipMemcpyHostToDevice));
-    DirectExec ex(series.as<float>(), T, l_m, T - l_m, target, o.k, o.S, o.seed);
+    DirectExec ex(series.as<float>(), T, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
     return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
 }
 

@@ -123,7 +123,7 @@ struct Worker {
     S &sm;
     const double *__restrict__ harm;
     uint32_t *__restrict__ err;
-    int g, t, gc, dx, dy, dz, n, lane, wave, tid;
+    int g, t, gc, dx, dy, dz, n, w, lane, wave, tid;
 
     __device__ Worker(const Job &j, S &s, const double *h, uint32_t *e, int g_, int t_)
         : J(j), sm(s), harm(h), err(e), g(g_), t(t_) {
@@ -131,6 +131,7 @@ struct Worker {
         dx = J.dx;
         dz = J.dz;
         dy = J.dy;
+        w = J.theiler;
         gc = min(G, J.n_est - g * G);
         tid = threadIdx.x;
         lane = tid & 63;
@@ -235,11 +236,12 @@ struct Worker {
         });
     }
 
-    // Self pairs and references at or past `hi` get distance +inf.
+    // Pairs inside the Theiler window |i - j| <= w (self pairs when w = 0) and
+    // references at or past `hi` get distance +inf.
     template <bool BOTH>
     __device__ __forceinline__ void mask(int j0, int hi, float (&az)[QP][kSteps], float (&ayz)[QP][kSteps]) {
         const int qlo = t * QT;
-        const bool diag = j0 < qlo + QT && j0 + kSteps > qlo;
+        const bool diag = j0 < qlo + QT + w && j0 + kSteps + w > qlo;
         const bool pad = j0 + kSteps > hi;
         if (!(diag || pad)) return;
 #pragma unroll
@@ -247,7 +249,7 @@ struct Worker {
             const int rel = qrow(q) - j0;
 #pragma unroll
             for (int r = 0; r < kSteps; ++r) {
-                const bool kill = (rel == r) || (j0 + r >= hi);
+                const bool kill = ((unsigned)(rel - r + w) <= (unsigned)(2 * w)) || (j0 + r >= hi);
                 if (BOTH) az[q][r] = kill ? inf_f() : az[q][r];
                 ayz[q][r] = kill ? inf_f() : ayz[q][r];
             }
@@ -372,7 +374,8 @@ struct Worker {
 #pragma unroll
             for (int q = 0; q < QP; ++q) {
                 const int i = qrow(q);
-                const int nz = dz == 0 ? n - 1 : cz[gg][q];
+                // without Z, n_z is the number of rows outside the window
+                const int nz = dz == 0 ? n - 1 - min(i, w) - min(n - 1 - i, w) : cz[gg][q];
                 double v = 0.0;
                 if (i < n) {
                     v = (harm[cxz[gg][q]] + harm[cyz[gg][q]]) - harm[nz];

@@ -186,7 +186,8 @@ __device__ __forceinline__ void acc_cols(const float *const *cols, const float (
 }
 
 // Calls f(r, j, d_z, d_yz) for every block row r (valid rows only) and every
-// other row j, row_batch<QB>() reference rows per thread at a time.
+// row j outside its Theiler window (|j - i| > w; j != i when w = 0),
+// row_batch<QB>() reference rows per thread at a time.
 template <int QB, class F>
 __device__ __forceinline__ void for_each_pair(const ListSet &S, const float (*q)[kMaxDy + kMaxDz], int i0,
                                               int nq, int tid, F &&f) {
@@ -210,7 +211,7 @@ __device__ __forceinline__ void for_each_pair(const ListSet &S, const float (*q)
             if (j >= n) continue;
 #pragma unroll
             for (int r = 0; r < QB; ++r)
-                if (r < nq && j != i0 + r) f(r, j, a[r][u], b[r][u]);
+                if (r < nq && abs(j - (i0 + r)) > S.theiler) f(r, j, a[r][u], b[r][u]);
         }
     }
 }
@@ -306,7 +307,8 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
         const int r = x / (2 * kListPad), w = (x / kListPad) & 1, u = x % kListPad;
         if (r >= nq) continue;
         const int64_t i = i0 + r;
-        const uint32_t total = (uint32_t)(n - 1);
+        const int tw = S.theiler;   // rows outside the window
+        const uint32_t total = (uint32_t)(n - 1 - min((int)i, tw) - min(n - 1 - (int)i, tw));
         const uint32_t kb = sm.kept_bins[r][w], kr = sm.kept_rows[r][w];
         const float bound = kr == total ? inf_f() : __uint_as_float(kb << kKeyShift);
         const float sent = kr == total ? inf_f() : __uint_as_float((kb << kKeyShift) + 1u);
@@ -504,8 +506,8 @@ __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLau
         const int64_t cs = (int64_t)n * E;
         const float *const *yc = J.cols + dx;
         const float *const *zc = J.cols + dx + dy;
-        // distances of kFbBatch rows j0, j0 + kFbThreads, ... (row i and rows past
-        // the end get +inf in every subspace)
+        // distances of kFbBatch rows j0, j0 + kFbThreads, ... (rows inside row
+        // i's Theiler window and rows past the end get +inf in every subspace)
         auto dists = [&](int j0, float (&ax)[kFbBatch], float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
             int jj[kFbBatch];
 #pragma unroll
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLau
             }
 #pragma unroll
             for (int u = 0; u < kFbBatch; ++u)
-                if (jj[u] == i) ax[u] = ay[u] = az[u] = inf_f();
+                if (abs(jj[u] - i) <= J.theiler) ax[u] = ay[u] = az[u] = inf_f();
         };
         float top[KMAX];
 #pragma unroll

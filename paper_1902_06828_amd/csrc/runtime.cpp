@@ -217,6 +217,33 @@ int validate_dims(int dx, int dy, int dz, int64_t n, int k) {
     return MTE_OK;
 }
 
+int validate_theiler(int64_t n, int k, int theiler) {
+    if (theiler < 0) return fail(MTE_EINVAL, "Theiler window %d must be >= 0", theiler);
+    if (n < (int64_t)k + 1 + 2 * (int64_t)theiler)
+        return fail(MTE_EINVAL, "N=%lld leaves fewer than k=%d rows outside a Theiler window of %d", (long long)n,
+                    k, theiler);
+    return MTE_OK;
+}
+
+// Autocorrelation decay time: the shortest lag L >= 1 at which the biased
+// autocovariance r(L) = (1/T) sum_t (x_t - mu)(x_{t+L} - mu) drops below
+// r(0)/e (max_lag if none does), with float64 sums in time order.
+int autocorr_decay_time(const float *x, int64_t T, int max_lag) {
+    double mu = 0.0;
+    for (int64_t t = 0; t < T; ++t) mu += (double)x[t];
+    mu /= (double)T;
+    auto r = [&](int64_t lag) {
+        double s = 0.0;
+        for (int64_t t = 0; t + lag < T; ++t) s += ((double)x[t] - mu) * ((double)x[t + lag] - mu);
+        return s / (double)T;
+    };
+    const double thr = r(0) / 2.718281828459045;
+    const int64_t top = std::min<int64_t>(max_lag, T - 1);
+    for (int64_t lag = 1; lag <= top; ++lag)
+        if (r(lag) < thr) return (int)lag;
+    return max_lag;
+}
+
 int validate_host_finite(const float *p, int64_t count, const char *name) {
     for (int64_t i = 0; i < count; ++i)
         if (!std::isfinite(p[i]))
@@ -248,7 +275,7 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
         const JobSpec &sp = specs[j];
         // the list kernels index the transposed X columns with 32-bit offsets
         if (sp.dz <= 0 || force == 0 || (int64_t)sp.dx * sp.n * sp.n_est() >= ((int64_t)1 << 31)) continue;
-        std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz};
+        std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz, (uintptr_t)sp.theiler};
         for (int c = 0; c < sp.dy + sp.dz; ++c) key.push_back((uintptr_t)sp.cols[sp.dx + c]);
         auto it = groups.emplace(key, (int)group_est.size()).first;
         if (it->second == (int)group_est.size()) group_est.push_back(0);
@@ -428,6 +455,7 @@ size_t Batch::device_bytes() const {
 static int check_spec(const JobSpec &sp) {
     if (sp.n_est() < 1) return fail(MTE_EINVAL, "job without estimates");
     if (sp.n < sp.k + 1) return fail(MTE_EINVAL, "N < k+1");
+    if (validate_theiler(sp.n, sp.k, sp.theiler)) return MTE_EINVAL;
     if (sp.k < 1 || sp.k > kMaxK || sp.dx < 1 || sp.dx > kMaxDx || sp.dy < 1 || sp.dy > kMaxDy || sp.dz < 0 ||
         sp.dz > kMaxDz)
         return fail(MTE_EINVAL, "job dimensions out of range");
@@ -518,6 +546,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.n = sp.n;
         S.dy = sp.dy;
         S.dz = sp.dz;
+        S.theiler = sp.theiler;
         S.m1 = std::min(sp.n - 1, cap1);
         S.m2 = std::min(sp.n - 1, cap2);
         S.s1 = S.m1 + kListPad;
@@ -592,6 +621,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.n_est = sp.n_est();
         J.rs = 1;
         J.set = set_of[j];
+        J.theiler = sp.theiler;
         J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
         J.eps = sp.diag_eps ? sp.diag_eps : reinterpret_cast<float *>(sb + offs[j].eps);
         J.cnt = sp.diag_cnt ? sp.diag_cnt : reinterpret_cast<int32_t *>(sb + offs[j].cnt);
@@ -676,6 +706,7 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
         std::memset(&J, 0, sizeof J);
         for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
         J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
+        J.theiler = sp.theiler;
         J.n_est = sp.n_est();
         J.n_tiles = (sp.n + qt - 1) / qt;
         J.n_groups = (J.n_est + cfg.g - 1) / cfg.g;

@@ -71,6 +71,7 @@ struct HostBuf {
 struct JobSpec {
     const float *cols[kMaxCols] = {};
     int n = 0, dx = 0, dy = 0, dz = 0, k = 0;
+    int theiler = 0;                   // Theiler window w (|i - j| <= w left out)
     std::vector<EstKey> keys;          // one per estimate
     double *out = nullptr;             // device [n_est]
     float *diag_eps = nullptr;         // device [n_est][n] or null
@@ -187,6 +188,8 @@ int run_blocking(const std::vector<JobSpec> &specs, hipStream_t s);
 // Validation shared by the entry points.
 int validate_dims(int dx, int dy, int dz, int64_t n, int k);
 int validate_host_finite(const float *p, int64_t count, const char *name);
+int validate_theiler(int64_t n, int k, int theiler);
+int autocorr_decay_time(const float *x, int64_t T, int max_lag);
 
 // Host mirror of the device harmonic table (same summation order).
 double harmonic_host(int64_t n);

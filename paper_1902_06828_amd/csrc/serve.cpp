@@ -144,6 +144,7 @@ public:
         sp.dy = q.r.dy;
         sp.dz = q.r.dz;
         sp.k = q.r.k;
+        sp.theiler = q.r.theiler;
         sp.keys.resize((size_t)q.r.S + 1);
         sp.keys[0] = EstKey{0, 1, 0};
         for (int s = 0; s < q.r.S; ++s)
@@ -332,6 +333,7 @@ int mte_series_release(int32_t sid) {
 int mte_submit(const mte_request *req, uint64_t *ticket_out) {
     if (!req || !ticket_out || !req->nodes || !req->lags) return fail(MTE_EINVAL, "null argument");
     int rc = validate_dims(req->dx, req->dy, req->dz, req->N, req->k);
+    if (!rc) rc = validate_theiler(req->N, req->k, req->theiler);
     if (rc) return rc;
     if (req->S < 0) return fail(MTE_EINVAL, "S must be >= 0");
     Server &sv = server();

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert mte.lib().mte_abi_version() == 1
+    assert mte.lib().mte_abi_version() == 2
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 100, 1000, 4097, 10000])
@@ -96,3 +96,32 @@ def test_greedy_argument_validation():
         mte.mte_select_sources(data, 0, [5], alpha=0.1, S=20)         # node out of range
     with pytest.raises(mte.MteError):
         mte.mte_select_sources(data[:, :8], 0, [1], alpha=0.1, S=20)  # series too short
+
+
+def test_autocorr_decay_time_matches_oracle():
+    # the library's host computation takes the oracle's decisions on float32 series
+    from oracle import act
+    g = np.random.default_rng(9)
+    for phi, n in [(0.8, 20000), (0.95, 5000), (0.3, 3000), (0.0, 500)]:
+        e = g.standard_normal(n)
+        x = np.empty(n)
+        x[0] = e[0]
+        for i in range(1, n):
+            x[i] = phi * x[i - 1] + e[i]
+        x32 = x.astype(np.float32)
+        assert mte.mte_autocorr_decay_time(x32, 60) == act.decay_time(x32.astype(np.float64), 60)
+    t = np.arange(5000)
+    s = np.sin(2 * np.pi * t / 50).astype(np.float32)
+    assert mte.mte_autocorr_decay_time(s, 50) == act.decay_time(s.astype(np.float64), 50) == 10
+
+
+def test_theiler_argument_validation():
+    x, y, z = (np.random.default_rng(1).standard_normal((1, 20)).astype(np.float32) for _ in range(3))
+    with pytest.raises(mte.MteError) as e:
+        mte.cmi_ksg_diag(x, y, z, 4, 0, 0, 0, theiler=8)
+    assert e.value.code == mte._lib.MTE_EINVAL
+    with pytest.raises(mte.MteError) as e:
+        mte.cmi_ksg_diag(x, y, z, 4, 0, 0, 0, theiler=-1)
+    assert e.value.code == mte._lib.MTE_EINVAL
+    with pytest.raises(mte.MteError):
+        mte.mte_autocorr_decay_time(np.zeros(1, np.float32), 5)

@@ -238,3 +238,70 @@ def test_psi_identity_used_by_the_c_oracle():
     m = np.arange(0, 20001)
     assert np.max(np.abs((digamma(m + 1.0) + np.euler_gamma) - h)) < 1e-11
     assert math.isclose(h[3], 1 + 1 / 2 + 1 / 3)
+
+
+# ---------------------------------------------------------------- Theiler window
+def _exact_ksg_window(cols_x, cols_y, cols_z, k, w):
+    """Exact rational brute force with the rows |i - j| <= w left out of row i's
+    neighbour set (no Z: n_z is the size of that set)."""
+    n = len(cols_x[0])
+    fr = lambda cols: [[Fraction(float(v)) for v in c] for c in cols]
+    X, Y, Z = fr(cols_x), fr(cols_y), fr(cols_z)
+
+    def dist(cols, i, j):
+        return max([abs(c[i] - c[j]) for c in cols], default=Fraction(0))
+
+    out = []
+    for i in range(n):
+        R = [j for j in range(n) if abs(i - j) > w]
+        d = sorted(max(dist(X, i, j), dist(Y, i, j), dist(Z, i, j)) for j in R)
+        e = d[k - 1]
+        nxz = sum(1 for j in R if max(dist(X, i, j), dist(Z, i, j)) < e)
+        nyz = sum(1 for j in R if max(dist(Y, i, j), dist(Z, i, j)) < e)
+        nz = len(R) if not Z else sum(1 for j in R if dist(Z, i, j) < e)
+        out.append((e, nxz, nyz, nz))
+    return out
+
+
+@pytest.mark.parametrize("seed,n,dims,k,w", [(21, 12, (1, 1, 1), 2, 1), (22, 15, (2, 1, 2), 3, 3),
+                                            (23, 13, (1, 2, 0), 2, 2), (24, 16, (1, 1, 3), 4, 5)])
+def test_theiler_window_exact(seed, n, dims, k, w):
+    x, y, z = synth.random_points(n, dims, seed, kind="grid")
+    ref = _exact_ksg_window(x, y, [] if z is None else z, k, w)
+    eps, a, b, c = ksg.eps_and_counts(x, y, z, k, theiler=w)
+    assert [(Fraction(float(e)), int(p), int(q), int(r)) for e, p, q, r in zip(eps, a, b, c)] == ref
+    e2, a2, b2, c2, _ = cksg.eps_and_counts(x, y, z, k, theiler=w)
+    assert np.array_equal(eps, e2) and np.array_equal(a, a2) and np.array_equal(b, b2) and np.array_equal(c, c2)
+
+
+def test_theiler_window_against_kdtree():
+    # k-th neighbour outside the window: query k + 2w + 1 neighbours with a
+    # k-d tree and drop those inside the window
+    n, k, w = 500, 4, 3
+    g = np.random.default_rng(31)
+    pts = (g.integers(-4096, 4097, size=(3, n)) / 512.0).astype(np.float32)
+    x, y, z = pts[:1], pts[1:2], pts[2:]
+    eps, *_ = ksg.eps_and_counts(x, y, z, k, theiler=w)
+    tree = cKDTree(pts.T.astype(np.float64))
+    d, idx = tree.query(pts.T.astype(np.float64), k=k + 2 * w + 1 + 1, p=np.inf)
+    for i in range(n):
+        keep = [dd for dd, j in zip(d[i], idx[i]) if abs(int(j) - i) > w]
+        assert eps[i] == np.float32(keep[k - 1])
+
+
+def test_theiler_window_reversal_and_rejection():
+    # reversing the time order maps every window onto itself
+    x, y, z = synth.random_points(300, (1, 1, 2), seed=41)
+    rev = lambda a: np.ascontiguousarray(a[:, ::-1])
+    r1 = ksg.eps_and_counts(x, y, z, 4, theiler=6)
+    r2 = ksg.eps_and_counts(rev(x), rev(y), rev(z), 4, theiler=6)
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b[::-1])
+    # w = 0 is the plain estimator
+    for a, b in zip(ksg.eps_and_counts(x, y, z, 4, theiler=0), ksg.eps_and_counts(x, y, z, 4)):
+        assert np.array_equal(a, b)
+    # too few rows outside the window
+    with pytest.raises(ValueError):
+        ksg.eps_and_counts(x[:, :20], y[:, :20], z[:, :20], 4, theiler=8)
+    with pytest.raises(ValueError):
+        cksg.eps_and_counts(x[:, :20], y[:, :20], z[:, :20], 4, theiler=8)
