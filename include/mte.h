@@ -222,6 +222,53 @@ int mte_select_sources_sid(int32_t sid, int target, const int32_t *candidates, i
                            mte_result *out);
 
 /* --------------------------------------------------------------------------
+ * Network level (Combining across multiple targets; Validation sections).
+ * ------------------------------------------------------------------------ */
+
+/* Benjamini-Hochberg step-up at level q over p[m] (FDR correction of the
+ * targets' omnibus p-values): keep_out[i] = 1 for the rejected nulls, i.e.
+ * the ranks 1..r of the ascending order (stable for ties) where r is the
+ * largest rank with p_(r) <= q*r/m.  0 < q < 1, p in [0,1]. */
+int mte_fdr_bh(const double *p, int m, double q, uint8_t *keep_out);
+
+typedef struct {
+    int n_target_past;     /* selected target-past variables */
+    int n_sources;         /* accepted source variables (0 unless the omnibus test passed) */
+    int n_sources_tested;  /* selected source variables before the omnibus test */
+    double omnibus_te;     /* collective TE of the selected sources (0 if none) */
+    double omnibus_p;      /* omnibus p-value (1 if no source was selected) */
+    int significant;       /* omnibus test passed (p < alpha) */
+    int fdr_kept;          /* kept by the FDR correction (1 when it is off) */
+    int64_t n_estimates;   /* CMI estimates computed for this target */
+} mte_target_summary;
+
+/*
+ * Network inference over data [P][T] (host, row-major): the greedy source
+ * selection (mte_select_sources) of every target t with all other processes
+ * as candidate sources, run concurrently through the request loop on
+ * n_threads host threads (<= 0: min(P, 16)); target t uses surrogate seed
+ * opts->seed + t.  Then, if alpha_fdr > 0, the Benjamini-Hochberg correction
+ * at level alpha_fdr over the P omnibus p-values.  adj_out [P][P] (caller
+ * array): adj[s][t] = 1 iff some past variable of s is an accepted source of
+ * t, t's omnibus test passed and (if on) the correction kept t.  targets_out
+ * [P] (caller array).  opts may be NULL (defaults).  Errors as
+ * mte_select_sources; the first failing target's error is returned.
+ */
+int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, double alpha,
+                      double alpha_fdr, const mte_opts *opts, int n_threads, uint8_t *adj_out,
+                      mte_target_summary *targets_out);
+
+/*
+ * Link statistics of an inferred adjacency against a known one, over the
+ * P*(P-1) ordered pairs of distinct processes (Validation section):
+ * counts_out = {TP, FP, TN, FN}; rates_out = {precision TP/(TP+FP), recall
+ * TP/(TP+FN), specificity TN/(TN+FP), false positive rate FP/(FP+TN)} (NaN
+ * for an empty denominator).
+ */
+int mte_link_metrics(const uint8_t *inferred, const uint8_t *truth, int P, int64_t *counts_out,
+                     double *rates_out);
+
+/* --------------------------------------------------------------------------
  * Request loop (continuous batching).  Series registered once stay resident
  * in HBM; each request is one candidate test (1 + S estimates of
  * I(X;Y|Z) over lag-shifted windows of a resident series); requests are

@@ -12,11 +12,13 @@ Modules
   stats   maximum-statistic, minimum-statistic and omnibus tests
   act     autocorrelation decay time (the Theiler window heuristic)
   greedy  the four-step greedy multivariate TE inference for one target
+  network every target, Benjamini-Hochberg over omnibus p-values, adjacency,
+          precision / recall / specificity / false positive rate
   cksg    ctypes loader for ksg_oracle.c, the same brute force in plain C (timed)
 
 Parity status: ksg, perm, stats and act are pinned by tests/test_oracle_*.py against
 closed forms, hand-counted cases, invariances and published generator outputs.
-greedy's selections on real data are pinned only statistically (recovery of
+greedy's and network's selections on real data are pinned only statistically (recovery of
 known parents, no selection on independent data): beyond that, parity
 unpinned, since the paper prints no CMI or TE values.
 """

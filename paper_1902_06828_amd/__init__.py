@@ -17,7 +17,10 @@ from ._lib import (  # noqa: F401
     cmi_ksg_surrogates_dev,
     lib,
     mte_autocorr_decay_time,
+    mte_fdr_bh,
+    mte_infer_network,
     mte_init,
+    mte_link_metrics,
     mte_kernel_timing,
     mte_kernel_timing_read,
     mte_kernel_timing_stage,

@@ -51,6 +51,12 @@ class mte_request(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("cand", ctypes.c_uint32), ("theiler", ctypes.c_int)]
 
 
+class mte_target_summary(ctypes.Structure):
+    _fields_ = [("n_target_past", ctypes.c_int), ("n_sources", ctypes.c_int), ("n_sources_tested", ctypes.c_int),
+                ("omnibus_te", ctypes.c_double), ("omnibus_p", ctypes.c_double), ("significant", ctypes.c_int),
+                ("fdr_kept", ctypes.c_int), ("n_estimates", ctypes.c_int64)]
+
+
 class mte_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("estimates", ctypes.c_int64),
@@ -80,6 +86,9 @@ SIGNATURES = {
     "cmi_ksg_surrogates_dev": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _U64, _U32, _P, _P],
     "cmi_ksg_surrogates_dev_ex": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _I, _U64, _U32, _P, _P],
     "mte_autocorr_decay_time": [_P, _I64, _I, _P],
+    "mte_fdr_bh": [_P, _I, ctypes.c_double, _P],
+    "mte_link_metrics": [_P, _P, _I, _P, _P],
+    "mte_infer_network": [_P, _I, _I64, _I, ctypes.c_double, ctypes.c_double, _P, _I, _P, _P],
     "mte_permutation": [_U64, _U32, _U32, _I64, _P],
     "mte_max_statistic": [_P, _P, _I, _I, _D, _P, _P, _P],
     "mte_min_statistic": [_P, _P, _I, _I, _D, _P, _P, _P],
@@ -415,3 +424,40 @@ def mte_list_stats(reset: bool = False, entries: bool = False):
     if entries:
         return a.value, b.value, [int(v) for v in ent]
     return a.value, b.value
+
+
+# ---------------------------------------------------------------- network level
+def mte_fdr_bh(pvals, q: float):
+    """Benjamini-Hochberg keep mask (bool array) at level q."""
+    p = np.ascontiguousarray(pvals, dtype=np.float64)
+    keep = np.zeros(len(p), np.uint8)
+    _check(lib().mte_fdr_bh(_ptr(p), len(p), q, _ptr(keep)))
+    return keep.astype(bool)
+
+
+def mte_link_metrics(inferred, truth):
+    a = np.ascontiguousarray(inferred, dtype=np.uint8)
+    b = np.ascontiguousarray(truth, dtype=np.uint8)
+    counts = np.zeros(4, np.int64)
+    rates = np.zeros(4, np.float64)
+    _check(lib().mte_link_metrics(_ptr(a), _ptr(b), a.shape[0], _ptr(counts), _ptr(rates)))
+    return {"tp": int(counts[0]), "fp": int(counts[1]), "tn": int(counts[2]), "fn": int(counts[3]),
+            "precision": float(rates[0]), "recall": float(rates[1]), "specificity": float(rates[2]),
+            "fpr": float(rates[3])}
+
+
+def mte_infer_network(data, max_lag_sources: int = 5, alpha: float = 0.05, alpha_fdr: float = 0.05,
+                      k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
+                      n_threads: int = 0):
+    """Returns (adjacency uint8 [P][P], per-target summaries as dicts)."""
+    data = np.ascontiguousarray(data)
+    if data.dtype != np.float32 or data.ndim != 2:
+        raise TypeError("data must be float32 [P][T]")
+    P = data.shape[0]
+    adj = np.zeros((P, P), np.uint8)
+    tgt = (mte_target_summary * P)()
+    o = _opts(k, S, max_lag_target, seed, theiler)
+    _check(lib().mte_infer_network(_ptr(data), P, data.shape[1], max_lag_sources, alpha,
+                                   alpha_fdr if alpha_fdr else 0.0, ctypes.byref(o), n_threads, _ptr(adj), tgt))
+    summ = [{name: getattr(tgt[t], name) for name, _ in mte_target_summary._fields_} for t in range(P)]
+    return adj, summ

@@ -10,6 +10,7 @@ from .gen import (  # noqa: F401
     c1_gaussian,
     c2_te_inputs,
     clm_network,
+    empty_network,
     er_digraph,
     paper_var_network,
     random_points,

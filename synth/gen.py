@@ -13,6 +13,7 @@ Workloads (paper, Validation tasks section, and the configurations measured here
   of the VAR companion matrix is 0.9; unit Gaussian noise.
 * ``paper_var_network``: the paper's own VAR variant (self-coupling 0.5, couplings
   normalised to sum 0.4 per target, noise s.d. 0.1).
+* ``empty_network``: independent AR(1) processes (no links).
 * ``clm_network``: coupled logistic maps, coupling applied after the map.
 * ``random_points``: sample matrices with ties and duplicate rows for parity tests.
 """
@@ -146,6 +147,13 @@ def _simulate_linear(p_nodes, n_rows, seed, self_coef, links, noise_sd):
                 acc += a[lag - 1] @ x[t - lag]
         x[t] = acc
     return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32))
+
+
+def empty_network(p_nodes: int, n_rows: int, seed: int, self_coef: float = 0.4, noise_sd: float = 1.0):
+    """P independent AR(1) processes x_i(t) = self_coef * x_i(t-1) + noise: a
+    network without links, where every inferred link is a false positive
+    (Validation of false positive rate).  Returns series [P][n_rows+MAX_LAG]."""
+    return _simulate_linear(p_nodes, n_rows, seed, self_coef, [], noise_sd)
 
 
 # ---------------------------------------------------------------- CLM

@@ -125,3 +125,27 @@ def test_theiler_argument_validation():
     assert e.value.code == mte._lib.MTE_EINVAL
     with pytest.raises(mte.MteError):
         mte.mte_autocorr_decay_time(np.zeros(1, np.float32), 5)
+
+
+def test_fdr_bh_matches_oracle():
+    g = np.random.default_rng(4)
+    for m in (1, 5, 40, 200):
+        for q in (0.01, 0.05, 0.2):
+            p = np.concatenate([g.random(m // 2) * 0.02, g.random(m - m // 2)])
+            p[g.integers(0, m, size=m // 5)] = 0.0           # ties, as from permutation tests
+            assert np.array_equal(mte.mte_fdr_bh(p, q), stats.benjamini_hochberg(p, q))
+    with pytest.raises(mte.MteError):
+        mte.mte_fdr_bh([0.5, 1.5], 0.05)
+
+
+def test_link_metrics_matches_oracle():
+    from oracle import network
+    g = np.random.default_rng(5)
+    for P in (2, 7, 30):
+        a = (g.random((P, P)) < 0.3).astype(np.uint8)
+        b = (g.random((P, P)) < 0.2).astype(np.uint8)
+        got, ref = mte.mte_link_metrics(a, b), network.link_metrics(a, b)
+        for key in ("tp", "fp", "tn", "fn"):
+            assert got[key] == ref[key]
+        for key in ("precision", "recall", "specificity", "fpr"):
+            assert (np.isnan(got[key]) and np.isnan(ref[key])) or got[key] == ref[key]

@@ -172,3 +172,16 @@ def test_omnibus_and_bh():
     assert keep.tolist() == [True, True, True, True]
     keep = stats.benjamini_hochberg([0.01, 0.2, 0.03, 0.005], 0.05)
     assert keep.tolist() == [True, False, True, True]
+
+
+def test_link_metrics_hand_example():
+    # 3 nodes; truth 0->1, 1->2; inferred 0->1, 2->0
+    from oracle import network
+    truth = np.zeros((3, 3), np.uint8)
+    truth[0, 1] = truth[1, 2] = 1
+    inf = np.zeros((3, 3), np.uint8)
+    inf[0, 1] = inf[2, 0] = 1
+    m = network.link_metrics(inf, truth)
+    assert (m["tp"], m["fp"], m["tn"], m["fn"]) == (1, 1, 3, 1)
+    assert m["precision"] == 0.5 and m["recall"] == 0.5 and m["specificity"] == 0.75 and m["fpr"] == 0.25
+    assert np.array_equal(network.truth_adjacency(3, [(1, 0, 2, 0.3), (2, 1, 1, 0.2)]), truth)
