@@ -33,6 +33,7 @@ N_ROWS, S, K_NN, SEED = 10000, 200, 4, 2
 # lanes per clock x 2.4 GHz = 78.6 T operations/s for the non-FMA operations
 # (subtract, max, min, med3, compare, integer add) this kernel issues.
 PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0                  # MI355X HBM3E
 
 
 def log(*a):
@@ -57,13 +58,34 @@ def build_ops(n, dy, dz):
     return n * (n - 1) * (2 * (dy + dz) - 1)
 
 
-def scan_ops(dx, entries):
-    """Neighbour-list scan, from the list entries read: a k-NN entry costs
-    2*dx+1 ops (X subtract/|.|-max, max with d_yz, compare with the k-th), a
-    Z-list entry 2*dx+7 (X subtract/|.|-max, max with d_z, three compares,
-    three adds)."""
+def scan_bytes(dx, entries):
+    """Neighbour-list scan, from the list entries it reads: an entry of a
+    (Y,Z) list is 8 bytes (d_yz, row), of a Z list 12 bytes (d_z, d_yz, row),
+    and each entry also reads the row's dx permuted X values (4 bytes each)."""
     knn, zl = entries
-    return knn * (2 * dx + 1) + zl * (2 * dx + 7)
+    return knn * (8 + 4 * dx) + zl * (12 + 4 * dx)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its factor for a plain
+    copy of known size), or None when the summary covers another kernel or
+    the kernel source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if rec.get("stage") != kernel or rec.get("sha256") != h.hexdigest():
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(X, Y, Z, budget_s=15.0):
@@ -141,6 +163,24 @@ def served(mte, torch, n_burst=48, n_poisson=96, load=0.8):
     }
 
 
+def network_leg(mte):
+    """Network inference on the benchmark's 10-node VAR (T = 10000): every
+    target's greedy selection through the request loop (targets concurrent),
+    S = 200, alpha = 0.05, FDR over omnibus p-values; wall time, estimates per
+    second and the link statistics against the generating graph."""
+    import synth
+    from oracle import network
+    series, links = synth.var_network(10, N_ROWS, seed=SEED)
+    t = time.perf_counter()
+    adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, S=S, seed=SEED)
+    wall = time.perf_counter() - t
+    est = int(sum(s["n_estimates"] for s in summ))
+    m = mte.mte_link_metrics(adj, network.truth_adjacency(10, links))
+    return {"workload": "10-node VAR (config form), T=10000, all targets, S=200, alpha=0.05, BH-FDR 0.05",
+            "wall_s": wall, "estimates": est, "evals_per_s": est / wall,
+            "precision": m["precision"], "recall": m["recall"], "specificity": m["specificity"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +189,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 1 GiB (256Mi float32 read + written) before the "
                          "timed region, as the reference for HBM byte counters")
@@ -215,24 +256,25 @@ def main():
     mte.mte_list_stats_enable(False)
     pairs, undecided, entries = mte.mte_list_stats(reset=True, entries=True)
     dominant = max(stage_ms, key=lambda k: stage_ms[k]["ms_per_launch"] * stage_ms[k]["launches_per_step"])
-    if dominant == "all_pairs":
-        ops = algorithmic_ops(N_ROWS, 1, 1, 5, E)
-    elif dominant == "build":
-        ops = build_ops(N_ROWS, 1, 5)
-    elif dominant == "scan":
-        ops = scan_ops(1, entries)
-    else:
-        ops = None
     k_avg_ms = stage_ms[dominant]["ms_per_launch"]
-    achieved = ops / (k_avg_ms * 1e-3) / 1e12 if ops else None
+    if dominant == "scan":
+        # a gather/stream kernel: list entries and permuted X values it reads
+        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
+        work = scan_bytes(1, entries)
+        achieved = work / (k_avg_ms * 1e-3) / 1e9
+    else:
+        bound, unit, peak = "alu", "TOP/s", PEAK_TOPS
+        work = algorithmic_ops(N_ROWS, 1, 1, 5, E) if dominant == "all_pairs" else (
+            build_ops(N_ROWS, 1, 5) if dominant == "build" else None)
+        achieved = work / (k_avg_ms * 1e-3) / 1e12 if work else None
+    traffic = measured_traffic(dominant)
     equiv = algorithmic_ops(N_ROWS, 1, 1, 5, E) / (dt / args.steps) / 1e12
     log(f"batched: {value:.1f} evals/s, {dt / args.steps * 1e3:.3f} ms/step; stages (ms/step): " +
         ", ".join(f"{k} {v['ms_per_step']:.3f}" for k, v in stage_ms.items()))
     log(f"list path: {pairs} pairs, {undecided} redone over all rows, entries read {entries}")
     if achieved:
-        log(f"dominant kernel: {dominant} {k_avg_ms:.3f} ms, {achieved:.2f} TOP/s "
-            f"({achieved / PEAK_TOPS:.1%} of {PEAK_TOPS:.1f}); all-pairs-equivalent rate {equiv:.1f} TOP/s; "
-            f"TE p={p:.3f}")
+        log(f"dominant kernel: {dominant} {k_avg_ms:.3f} ms, {achieved:.2f} {unit} ({achieved / peak:.1%} of "
+            f"{peak:.1f}); all-pairs-equivalent rate {equiv:.1f} TOP/s; TE p={p:.3f}")
 
     # graph replay of the same step (timing off)
     torch.cuda.synchronize()
@@ -276,6 +318,13 @@ def main():
         log(f"served: {srv['saturation_evals_per_s']:.1f} evals/s saturated; Poisson p50 "
             f"{srv['p50_latency_s'] * 1e3:.1f} ms p99 {srv['p99_latency_s'] * 1e3:.1f} ms")
 
+    net = None
+    if not args.no_network:
+        log("network: all targets of the 10-node VAR")
+        net = network_leg(mte)
+        log(f"network: {net['wall_s']:.2f} s, {net['evals_per_s']:.1f} evals/s, precision {net['precision']:.2f} "
+            f"recall {net['recall']:.2f}")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: C oracle on a bounded sample")
@@ -301,9 +350,9 @@ def main():
                         "201 estimates in one batched launch, host significance test",
             "N": N_ROWS, "dims": [1, 1, 5], "k": K_NN, "estimates_per_step": E,
         },
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_TOPS if achieved else None, "traffic": None,
-                     "kernel": dominant, "kernel_ms": k_avg_ms, "ops_per_launch": ops},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak if achieved else None, "traffic": traffic,
+                     "kernel": dominant, "kernel_ms": k_avg_ms, "work_per_launch": work},
         "stages_ms_per_step": {k: v["ms_per_step"] for k, v in stage_ms.items()},
         "list_path": {"pairs": pairs, "redone_over_all_rows": undecided, "entries_read": entries},
         "all_pairs_equivalent_tops": equiv,
@@ -311,6 +360,7 @@ def main():
         "graph_replay_evals_per_s": graph_value,
         "plain": plain,
         "served": srv,
+        "network": net,
     }
     print(json.dumps(line), flush=True)
 
