@@ -11,12 +11,14 @@ Modules
   perm    keyed surrogate permutation (swap-or-not shuffle keyed by SplitMix64)
   stats   maximum-statistic, minimum-statistic and omnibus tests
   act     autocorrelation decay time (the Theiler window heuristic)
-  greedy  the four-step greedy multivariate TE inference for one target
+  gauss   Gaussian (linear) CMI estimator and its analytic chi^2 null
+  greedy  the four-step greedy multivariate TE inference for one target (surrogate
+          tests with KSG, or analytic tests with the Gaussian estimator)
   network every target, Benjamini-Hochberg over omnibus p-values, adjacency,
           precision / recall / specificity / false positive rate
   cksg    ctypes loader for ksg_oracle.c, the same brute force in plain C (timed)
 
-Parity status: ksg, perm, stats and act are pinned by tests/test_oracle_*.py against
+Parity status: ksg, perm, stats, act and gauss are pinned by tests/test_oracle_*.py against
 closed forms, hand-counted cases, invariances and published generator outputs.
 greedy's and network's selections on real data are pinned only statistically (recovery of
 known parents, no selection on independent data): beyond that, parity

@@ -34,7 +34,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ksg, perm, stats
+from . import gauss, ksg, perm, stats
 
 
 def embed(series: np.ndarray, node: int, lag: int, l_m: int) -> np.ndarray:
@@ -83,11 +83,20 @@ def _numpy_estimator(x, y, z, k, theiler=0):
 
 def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
                    max_lag_target: int = 5, alpha: float = 0.05, k: int = 4,
-                   n_surr: int = 200, seed: int = 0, estimator=None, theiler: int = 0):
+                   n_surr: int = 200, seed: int = 0, estimator=None, theiler: int = 0,
+                   null: str = "surrogate"):
+    """null = "surrogate": the KSG estimator (or `estimator`) with the
+    surrogate tests.  null = "analytic": the Gaussian estimator with the
+    analytic (chi^2) null of oracle/gauss.py; no surrogates are drawn."""
     series = np.asarray(series)
     if series.dtype != np.float32:
         raise TypeError("series must be float32")
-    stats.require_surrogates(n_surr, alpha)
+    analytic = null == "analytic"
+    if analytic:
+        n_surr = 0
+        estimator = lambda x, y, z, kk, theiler=0: gauss.cmi_gauss(x, y, z)
+    else:
+        stats.require_surrogates(n_surr, alpha)
     if target in candidates:
         raise ValueError("target among candidates")
     l_m = max(max_lag_target, max_lag_sources)
@@ -95,13 +104,29 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
     run = _Run(series, target, k, n_surr, seed, l_m,
                (lambda x, y, z, kk: est(x, y, z, kk, theiler=theiler)) if theiler else est)
 
+    n_rows = run.y.shape[1]
+
+    def max_test(real, surr):
+        if not analytic:
+            return stats.max_statistic(real, surr, alpha)
+        j = int(np.argmax(real))
+        p = gauss.p_max(float(real[j]), len(real), n_rows, 1)
+        return j, p, p < alpha
+
+    def min_test(real, surr):
+        if not analytic:
+            return stats.min_statistic(real, surr, alpha)
+        j = int(np.argmin(real))
+        p = gauss.p_min(float(real[j]), len(real), n_rows, 1)
+        return j, p, p < alpha
+
     # Step 1: target past
     ycand = [(target, lag) for lag in range(1, max_lag_target + 1)]
     ysel = []
     while ycand:
         yv = [(n, l) for (n, l, _, _) in ysel]
         real, surr = run.test_candidates(ycand, lambda c: yv)
-        j, p, sig = stats.max_statistic(real, surr, alpha)
+        j, p, sig = max_test(real, surr)
         if not sig:
             break
         ysel.append(ycand[j] + (float(real[j]), p))
@@ -114,7 +139,7 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
     while xcand:
         xvars = [(n, l) for (n, l, _, _) in xsel]
         real, surr = run.test_candidates(xcand, lambda c: yvars + xvars)
-        j, p, sig = stats.max_statistic(real, surr, alpha)
+        j, p, sig = max_test(real, surr)
         if not sig:
             break
         xsel.append(xcand[j] + (float(real[j]), p))
@@ -125,7 +150,7 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
         xvars = [(n, l) for (n, l, _, _) in xsel]
         real, surr = run.test_candidates(
             xvars, lambda c: yvars + [v for v in xvars if v != c])
-        j, p, sig = stats.min_statistic(real, surr, alpha)
+        j, p, sig = min_test(real, surr)
         if sig:
             break
         del xsel[j]
@@ -137,14 +162,19 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
         x = run.cols(xvars)
         z = run.cols(yvars)
         omni_te = run.est(x, run.y, z, k)
-        n_rows = run.y.shape[1]
-        surr = np.empty(n_surr)
-        for s in range(n_surr):
-            p_ = perm.permutation(seed, run.tid, s, n_rows)
-            surr[s] = run.est(ksg.permute_rows(x, p_), run.y, z, k)
-        run.tid += 1
-        run.n_estimates += 1 + n_surr
-        omni_p, omni_sig = stats.omnibus(omni_te, surr, alpha)
+        if analytic:
+            run.tid += 1
+            run.n_estimates += 1
+            omni_p = gauss.p_value(omni_te, n_rows, len(xvars))
+            omni_sig = omni_p < alpha
+        else:
+            surr = np.empty(n_surr)
+            for s in range(n_surr):
+                p_ = perm.permutation(seed, run.tid, s, n_rows)
+                surr[s] = run.est(ksg.permute_rows(x, p_), run.y, z, k)
+            run.tid += 1
+            run.n_estimates += 1 + n_surr
+            omni_p, omni_sig = stats.omnibus(omni_te, surr, alpha)
     return {
         "target_past": ysel,
         "sources": xsel if omni_sig else [],

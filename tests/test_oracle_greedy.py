@@ -50,3 +50,28 @@ def test_rejects_too_few_surrogates():
         greedy.select_sources(s, 0, [1], alpha=0.05, n_surr=20)
     with pytest.raises(ValueError):
         greedy.select_sources(s, 0, [0], alpha=0.5, n_surr=20)
+
+
+def test_analytic_null_recovers_var_parents():
+    # Gaussian estimator with the chi^2 null on a linear VAR: the paper's
+    # choice for its VAR experiments.  Target 0 of the 5-node network has the
+    # parents (2, lag 2) and (4, lag 2).
+    from synth import gen
+    s, _ = gen.var_network(5, 2000, seed=1)
+    res = greedy.select_sources(s, 0, [1, 2, 3, 4], max_lag_sources=3, max_lag_target=3,
+                                alpha=0.05, seed=0, null="analytic")
+    assert sorted((n, l) for (n, l, _, _) in res["sources"]) == [(2, 2), (4, 2)]
+    assert res["significant"] and res["omnibus_p"] < 1e-10
+    # no surrogates: one estimate per candidate test
+    assert res["n_estimates"] < 60
+
+
+def test_analytic_null_on_independent_series_selects_little():
+    hits = 0
+    for seed in range(10):
+        g = np.random.default_rng(300 + seed)
+        s = g.standard_normal((3, 1000)).astype(np.float32)
+        res = greedy.select_sources(s, 0, [1, 2], max_lag_sources=3, max_lag_target=2,
+                                    alpha=0.05, null="analytic")
+        hits += len(res["sources"]) > 0
+    assert hits <= 3
