@@ -141,6 +141,48 @@ int cmi_ksg_surrogates_dev_ex(const float *dX, int dx, const float *dY, int dy, 
  */
 int mte_autocorr_decay_time(const float *x, int64_t T, int max_lag, int *act_out);
 
+/* --------------------------------------------------------------------------
+ * Gaussian (linear) estimator of I(X;Y|Z), in nats: the estimator the paper
+ * uses for its VAR processes (VAR section) and compares with KSG on coupled
+ * logistic maps (Estimators section); its null distribution is analytic
+ * (Maximum statistic test section).
+ *   Sigma  = (1/N) sum_t (v_t - mean)(v_t - mean)^T, float64, two passes
+ *            (means first); every entry is the same bits in any matrix that
+ *            holds both of its columns;
+ *   I      = 1/2 [ln det Sigma_XZ + ln det Sigma_YZ - ln det Sigma_Z
+ *                 - ln det Sigma_XYZ]
+ *          = 1/2 [ln det Sigma_{Y|Z} - ln det Sigma_{Y|XZ}] (Schur complements,
+ *            from Cholesky factorisations of the (Z,Y) and (Z,X,Y) blocks);
+ *   null   2 N I ~ chi^2 with dx*dy degrees of freedom.
+ * Limits: dx, dy >= 1, dz >= 0, dx+dy+dz <= 64; 2 <= N <= 2^31-1.
+ * MTE_EINVAL if a covariance block is not positive definite (a constant or
+ * collinear variable, or N too small for the dimension).
+ * ------------------------------------------------------------------------ */
+
+/* One estimate from host column-major buffers X[dx][N], Y[dy][N], Z[dz][N]
+ * (Z NULL iff dz == 0), blocking.  p_out (may be NULL) receives the analytic
+ * p-value sf_{dx*dy}(2 N I). */
+int cmi_gauss(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
+              int64_t N, double *cmi_out, double *p_out);
+
+/* Covariance matrix of D device columns dV + c*ld (c < D, N rows each) into
+ * the device array d_cov[D][D] (row-major, symmetric).  1 <= D <= 512,
+ * ld >= N.  Runs on `stream` and returns when it has finished (the partial
+ * sums use library-owned scratch of about min(256, N/256) * D * D doubles). */
+int mte_gauss_covariance_dev(const float *dV, int D, int64_t N, int64_t ld, double *d_cov,
+                             void *stream);
+
+/* I for n_sets index sets against a device covariance d_cov[D][D] (from
+ * mte_gauss_covariance_dev): dims[3*j..] = (dx, dy, dz) of set j and idx
+ * holds, set after set, its X, Y and Z column indices (0 <= index < D).
+ * Host arrays; cmi_out[n_sets] on the host; returns when finished. */
+int mte_gauss_cmi_sets(const double *d_cov, int D, int n_sets, const int32_t *dims,
+                       const int32_t *idx, double *cmi_out, void *stream);
+
+/* Chi-squared survival function P(chi^2_dof > x) for integer dof >= 1 (the
+ * finite incomplete-gamma series for integer and half-integer order). */
+int mte_chi2_sf(double x, int dof, double *out);
+
 /*
  * The surrogate permutation pi_{seed,cand,s} of {0..N-1} (host computation of
  * the same definition the kernels use): a swap-or-not shuffle (Hoang, Morris,
@@ -182,8 +224,22 @@ typedef struct {
     int S;              /* surrogates per candidate test (default 200) */
     int max_lag_target; /* target-past candidate lags 1..max_lag_target (default 5) */
     uint64_t seed;      /* surrogate key seed (default 0) */
-    int theiler;        /* Theiler window of every estimate (default 0) */
+    int theiler;        /* Theiler window of every estimate (default 0; KSG only) */
+    int estimator;      /* MTE_ESTIMATOR_KSG (default) or MTE_ESTIMATOR_GAUSS */
 } mte_opts;
+
+/* Estimators of the greedy search.  KSG: every test is a surrogate test
+ * with S permutation surrogates (k, S, seed, theiler apply).  GAUSS: the
+ * Gaussian estimator (cmi_gauss) with its analytic null, no surrogates (k, S
+ * and seed are ignored; theiler must be 0): with n candidates in a round and
+ * N rows, the maximum-statistic p is 1 - (1 - sf_1(2 N I_max))^n, the
+ * minimum-statistic p is sf_1(2 N I_min)^n, and the omnibus p is
+ * sf_{|X^S|}(2 N T) (sf_d: chi^2 survival function with d degrees of freedom),
+ * the candidates' statistics being treated as independent, as in the
+ * family-wise error correction of the Maximum statistic test section.
+ * n_estimates counts one estimate per candidate test. */
+#define MTE_ESTIMATOR_KSG 0
+#define MTE_ESTIMATOR_GAUSS 1
 
 typedef struct {
     int32_t node, lag;  /* process index and lag in samples */

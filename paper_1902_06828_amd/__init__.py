@@ -2,14 +2,17 @@
 transfer-entropy network inference (arXiv:1902.06828): the KSG
 conditional-mutual-information estimator with permutation surrogates, the
 maximum/minimum-statistic and omnibus tests, the four-step greedy source
-selection and a continuous-batching request loop.
+selection and a continuous-batching request loop; the Gaussian estimator with
+its analytic null as the alternative estimator of the greedy search.
 
 All work runs in libmte.so (HIP kernels and C++ runtime); this package only
 marshals arguments.  The C ABI is declared in include/mte.h.
 """
 
 from ._lib import (  # noqa: F401
+    ESTIMATORS,
     MteError,
+    cmi_gauss,
     cmi_ksg,
     cmi_ksg_dev,
     cmi_ksg_diag,
@@ -17,7 +20,10 @@ from ._lib import (  # noqa: F401
     cmi_ksg_surrogates_dev,
     lib,
     mte_autocorr_decay_time,
+    mte_chi2_sf,
     mte_fdr_bh,
+    mte_gauss_cmi_sets,
+    mte_gauss_covariance_dev,
     mte_infer_network,
     mte_init,
     mte_link_metrics,

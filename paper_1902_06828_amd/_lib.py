@@ -28,7 +28,7 @@ class MteError(RuntimeError):
 
 class mte_opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("S", ctypes.c_int), ("max_lag_target", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int), ("estimator", ctypes.c_int)]
 
 
 class mte_var(ctypes.Structure):
@@ -106,7 +106,13 @@ SIGNATURES = {
     "mte_kernel_timing_stage": [_I, _P, _P, _I],
     "mte_list_stats": [_P, _P, _P, _I],
     "mte_list_stats_enable": [_I],
+    "cmi_gauss": [_P, _I, _P, _I, _P, _I, _I64, _P, _P],
+    "mte_gauss_covariance_dev": [_P, _I, _I64, _I64, _P, _P],
+    "mte_gauss_cmi_sets": [_P, _I, _I, _P, _P, _P, _P],
+    "mte_chi2_sf": [_D, _I, _P],
 }
+
+ESTIMATORS = {"ksg": 0, "gauss": 1}
 
 _lib = None
 
@@ -215,6 +221,11 @@ def mte_autocorr_decay_time(x, max_lag: int) -> int:
     return out.value
 
 
+def _torch():
+    import torch
+    return torch
+
+
 def _stream_ptr(stream):
     if stream is None:
         import torch
@@ -303,12 +314,16 @@ def _result_dict(res, tp, src):
     }
 
 
-def _opts(k, S, max_lag_target, seed, theiler=0):
-    return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed, theiler=theiler)
+def _opts(k, S, max_lag_target, seed, theiler=0, estimator="ksg"):
+    if estimator not in ESTIMATORS:
+        raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
+    return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed, theiler=theiler,
+                    estimator=ESTIMATORS[estimator])
 
 
 def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, alpha: float = 0.05,
-                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0):
+                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
+                       estimator: str = "ksg"):
     data = np.ascontiguousarray(data)
     if data.dtype != np.float32 or data.ndim != 2:
         raise TypeError("data must be float32 [P][T]")
@@ -316,7 +331,7 @@ def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, 
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed, theiler)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
     _check(lib().mte_select_sources(_ptr(data), data.shape[0], data.shape[1], target, _ptr(cands),
                                     len(cands), max_lag_sources, alpha, ctypes.byref(o),
                                     ctypes.byref(res)))
@@ -325,12 +340,12 @@ def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, 
 
 def mte_select_sources_sid(sid: int, target: int, candidates, max_lag_sources: int = 5,
                            alpha: float = 0.05, k: int = 4, S: int = 200, max_lag_target: int = 5,
-                           seed: int = 0, theiler: int = 0):
+                           seed: int = 0, theiler: int = 0, estimator: str = "ksg"):
     cands = np.ascontiguousarray(candidates, dtype=np.int32)
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed, theiler)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
     _check(lib().mte_select_sources_sid(sid, target, _ptr(cands), len(cands), max_lag_sources, alpha,
                                         ctypes.byref(o), ctypes.byref(res)))
     return _result_dict(res, tp, src)
@@ -448,7 +463,7 @@ def mte_link_metrics(inferred, truth):
 
 def mte_infer_network(data, max_lag_sources: int = 5, alpha: float = 0.05, alpha_fdr: float = 0.05,
                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
-                      n_threads: int = 0):
+                      n_threads: int = 0, estimator: str = "ksg"):
     """Returns (adjacency uint8 [P][P], per-target summaries as dicts)."""
     data = np.ascontiguousarray(data)
     if data.dtype != np.float32 or data.ndim != 2:
@@ -456,8 +471,52 @@ def mte_infer_network(data, max_lag_sources: int = 5, alpha: float = 0.05, alpha
     P = data.shape[0]
     adj = np.zeros((P, P), np.uint8)
     tgt = (mte_target_summary * P)()
-    o = _opts(k, S, max_lag_target, seed, theiler)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
     _check(lib().mte_infer_network(_ptr(data), P, data.shape[1], max_lag_sources, alpha,
                                    alpha_fdr if alpha_fdr else 0.0, ctypes.byref(o), n_threads, _ptr(adj), tgt))
     summ = [{name: getattr(tgt[t], name) for name, _ in mte_target_summary._fields_} for t in range(P)]
     return adj, summ
+
+
+# ---------------------------------------------------------------- Gaussian estimator
+def cmi_gauss(X, Y, Z=None):
+    """Gaussian I(X;Y|Z) in nats and its analytic p-value sf_{dx*dy}(2 N I)."""
+    X, dx, Y, dy, Z, dz, n = _xyz(X, Y, Z)
+    out, p = ctypes.c_double(), ctypes.c_double()
+    _check(lib().cmi_gauss(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, ctypes.byref(out), ctypes.byref(p)))
+    return out.value, p.value
+
+
+def mte_gauss_covariance_dev(V, cov, n: int | None = None, stream=None) -> None:
+    """Covariance of the rows of a device float32 tensor V [D][ld] (first n
+    columns of each row) into the device float64 tensor cov [D][D]."""
+    if V.dtype != _torch().float32 or V.dim() != 2 or V.stride(1) != 1:
+        raise TypeError("V must be a float32 [D][ld] tensor with unit column stride")
+    D = V.shape[0]
+    if cov.dtype != _torch().float64 or tuple(cov.shape) != (D, D) or not cov.is_contiguous():
+        raise TypeError("cov must be a contiguous float64 [D][D] tensor")
+    rows = V.shape[1] if n is None else n
+    _check(lib().mte_gauss_covariance_dev(ctypes.c_void_p(V.data_ptr()), D, rows, V.stride(0),
+                                          ctypes.c_void_p(cov.data_ptr()), _stream_ptr(stream)))
+
+
+def mte_gauss_cmi_sets(cov, sets, stream=None):
+    """I for each (X, Y, Z) index-list triple against a device covariance."""
+    if cov.dtype != _torch().float64 or cov.dim() != 2 or not cov.is_contiguous():
+        raise TypeError("cov must be a contiguous float64 [D][D] tensor")
+    dims, idx = [], []
+    for x, y, z in sets:
+        dims += [len(x), len(y), len(z)]
+        idx += list(x) + list(y) + list(z)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    idx = np.ascontiguousarray(idx if idx else [0], dtype=np.int32)
+    out = np.zeros(max(1, len(sets)), np.float64)
+    _check(lib().mte_gauss_cmi_sets(ctypes.c_void_p(cov.data_ptr()), cov.shape[0], len(sets), _ptr(dims),
+                                    _ptr(idx), _ptr(out), _stream_ptr(stream)))
+    return out[:len(sets)]
+
+
+def mte_chi2_sf(x: float, dof: int) -> float:
+    out = ctypes.c_double()
+    _check(lib().mte_chi2_sf(float(x), dof, ctypes.byref(out)))
+    return out.value

@@ -1,0 +1,224 @@
+// Gaussian estimator kernels (gfx950): the float64 covariance of a set of
+// columns and, from it, I(X;Y|Z) of many (X, Y, Z) index sets.
+//
+//   colsum   per row chunk and column, the float64 sum of the chunk's rows
+//            (lane-strided, then a fixed butterfly);
+//   gram     per row chunk and 64x64 tile of the upper triangle, the centered
+//            cross products sum_r (a_r - mean_a)(b_r - mean_b) in float64, one
+//            fma chain per entry over the chunk's rows in order;
+//   reduce   per entry, the chunk partials summed in chunk order, / N.
+//
+// The chunking depends on N only and every entry is one fixed sequence of
+// operations on its two columns, so an entry has the same bits in any
+// covariance matrix that contains both columns (an estimate from a small
+// matrix equals the same estimate taken from a large one).
+//
+//   cmi      one wave per estimate: Cholesky (outer-product form) of the
+//            submatrix ordered (Z, X, Y), then of (Z, Y); the Schur pivots of
+//            the Y block give ln det Sigma_{Y|XZ} and ln det Sigma_{Y|Z}.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gauss.h"
+
+namespace mte {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kT = kGaussTile;
+constexpr int kRB = kGaussRowStage;
+constexpr int kLd = kT + 2;   // LDS row stride (doubles), keeps 16-byte alignment
+
+__device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int bid_x() { return (int)__builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ int bid_y() { return (int)__builtin_amdgcn_workgroup_id_y(); }
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) void gauss_colsum_kernel(GaussCov a) {
+    const int lane = tid_x() & 63, wave = tid_x() >> 6;
+    const int c = bid_x();
+    const int r0 = c * a.chunk_rows;
+    const int r1 = min(a.n, r0 + a.chunk_rows);
+    for (int col = wave; col < a.D; col += kThreads / 64) {
+        const float *p = a.cols[col];
+        double s = 0.0;
+        for (int r = r0 + lane; r < r1; r += 64) s += (double)p[r];
+        s = wave_sum_f64(s);
+        if (lane == 0) a.part_mean[(int64_t)c * a.D + col] = s;
+    }
+}
+
+// Upper-triangle tile pair y -> (tp, tq), tp <= tq.
+__device__ __forceinline__ void tile_pair(int y, int n_tiles, int *tp, int *tq) {
+    int p = 0;
+    while (y >= n_tiles - p) {
+        y -= n_tiles - p;
+        ++p;
+    }
+    *tp = p;
+    *tq = p + y;
+}
+
+__global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
+    __shared__ double mu[2][kT];
+    __shared__ __align__(16) double As[kRB][kLd];
+    __shared__ __align__(16) double Bs[kRB][kLd];
+    const int tid = tid_x();
+    const int c = bid_x();
+    int tp, tq;
+    tile_pair(bid_y(), a.n_tiles, &tp, &tq);
+    const int p0 = tp * kT, q0 = tq * kT;
+    const int r0 = c * a.chunk_rows;
+    const int r1 = min(a.n, r0 + a.chunk_rows);
+
+    if (tid < 2 * kT) {
+        const int col = (tid < kT ? p0 : q0 - kT) + tid;
+        double s = 0.0;
+        if (col < a.D)
+            for (int h = 0; h < a.n_chunks; ++h) s += a.part_mean[(int64_t)h * a.D + col];
+        mu[tid / kT][tid % kT] = s / (double)a.n;
+    }
+
+    const int ty = tid >> 4, tx = tid & 15;   // rows ty*4.., columns tx*4.. of the tile
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    for (int rs = r0; rs < r1; rs += kRB) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kRB * kT / kThreads; ++m) {
+            const int e = tid + m * kThreads;
+            const int r = e % kRB, col = e / kRB;
+            const int row = rs + r;
+            double va = 0.0, vb = 0.0;
+            if (row < r1) {
+                if (p0 + col < a.D) va = (double)a.cols[p0 + col][row] - mu[0][col];
+                if (q0 + col < a.D) vb = (double)a.cols[q0 + col][row] - mu[1][col];
+            }
+            As[r][col] = va;
+            Bs[r][col] = vb;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < kRB; ++r) {
+            const double2 a01 = *reinterpret_cast<const double2 *>(&As[r][ty * 4]);
+            const double2 a23 = *reinterpret_cast<const double2 *>(&As[r][ty * 4 + 2]);
+            const double2 b01 = *reinterpret_cast<const double2 *>(&Bs[r][tx * 4]);
+            const double2 b23 = *reinterpret_cast<const double2 *>(&Bs[r][tx * 4 + 2]);
+            const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+            const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+    double *out = a.part + (int64_t)c * a.D * a.D;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int p = p0 + ty * 4 + i;
+        if (p >= a.D) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = q0 + tx * 4 + j;
+            if (q < a.D) out[(int64_t)p * a.D + q] = acc[i][j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gauss_cov_reduce_kernel(GaussCov a) {
+    const int64_t e = (int64_t)bid_x() * kThreads + tid_x();
+    if (e >= (int64_t)a.D * a.D) return;
+    const int p = (int)(e / a.D), q = (int)(e % a.D);
+    if (p > q) return;
+    double s = 0.0;
+    for (int h = 0; h < a.n_chunks; ++h) s += a.part[(int64_t)h * a.D * a.D + e];
+    s /= (double)a.n;
+    a.cov[(int64_t)p * a.D + q] = s;
+    a.cov[(int64_t)q * a.D + p] = s;
+}
+
+// One wave per estimate.  Outer-product Cholesky: at step k the pivot is
+// the Schur complement diagonal d_k, and column j > k (owned by lane j) is
+// updated below its diagonal by A[i][j] -= A[i][k] * (A[j][k] / d_k).  Only
+// column k (rows >= k) is read at step k and it is not written then, so one
+// barrier per step suffices.  ln det of a leading block = sum of ln d_k.
+__global__ __launch_bounds__(64) void gauss_cmi_kernel(GaussJobs a) {
+    __shared__ double A[kGaussMaxVars][kGaussMaxVars + 1];
+    __shared__ int32_t ix[kGaussMaxVars];
+    const int lane = tid_x();
+    const int jb = bid_x();
+    const GaussJob J = a.jobs[jb];
+    double ylog[2] = {0.0, 0.0};
+    int bad = 0;
+    for (int f = 0; f < 2 && !bad; ++f) {
+        // f = 0: (Z, X, Y); f = 1: (Z, Y)
+        const int m = f == 0 ? J.dz + J.dx + J.dy : J.dz + J.dy;
+        const int ybeg = m - J.dy;
+        __syncthreads();
+        if (lane < m) ix[lane] = a.idx[J.off + ((f == 1 && lane >= J.dz) ? lane + J.dx : lane)];
+        __syncthreads();
+        if (lane < m) {
+            const int64_t cj = ix[lane];
+            for (int i = 0; i < m; ++i) A[i][lane] = a.cov[(int64_t)ix[i] * a.D + cj];
+        }
+        __syncthreads();
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) {
+            const double d = A[k][k];
+            if (!(d > 0.0)) {
+                bad = 1;
+                break;
+            }
+            if (k >= ybeg) acc += log(d);
+            if (lane > k && lane < m) {
+                const double t = A[lane][k] / d;
+                for (int i = lane; i < m; ++i) A[i][lane] -= A[i][k] * t;
+            }
+            __syncthreads();
+        }
+        ylog[f] = acc;
+    }
+    if (lane == 0) {
+        a.out[jb] = bad ? 0.0 : 0.5 * (ylog[1] - ylog[0]);
+        a.status[jb] = bad;
+    }
+}
+
+}  // namespace
+
+GaussChunks gauss_chunks(int64_t n) {
+    int64_t rows = (n + kGaussMaxChunks - 1) / kGaussMaxChunks;
+    if (rows < 256) rows = 256;
+    rows = (rows + kRB - 1) / kRB * kRB;
+    return GaussChunks{(int)rows, (int)((n + rows - 1) / rows)};
+}
+
+int launch_gauss_cov(const GaussCov &a, hipStream_t s) {
+    if (a.D < 1 || a.n < 1) return 0;
+    hipLaunchKernelGGL(gauss_colsum_kernel, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a);
+    const int pairs = a.n_tiles * (a.n_tiles + 1) / 2;
+    hipLaunchKernelGGL(gauss_gram_kernel, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0, s, a);
+    const int64_t entries = (int64_t)a.D * a.D;
+    hipLaunchKernelGGL(gauss_cov_reduce_kernel, dim3((unsigned)((entries + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gauss_cmi(const GaussJobs &a, hipStream_t s) {
+    if (a.n_jobs < 1) return 0;
+    hipLaunchKernelGGL(gauss_cmi_kernel, dim3((unsigned)a.n_jobs), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mte

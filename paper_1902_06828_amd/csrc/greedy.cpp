@@ -16,8 +16,10 @@
 //    is not significant; an empty X^S skips the omnibus test (p = 1).
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <cstring>
 
+#include "gauss.h"
 #include "runtime.h"
 
 namespace mte {
@@ -89,6 +91,9 @@ public:
     // real[n], surr[n][S]
     virtual int run(const Round &r, uint32_t tid0, std::vector<double> *real,
                     std::vector<double> *surr) = 0;
+    // true: no surrogates; the tests use the chi^2 null with `rows` samples
+    virtual bool analytic() const { return false; }
+    virtual int64_t rows() const { return 0; }
     double gpu_seconds = 0.0;
 };
 
@@ -209,8 +214,99 @@ private:
     uint64_t seed_;
 };
 
+// Gaussian executor: one float64 covariance matrix of every variable the
+// search can touch (target present, target lags 1..l_t, each candidate with
+// lags 1..l_s), computed once; each round is one launch of the estimate
+// kernel over index sets into that matrix.  No surrogates.
+class GaussExec : public RoundExec {
+public:
+    GaussExec(const float *dev_series, int64_t T, int l_m, int64_t N, int target, const int32_t *cands,
+              int n_cands, int l_s, int l_t)
+        : d_(dev_series), T_(T), lm_(l_m), N_(N), target_(target), ls_(l_s), lt_(l_t) {
+        for (int i = 0; i < n_cands; ++i) slot_[cands[i]] = i;
+        cols_.push_back(col(Var{target, 0}));
+        for (int l = 1; l <= l_t; ++l) cols_.push_back(col(Var{target, l}));
+        for (int i = 0; i < n_cands; ++i)
+            for (int l = 1; l <= l_s; ++l) cols_.push_back(col(Var{cands[i], l}));
+    }
+    bool analytic() const override { return true; }
+    int64_t rows() const override { return N_; }
+    int run(const Round &r, uint32_t, std::vector<double> *real, std::vector<double> *surr) override {
+        int rc;
+        hipStream_t s;
+        if ((rc = stream(&s))) return rc;
+        auto t0 = std::chrono::steady_clock::now();
+        if (!have_cov_) {
+            if ((int)cols_.size() > kGaussMaxD)
+                return fail(MTE_EINVAL, "%zu variables exceed the %d-column covariance limit", cols_.size(),
+                            kGaussMaxD);
+            if ((rc = gauss_covariance(cols_, N_, s, &work_, &cov_))) return rc;
+            have_cov_ = true;
+        }
+        const int n = (int)r.xs.size();
+        std::vector<GaussJob> jobs((size_t)n);
+        std::vector<int32_t> idx;
+        for (int j = 0; j < n; ++j) {
+            jobs[(size_t)j] = GaussJob{(int32_t)r.xs[j].size(), 1, (int32_t)r.zs[j].size(), (int32_t)idx.size()};
+            for (const Var &v : r.zs[j]) idx.push_back(index(v));
+            for (const Var &v : r.xs[j]) idx.push_back(index(v));
+            idx.push_back(0);
+        }
+        if ((rc = gauss_estimates(cov_.as<double>(), (int)cols_.size(), jobs, idx, s, &wj_, real))) return rc;
+        gpu_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        surr->clear();
+        return MTE_OK;
+    }
+    ~GaussExec() override {
+        if (s_) (void)hipStreamDestroy(s_);
+    }
+private:
+    const float *col(const Var &v) const { return d_ + (size_t)v.node * T_ + (lm_ - v.lag); }
+    int index(const Var &v) const {
+        if (v.node == target_) return v.lag;
+        return 1 + lt_ + slot_.at(v.node) * ls_ + (v.lag - 1);
+    }
+    int stream(hipStream_t *s) {
+        if (!s_) MTE_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+        *s = s_;
+        return MTE_OK;
+    }
+    const float *d_;
+    int64_t T_;
+    int lm_;
+    int64_t N_;
+    int target_, ls_, lt_;
+    std::map<int, int> slot_;
+    std::vector<const float *> cols_;
+    bool have_cov_ = false;
+    DevBuf work_, cov_, wj_;
+    hipStream_t s_ = nullptr;
+};
+
+// The three tests of a round: surrogate-based, or with the analytic null.
+static int test_max(const RoundExec &ex, const std::vector<double> &real, const std::vector<double> &surr, int S,
+                    double alpha, int *j, double *p, int *sig) {
+    if (!ex.analytic()) return stat_max(real.data(), surr.data(), (int)real.size(), S, alpha, j, p, sig);
+    const int n = (int)real.size();
+    *j = (int)(std::max_element(real.begin(), real.end()) - real.begin());
+    *p = p_max_analytic(real[(size_t)*j], n, ex.rows());
+    *sig = *p < alpha;
+    return MTE_OK;
+}
+
+static int test_min(const RoundExec &ex, const std::vector<double> &real, const std::vector<double> &surr, int S,
+                    double alpha, int *j, double *p, int *sig) {
+    if (!ex.analytic()) return stat_min(real.data(), surr.data(), (int)real.size(), S, alpha, j, p, sig);
+    const int n = (int)real.size();
+    *j = (int)(std::min_element(real.begin(), real.end()) - real.begin());
+    *p = p_min_analytic(real[(size_t)*j], n, ex.rows());
+    *sig = *p < alpha;
+    return MTE_OK;
+}
+
 static int greedy(RoundExec &ex, int target, const int32_t *cands, int n_cands, int l_s, int l_t,
                   double alpha, int S, mte_result *out) {
+    if (ex.analytic()) S = 0;
     uint32_t tid = 0;
     int64_t n_est = 0;
     std::vector<double> real, surr;
@@ -227,7 +323,7 @@ static int greedy(RoundExec &ex, int target, const int32_t *cands, int n_cands, 
         n_est += (int64_t)ycand.size() * (S + 1);
         int j, sig;
         double p;
-        if ((rc = stat_max(real.data(), surr.data(), (int)ycand.size(), S, alpha, &j, &p, &sig))) return rc;
+        if ((rc = test_max(ex, real, surr, S, alpha, &j, &p, &sig))) return rc;
         if (!sig) break;
         ysel.push_back(ycand[(size_t)j]);
         ystat.emplace_back(real[(size_t)j], p);
@@ -250,7 +346,7 @@ static int greedy(RoundExec &ex, int target, const int32_t *cands, int n_cands, 
         n_est += (int64_t)xcand.size() * (S + 1);
         int j, sig;
         double p;
-        if ((rc = stat_max(real.data(), surr.data(), (int)xcand.size(), S, alpha, &j, &p, &sig))) return rc;
+        if ((rc = test_max(ex, real, surr, S, alpha, &j, &p, &sig))) return rc;
         if (!sig) break;
         xsel.push_back(xcand[(size_t)j]);
         xstat.emplace_back(real[(size_t)j], p);
@@ -271,7 +367,7 @@ static int greedy(RoundExec &ex, int target, const int32_t *cands, int n_cands, 
         n_est += (int64_t)xsel.size() * (S + 1);
         int j, sig;
         double p;
-        if ((rc = stat_min(real.data(), surr.data(), (int)xsel.size(), S, alpha, &j, &p, &sig))) return rc;
+        if ((rc = test_min(ex, real, surr, S, alpha, &j, &p, &sig))) return rc;
         if (sig) break;
         xsel.erase(xsel.begin() + j);
         xstat.erase(xstat.begin() + j);
@@ -289,7 +385,12 @@ static int greedy(RoundExec &ex, int target, const int32_t *cands, int n_cands, 
         tid += 1;
         n_est += S + 1;
         omni = real[0];
-        if ((rc = stat_omnibus(omni, surr.data(), S, alpha, &omni_p, &omni_sig))) return rc;
+        if (ex.analytic()) {
+            omni_p = chi2_sf(2.0 * (double)ex.rows() * omni, (int)xsel.size());
+            omni_sig = omni_p < alpha;
+        } else if ((rc = stat_omnibus(omni, surr.data(), S, alpha, &omni_p, &omni_sig))) {
+            return rc;
+        }
     }
     out->n_target_past = (int)ysel.size();
     for (size_t i = 0; i < ysel.size(); ++i)
@@ -311,8 +412,12 @@ static int check_greedy_args(int P, int64_t T, int target, const int32_t *cands,
     if (!out || !cands || n_cands < 0) return fail(MTE_EINVAL, "null argument");
     if (P < 1 || target < 0 || target >= P) return fail(MTE_EINVAL, "target %d out of range", target);
     if (l_s < 1 || o.max_lag_target < 1) return fail(MTE_EINVAL, "maximum lags must be >= 1");
-    if (o.k < 1 || o.k > kMaxK) return fail(MTE_EINVAL, "k=%d out of range", o.k);
-    if (o.S < 1 || !(o.S * alpha > 1.0)) return fail(MTE_EINVAL, "S*alpha must exceed 1");
+    if (o.estimator != MTE_ESTIMATOR_KSG && o.estimator != MTE_ESTIMATOR_GAUSS)
+        return fail(MTE_EINVAL, "unknown estimator %d", o.estimator);
+    const bool gauss = o.estimator == MTE_ESTIMATOR_GAUSS;
+    if (!gauss && (o.k < 1 || o.k > kMaxK)) return fail(MTE_EINVAL, "k=%d out of range", o.k);
+    if (!gauss && (o.S < 1 || !(o.S * alpha > 1.0))) return fail(MTE_EINVAL, "S*alpha must exceed 1");
+    if (gauss && o.theiler != 0) return fail(MTE_EINVAL, "the Theiler window applies to the KSG estimator only");
     if (!(alpha > 0.0 && alpha < 1.0)) return fail(MTE_EINVAL, "alpha must be in (0,1)");
     for (int i = 0; i < n_cands; ++i) {
         if (cands[i] < 0 || cands[i] >= P) return fail(MTE_EINVAL, "candidate %d out of range", cands[i]);
@@ -321,9 +426,11 @@ static int check_greedy_args(int P, int64_t T, int target, const int32_t *cands,
             if (cands[j] == cands[i]) return fail(MTE_EINVAL, "duplicate candidate %d", cands[i]);
     }
     const int l_m = std::max(l_s, o.max_lag_target);
-    if (T <= (int64_t)l_m + o.k) return fail(MTE_EINVAL, "T=%lld too short", (long long)T);
-    int rc = validate_theiler(T - l_m, o.k, o.theiler);
-    if (rc) return rc;
+    if (T <= (int64_t)l_m + (gauss ? 1 : o.k)) return fail(MTE_EINVAL, "T=%lld too short", (long long)T);
+    if (!gauss) {
+        int rc = validate_theiler(T - l_m, o.k, o.theiler);
+        if (rc) return rc;
+    }
     if (T - l_m > 0x7fffffffLL) return fail(MTE_EINVAL, "T too long");
     if (!out->target_past || (n_cands > 0 && !out->sources))
         return fail(MTE_EINVAL, "result arrays must be allocated by the caller");
@@ -337,8 +444,12 @@ static mte_opts opts_or_default(const mte_opts *o) {
     d.max_lag_target = 5;
     d.seed = 0;
     d.theiler = 0;
+    d.estimator = MTE_ESTIMATOR_KSG;
     return o ? *o : d;
 }
+
+int series_pin(int32_t sid, const float **dev, int *P, int64_t *T);
+void series_unpin(int32_t sid);
 
 int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32_t *candidates,
                           int n_candidates, int max_lag_sources, double alpha, const mte_opts *opts,
@@ -347,6 +458,18 @@ int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32
     int rc = check_greedy_args(P, T, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
     if (rc) return rc;
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
+    if (o.estimator == MTE_ESTIMATOR_GAUSS) {
+        const float *dev;
+        int P2;
+        int64_t T2;
+        if ((rc = series_pin(sid, &dev, &P2, &T2))) return rc;
+        {
+            GaussExec ex(dev, T, l_m, T - l_m, target, candidates, n_candidates, max_lag_sources, o.max_lag_target);
+            rc = greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
+        }
+        series_unpin(sid);
+        return rc;
+    }
     ServedExec ex(sid, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
     return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
 }
@@ -387,6 +510,11 @@ int mte_select_sources(const float *data, int P, int64_t T, int target, const in
     DevBuf series;
     if ((rc = series.ensure(sizeof(float) * (size_t)P * T))) return rc;
     MTE_HIP(hipMemcpy(series.p, data, sizeof(float) * (size_t)P * T, hipMemcpyHostToDevice));
+    if (o.estimator == MTE_ESTIMATOR_GAUSS) {
+        GaussExec ex(series.as<float>(), T, l_m, T - l_m, target, candidates, n_candidates, max_lag_sources,
+                     o.max_lag_target);
+        return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
+    }
     DirectExec ex(series.as<float>(), T, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
     return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
 }

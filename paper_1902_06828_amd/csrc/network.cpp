@@ -84,6 +84,7 @@ int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, 
     base.max_lag_target = 5;
     base.seed = 0;
     base.theiler = 0;
+    base.estimator = MTE_ESTIMATOR_KSG;
     if (opts) base = *opts;
     int32_t sid = -1;
     int rc = mte_series_register(data, P, T, &sid);

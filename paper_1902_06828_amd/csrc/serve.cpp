@@ -295,6 +295,27 @@ int series_shape(int32_t sid, int *P, int64_t *T) {
     return MTE_OK;
 }
 
+// Device copy of a registered series for a caller that reads it directly
+// (the Gaussian greedy search); the series counts as in use until unpinned.
+int series_pin(int32_t sid, const float **dev, int *P, int64_t *T) {
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+    it->second.pending++;
+    *dev = it->second.buf->as<float>();
+    *P = it->second.P;
+    *T = it->second.T;
+    return MTE_OK;
+}
+
+void series_unpin(int32_t sid) {
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it != sv.series.end()) it->second.pending--;
+}
+
 }  // namespace mte
 
 using namespace mte;

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert mte.lib().mte_abi_version() == 2
+    assert mte.lib().mte_abi_version() == 3
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 100, 1000, 4097, 10000])
@@ -149,3 +149,38 @@ def test_link_metrics_matches_oracle():
             assert got[key] == ref[key]
         for key in ("precision", "recall", "specificity", "fpr"):
             assert (np.isnan(got[key]) and np.isnan(ref[key])) or got[key] == ref[key]
+
+
+def test_chi2_survival_matches_scipy():
+    # The analytic null of the Gaussian estimator: the library's finite
+    # incomplete-gamma series against scipy's independent implementation.
+    from scipy.stats import chi2
+    for dof in list(range(1, 41)) + [64, 127, 128]:
+        for x in [1e-8, 1e-3, 0.5, 1.0, 3.84, 10.0, 47.3, 150.0, 600.0, 1300.0]:
+            got, want = mte.mte_chi2_sf(x, dof), float(chi2.sf(x, dof))
+            if want > 1e-280:
+                assert got == pytest.approx(want, rel=1e-10, abs=0), (dof, x)
+            else:
+                assert got < 1e-270, (dof, x)
+    assert mte.mte_chi2_sf(0.0, 3) == 1.0
+    assert mte.mte_chi2_sf(-1.0, 1) == 1.0
+    with pytest.raises(mte.MteError):
+        mte.mte_chi2_sf(1.0, 0)
+
+
+def test_gauss_argument_validation():
+    g = np.random.default_rng(0)
+    x = g.standard_normal((1, 50)).astype(np.float32)
+    with pytest.raises(mte.MteError):
+        mte.cmi_gauss(x, x, np.zeros((63, 50), np.float32))     # 65 variables
+    with pytest.raises(mte.MteError):
+        mte.cmi_gauss(x[:, :1], x[:, :1])                       # N = 1
+    bad = x.copy()
+    bad[0, 3] = np.inf
+    with pytest.raises(mte.MteError):
+        mte.cmi_gauss(bad, x)
+    s = g.standard_normal((3, 200)).astype(np.float32)
+    with pytest.raises(mte.MteError, match="Theiler"):
+        mte.mte_select_sources(s, 0, [1, 2], estimator="gauss", theiler=2)
+    with pytest.raises(ValueError):
+        mte.mte_select_sources(s, 0, [1, 2], estimator="nope")
