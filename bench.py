@@ -181,6 +181,57 @@ def network_leg(mte):
             "precision": m["precision"], "recall": m["recall"], "specificity": m["specificity"]}
 
 
+PEAK_F64_TFLOPS = 78.6                 # MI355X fp64 (vector and matrix rates are equal)
+
+
+def gauss_leg(mte, torch, dev):
+    """The Gaussian estimator with its analytic null: network inference on the
+    same 10-node VAR (T = 10000; one covariance matrix per target, then one
+    Cholesky launch per greedy round), and the float64 Gram kernel timed with
+    HIP events on its stream, at the network's shape (D = 51 variables: target,
+    5 target lags, 9 sources x 5 lags; N = 9995) and at the largest covariance
+    the library takes (D = 512, N = 10^6).  Gram flops: one fma (2 flops) per
+    upper-triangle entry and row, D (D + 1) N."""
+    import synth
+    from oracle import network
+    series, links = synth.var_network(10, N_ROWS, seed=SEED)
+    mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, estimator="gauss")
+    t = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05,
+                                          estimator="gauss")
+    wall = (time.perf_counter() - t) / reps
+    est = int(sum(s["n_estimates"] for s in summ))
+    m = mte.mte_link_metrics(adj, network.truth_adjacency(10, links))
+    out = {"workload": "10-node VAR, T=10000, all targets, Gaussian estimator, analytic null, alpha=0.05, "
+                       "BH-FDR 0.05",
+           "wall_s": wall, "estimates": est, "precision": m["precision"], "recall": m["recall"],
+           "specificity": m["specificity"]}
+    gram = []
+    for D, n, reps in ((51, N_ROWS - 5, 20), (512, 1000000, 5)):
+        g = torch.Generator(device=dev).manual_seed(SEED)
+        V = torch.randn((D, n), generator=g, device=dev, dtype=torch.float32)
+        cov = torch.empty((D, D), dtype=torch.float64, device=dev)
+        mte.mte_gauss_covariance_dev(V, cov)
+        mte.mte_kernel_timing_stage("gauss_gram", reset=True)
+        mte.mte_kernel_timing(True)
+        t = time.perf_counter()
+        for _ in range(reps):
+            mte.mte_gauss_covariance_dev(V, cov)
+        call_ms = (time.perf_counter() - t) / reps * 1e3
+        mte.mte_kernel_timing(False)
+        launches, ms = mte.mte_kernel_timing_stage("gauss_gram", reset=True)
+        k_ms = ms / max(1, launches)
+        flops = float(D) * (D + 1) * n
+        tf = flops / (k_ms * 1e-3) / 1e12
+        gram.append({"D": D, "N": n, "kernel_ms": k_ms, "covariance_call_ms": call_ms, "tflops": tf,
+                     "frac_fp64_peak": tf / PEAK_F64_TFLOPS, "hbm_bytes_read": 4 * D * n})
+        del V, cov
+    out["gram"] = gram
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-network", action="store_true")
+    ap.add_argument("--no-gauss", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 1 GiB (256Mi float32 read + written) before the "
                          "timed region, as the reference for HBM byte counters")
@@ -325,6 +377,14 @@ def main():
         log(f"network: {net['wall_s']:.2f} s, {net['evals_per_s']:.1f} evals/s, precision {net['precision']:.2f} "
             f"recall {net['recall']:.2f}")
 
+    gl = None
+    if not args.no_gauss:
+        log("gauss: network inference with the Gaussian estimator, Gram kernel")
+        gl = gauss_leg(mte, torch, dev)
+        log(f"gauss: network {gl['wall_s'] * 1e3:.1f} ms, precision {gl['precision']:.2f} recall "
+            f"{gl['recall']:.2f}; gram " + ", ".join(f"D={g['D']} N={g['N']}: {g['kernel_ms']:.3f} ms "
+                                                     f"{g['tflops']:.1f} TF/s" for g in gl["gram"]))
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: C oracle on a bounded sample")
@@ -361,6 +421,7 @@ def main():
         "plain": plain,
         "served": srv,
         "network": net,
+        "gauss": gl,
     }
     print(json.dumps(line), flush=True)
 

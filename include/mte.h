@@ -192,6 +192,45 @@ int mte_chi2_sf(double x, int dof, double *out);
 int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_t *out);
 
 /* --------------------------------------------------------------------------
+ * Replications (trials).  With R replications of the same experiment the
+ * rows of an estimate are the embedded rows of every replication, one
+ * replication after the other: row i = r*n_r + t, N = R*n_r.  The Maximum
+ * statistic test section prefers surrogates that shuffle the order of the
+ * candidate's replications (the other variables keep theirs) and falls back to
+ * shuffling the embedded samples within each trial when the replications allow
+ * too few permutations:
+ *   MTE_SHUFFLE_REPLICATIONS  row (r, t) of surrogate s takes row
+ *                             (sigma(r), t), sigma = pi_{seed,cand,s} over R;
+ *   MTE_SHUFFLE_WITHIN        row (r, t) takes (r, pi_r(t)), pi_r the
+ *                             swap-or-not permutation of {0..n_r-1} keyed by
+ *                             h_r = mix64(h ^ ((r+1)*0x9E3779B97F4A7C15)) with
+ *                             h the key hash of (seed, cand, s) (R = 1: keyed
+ *                             by h itself, i.e. pi_{seed,cand,s} over N);
+ *   MTE_SHUFFLE_AUTO          REPLICATIONS when R! >= S, else WITHIN.
+ * The Theiler window is defined for one replication only (theiler must be 0
+ * when R > 1).
+ * ------------------------------------------------------------------------ */
+#define MTE_SHUFFLE_AUTO (-1)
+#define MTE_SHUFFLE_WITHIN 0
+#define MTE_SHUFFLE_REPLICATIONS 1
+
+/* The mode MTE_SHUFFLE_AUTO picks for R replications and S surrogates. */
+int mte_shuffle_mode(int R, int S, int *mode_out);
+
+/* Source rows of surrogate s (host computation of the kernels' definition):
+ * out[i] = the candidate row that row i takes.  N a multiple of R; mode
+ * WITHIN or REPLICATIONS (REPLICATIONS needs R >= 2). */
+int mte_permutation_rep(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, int R, int mode,
+                        uint32_t *out);
+
+/* cmi_ksg_surrogates over R replications (X, Y, Z [d][N] host buffers with
+ * the rows of replication r at r*N/R..), surrogate keys pi_{seed,cand,s}
+ * and the given shuffle mode (MTE_SHUFFLE_AUTO allowed). */
+int cmi_ksg_surrogates_rep(const float *X, int dx, const float *Y, int dy, const float *Z,
+                           int dz, int64_t N, int R, int k, int S, uint64_t seed, uint32_t cand,
+                           int mode, double *cmi_out, double *surr_out);
+
+/* --------------------------------------------------------------------------
  * Significance tests over CMI estimates (Statistical tests section, Table 1).
  * real[n] are the candidates' estimates, surr[n][S] their surrogates
  * (row-major).  S*alpha must exceed 1 (Maximum statistic test, item a).
@@ -209,7 +248,9 @@ int mte_omnibus(double real, const double *surr, int S, double alpha, double *p_
 
 /* --------------------------------------------------------------------------
  * Greedy source selection for one target (Inference algorithm section,
- * steps 1-4).  data: host float32 [P][T] row-major (one series per process).
+ * steps 1-4).  data: host float32 [P][T] row-major (one series per process),
+ * or [R][P][T] with mte_opts.replications = R > 1 (rows of replication r
+ * follow those of r-1; see Replications above).
  * Embedding rows t = L..T-1 with L = max(max_lag_target, max_lag_sources);
  * variable (node, lag) is data[node][t-lag].  Candidates: target lags
  * 1..max_lag_target, then each candidate source (given order) with lags
@@ -226,6 +267,10 @@ typedef struct {
     uint64_t seed;      /* surrogate key seed (default 0) */
     int theiler;        /* Theiler window of every estimate (default 0; KSG only) */
     int estimator;      /* MTE_ESTIMATOR_KSG (default) or MTE_ESTIMATOR_GAUSS */
+    int replications;   /* R >= 1 (default 1): data holds R replications [R][P][T], T per
+                           replication; the rows of all replications are pooled
+                           (N = R*(T-L)) and the surrogates follow MTE_SHUFFLE_AUTO;
+                           needs theiler = 0 when R > 1 (not for the _sid form) */
 } mte_opts;
 
 /* Estimators of the greedy search.  KSG: every test is a surrogate test
@@ -395,6 +440,8 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
  *   MTE_STAGE_FALLBACK   all-rows redo of the pairs the lists cannot decide
  *   MTE_STAGE_REDUCE     fixed-order digamma sums of the list path
  *   MTE_STAGE_PERMUTE    surrogate permutation of the X columns (both paths)
+ *   MTE_STAGE_GAUSS_GRAM float64 centered Gram product of the Gaussian estimator
+ *   MTE_STAGE_GAUSS_CMI  Cholesky estimates of the Gaussian estimator
  * ------------------------------------------------------------------------ */
 enum {
     MTE_STAGE_ALL_PAIRS = 0,
@@ -402,7 +449,9 @@ enum {
     MTE_STAGE_SCAN = 2,
     MTE_STAGE_FALLBACK = 3,
     MTE_STAGE_REDUCE = 4,
-    MTE_STAGE_PERMUTE = 5
+    MTE_STAGE_PERMUTE = 5,
+    MTE_STAGE_GAUSS_GRAM = 6,
+    MTE_STAGE_GAUSS_CMI = 7
 };
 int mte_kernel_timing(int enable);
 int mte_kernel_timing_read(int64_t *launches_out, double *total_ms_out, int reset);

@@ -38,6 +38,13 @@ from . import gauss, ksg, perm, stats
 
 
 def embed(series: np.ndarray, node: int, lag: int, l_m: int) -> np.ndarray:
+    """Column of variable (node, lag): rows t = l_m..T-1 of series[node][t-lag];
+    with replications (series [R][P][T]) the rows of every replication in
+    replication order."""
+    if series.ndim == 3:
+        t = series.shape[2]
+        return np.ascontiguousarray(np.concatenate([series[r, node, l_m - lag: t - lag]
+                                                    for r in range(series.shape[0])])[None, :])
     t = series.shape[1]
     return np.ascontiguousarray(series[node, l_m - lag: t - lag][None, :])
 
@@ -54,6 +61,11 @@ class _Run:
         self.n_estimates = 0
         self.est = estimator
         self.y = embed(series, target, 0, l_m)
+        self.reps = series.shape[0] if series.ndim == 3 else 1
+        self.mode = perm.shuffle_mode(self.reps, n_surr)
+
+    def source_rows(self, s, n_rows):
+        return perm.replication_source_rows(self.seed, self.tid, s, n_rows, self.reps, self.mode)
 
     def cols(self, variables):
         if not variables:
@@ -70,7 +82,7 @@ class _Run:
             z = self.cols(cond_of(c))
             real[j] = self.est(x, self.y, z, self.k)
             for s in range(self.n_surr):
-                p = perm.permutation(self.seed, self.tid, s, n_rows)
+                p = self.source_rows(s, n_rows)
                 surr[j, s] = self.est(ksg.permute_rows(x, p), self.y, z, self.k)
             self.tid += 1
             self.n_estimates += 1 + self.n_surr
@@ -87,10 +99,15 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
                    null: str = "surrogate"):
     """null = "surrogate": the KSG estimator (or `estimator`) with the
     surrogate tests.  null = "analytic": the Gaussian estimator with the
-    analytic (chi^2) null of oracle/gauss.py; no surrogates are drawn."""
+    analytic (chi^2) null of oracle/gauss.py; no surrogates are drawn.
+    series: [P][T], or [R][P][T] for R replications (rows of all
+    replications pooled; surrogates shuffle the replications of the candidate
+    when R! >= S, else the samples within each replication, oracle/perm.py)."""
     series = np.asarray(series)
     if series.dtype != np.float32:
         raise TypeError("series must be float32")
+    if series.ndim == 3 and theiler:
+        raise ValueError("the Theiler window is defined for a single replication")
     analytic = null == "analytic"
     if analytic:
         n_surr = 0
@@ -170,7 +187,7 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
         else:
             surr = np.empty(n_surr)
             for s in range(n_surr):
-                p_ = perm.permutation(seed, run.tid, s, n_rows)
+                p_ = run.source_rows(s, n_rows)
                 surr[s] = run.est(ksg.permute_rows(x, p_), run.y, z, k)
             run.tid += 1
             run.n_estimates += 1 + n_surr

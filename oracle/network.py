@@ -32,7 +32,7 @@ def infer_network(series, max_lag_sources: int = 5, max_lag_target: int = 5, alp
     """Returns (adjacency uint8 [P][P] with A[s][t] = 1 for an inferred link
     s -> t, per-target results of greedy.select_sources, FDR keep mask [P])."""
     series = np.asarray(series)
-    P = series.shape[0]
+    P = series.shape[-2]
     results = []
     for t in range(P):
         cands = [j for j in range(P) if j != t]

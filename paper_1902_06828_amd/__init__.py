@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     cmi_ksg_dev,
     cmi_ksg_diag,
     cmi_ksg_surrogates,
+    cmi_ksg_surrogates_rep,
     cmi_ksg_surrogates_dev,
     lib,
     mte_autocorr_decay_time,
@@ -36,11 +37,13 @@ from ._lib import (  # noqa: F401
     mte_min_statistic,
     mte_omnibus,
     mte_permutation,
+    mte_permutation_rep,
     mte_select_sources,
     mte_select_sources_sid,
     mte_serve_get_stats,
     mte_series_register,
     mte_series_release,
+    mte_shuffle_mode,
     mte_shutdown,
     mte_submit,
     mte_tile_configs,

@@ -28,7 +28,8 @@ class MteError(RuntimeError):
 
 class mte_opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("S", ctypes.c_int), ("max_lag_target", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int), ("estimator", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int), ("estimator", ctypes.c_int),
+                ("replications", ctypes.c_int)]
 
 
 class mte_var(ctypes.Structure):
@@ -110,7 +111,12 @@ SIGNATURES = {
     "mte_gauss_covariance_dev": [_P, _I, _I64, _I64, _P, _P],
     "mte_gauss_cmi_sets": [_P, _I, _I, _P, _P, _P, _P],
     "mte_chi2_sf": [_D, _I, _P],
+    "mte_shuffle_mode": [_I, _I, _P],
+    "mte_permutation_rep": [_U64, _U32, _U32, _I64, _I, _I, _P],
+    "cmi_ksg_surrogates_rep": [_P, _I, _P, _I, _P, _I, _I64, _I, _I, _I, _U64, _U32, _I, _P, _P],
 }
+
+SHUFFLE = {"auto": -1, "within": 0, "replications": 1}
 
 ESTIMATORS = {"ksg": 0, "gauss": 1}
 
@@ -314,25 +320,34 @@ def _result_dict(res, tp, src):
     }
 
 
-def _opts(k, S, max_lag_target, seed, theiler=0, estimator="ksg"):
+def _opts(k, S, max_lag_target, seed, theiler=0, estimator="ksg", replications=1):
     if estimator not in ESTIMATORS:
         raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
     return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed, theiler=theiler,
-                    estimator=ESTIMATORS[estimator])
+                    estimator=ESTIMATORS[estimator], replications=replications)
+
+
+def _series(data):
+    """float32 [P][T] (one replication) or [R][P][T] -> (array, R, P, T)."""
+    data = np.ascontiguousarray(data)
+    if data.dtype != np.float32 or data.ndim not in (2, 3):
+        raise TypeError("data must be float32 [P][T] or [R][P][T]")
+    if data.ndim == 2:
+        return data, 1, data.shape[0], data.shape[1]
+    return data, data.shape[0], data.shape[1], data.shape[2]
 
 
 def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, alpha: float = 0.05,
                        k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
                        estimator: str = "ksg"):
-    data = np.ascontiguousarray(data)
-    if data.dtype != np.float32 or data.ndim != 2:
-        raise TypeError("data must be float32 [P][T]")
+    """data: float32 [P][T], or [R][P][T] for R replications."""
+    data, R, P, T = _series(data)
     cands = np.ascontiguousarray(candidates, dtype=np.int32)
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
-    _check(lib().mte_select_sources(_ptr(data), data.shape[0], data.shape[1], target, _ptr(cands),
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R)
+    _check(lib().mte_select_sources(_ptr(data), P, T, target, _ptr(cands),
                                     len(cands), max_lag_sources, alpha, ctypes.byref(o),
                                     ctypes.byref(res)))
     return _result_dict(res, tp, src)
@@ -415,7 +430,8 @@ def mte_kernel_timing_read(reset: bool = False):
     return n.value, ms.value
 
 
-STAGES = {"all_pairs": 0, "build": 1, "scan": 2, "fallback": 3, "reduce": 4, "permute": 5}
+STAGES = {"all_pairs": 0, "build": 1, "scan": 2, "fallback": 3, "reduce": 4, "permute": 5, "gauss_gram": 6,
+          "gauss_cmi": 7}
 
 
 def mte_kernel_timing_stage(stage, reset: bool = False):
@@ -464,15 +480,13 @@ def mte_link_metrics(inferred, truth):
 def mte_infer_network(data, max_lag_sources: int = 5, alpha: float = 0.05, alpha_fdr: float = 0.05,
                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
                       n_threads: int = 0, estimator: str = "ksg"):
-    """Returns (adjacency uint8 [P][P], per-target summaries as dicts)."""
-    data = np.ascontiguousarray(data)
-    if data.dtype != np.float32 or data.ndim != 2:
-        raise TypeError("data must be float32 [P][T]")
-    P = data.shape[0]
+    """data: float32 [P][T], or [R][P][T] for R replications.  Returns
+    (adjacency uint8 [P][P], per-target summaries as dicts)."""
+    data, R, P, T = _series(data)
     adj = np.zeros((P, P), np.uint8)
     tgt = (mte_target_summary * P)()
-    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
-    _check(lib().mte_infer_network(_ptr(data), P, data.shape[1], max_lag_sources, alpha,
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R)
+    _check(lib().mte_infer_network(_ptr(data), P, T, max_lag_sources, alpha,
                                    alpha_fdr if alpha_fdr else 0.0, ctypes.byref(o), n_threads, _ptr(adj), tgt))
     summ = [{name: getattr(tgt[t], name) for name, _ in mte_target_summary._fields_} for t in range(P)]
     return adj, summ
@@ -520,3 +534,27 @@ def mte_chi2_sf(x: float, dof: int) -> float:
     out = ctypes.c_double()
     _check(lib().mte_chi2_sf(float(x), dof, ctypes.byref(out)))
     return out.value
+
+
+# ---------------------------------------------------------------- replications
+def mte_shuffle_mode(R: int, S: int) -> str:
+    out = ctypes.c_int()
+    _check(lib().mte_shuffle_mode(R, S, ctypes.byref(out)))
+    return {v: k for k, v in SHUFFLE.items()}[out.value]
+
+
+def mte_permutation_rep(seed: int, cand: int, s: int, n: int, R: int, mode: str):
+    """Source row of every row of surrogate s over R replications (host)."""
+    out = np.empty(n, np.uint32)
+    _check(lib().mte_permutation_rep(seed, cand, s, n, R, SHUFFLE[mode], _ptr(out)))
+    return out
+
+
+def cmi_ksg_surrogates_rep(X, Y, Z=None, k: int = 4, S: int = 20, R: int = 1, seed: int = 0, cand: int = 0,
+                           mode: str = "auto"):
+    """Estimate and S surrogates over R replications of N/R rows each."""
+    X, dx, Y, dy, Z, dz, n = _xyz(X, Y, Z)
+    out, surr = ctypes.c_double(), np.zeros(S, np.float64)
+    _check(lib().cmi_ksg_surrogates_rep(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, R, k, S, seed, cand,
+                                        SHUFFLE[mode], ctypes.byref(out), _ptr(surr)))
+    return out.value, surr

@@ -54,6 +54,34 @@ void permutation_host(uint64_t h, int64_t n, uint32_t *out) {
     }
 }
 
+void replication_source_rows_host(uint64_t h, int64_t n, int reps, int rep_shuffle, uint32_t *out) {
+    const int64_t nr = n / reps;
+    if (rep_shuffle) {
+        std::vector<uint32_t> sigma((size_t)reps);
+        permutation_host(h, reps, sigma.data());
+        for (int r = 0; r < reps; ++r)
+            for (int64_t t = 0; t < nr; ++t) out[r * nr + t] = (uint32_t)(sigma[(size_t)r] * nr + t);
+        return;
+    }
+    if (reps == 1) {
+        permutation_host(h, n, out);
+        return;
+    }
+    for (int r = 0; r < reps; ++r) {
+        permutation_host(mix64(h ^ ((uint64_t)(r + 1) * kGolden)), nr, out + r * nr);
+        for (int64_t t = 0; t < nr; ++t) out[r * nr + t] += (uint32_t)(r * nr);
+    }
+}
+
+// Replication shuffle when R! >= S (at least S distinct orderings), else
+// within-replication shuffle.
+int shuffle_mode(int reps, int S) {
+    if (reps < 2) return MTE_SHUFFLE_WITHIN;
+    double f = 1.0;
+    for (int r = 2; r <= reps && f < (double)S; ++r) f *= r;
+    return f >= (double)S ? MTE_SHUFFLE_REPLICATIONS : MTE_SHUFFLE_WITHIN;
+}
+
 // ---------------------------------------------------------------- helpers
 static thread_local hipStream_t t_stream = nullptr;
 
@@ -72,7 +100,8 @@ static void fill_keys(JobSpec &sp, int S, uint64_t seed, uint32_t cand) {
 // Host-buffer estimate with S surrogates; optional diagnostics.
 static int host_estimate(const float *X, int dx, const float *Y, int dy, const float *Z, int dz,
                          int64_t N, int k, int theiler, int S, uint64_t seed, uint32_t cand,
-                         double *cmi_out, float *eps_out, int32_t *nxz, int32_t *nyz, int32_t *nz) {
+                         double *cmi_out, float *eps_out, int32_t *nxz, int32_t *nyz, int32_t *nz,
+                         int reps = 1, int rep_shuffle = 0) {
     int rc;
     if ((rc = validate_dims(dx, dy, dz, N, k))) return rc;
     if ((rc = validate_theiler(N, k, theiler))) return rc;
@@ -102,6 +131,8 @@ static int host_estimate(const float *X, int dx, const float *Y, int dy, const f
     JobSpec sp;
     for (int c = 0; c < dx + dy + dz; ++c) sp.cols[c] = d + (size_t)c * N;
     sp.n = (int)N; sp.dx = dx; sp.dy = dy; sp.dz = dz; sp.k = k; sp.theiler = theiler;
+    sp.reps = reps;
+    sp.rep_shuffle = rep_shuffle;
     fill_keys(sp, S, seed, cand);
     sp.out = out.as<double>();
     if (diag) {
@@ -291,6 +322,40 @@ int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_
     if (N < 1 || N > 0x7fffffffLL) return fail(MTE_EINVAL, "N=%lld out of range", (long long)N);
     if (!out) return fail(MTE_EINVAL, "null output pointer");
     permutation_host(surrogate_key(seed, cand, s), N, out);
+    return MTE_OK;
+}
+
+int mte_shuffle_mode(int R, int S, int *mode_out) {
+    if (!mode_out || R < 1 || S < 1) return fail(MTE_EINVAL, "bad arguments");
+    *mode_out = shuffle_mode(R, S);
+    return MTE_OK;
+}
+
+int mte_permutation_rep(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, int R, int mode, uint32_t *out) {
+    if (N < 1 || N > 0x7fffffffLL) return fail(MTE_EINVAL, "N=%lld out of range", (long long)N);
+    if (!out) return fail(MTE_EINVAL, "null output pointer");
+    if (R < 1 || N % R) return fail(MTE_EINVAL, "N=%lld is not a multiple of R=%d", (long long)N, R);
+    if (mode != MTE_SHUFFLE_WITHIN && mode != MTE_SHUFFLE_REPLICATIONS) return fail(MTE_EINVAL, "bad mode %d", mode);
+    if (mode == MTE_SHUFFLE_REPLICATIONS && R < 2) return fail(MTE_EINVAL, "a replication shuffle needs R >= 2");
+    replication_source_rows_host(surrogate_key(seed, cand, s), N, R, mode == MTE_SHUFFLE_REPLICATIONS, out);
+    return MTE_OK;
+}
+
+int cmi_ksg_surrogates_rep(const float *X, int dx, const float *Y, int dy, const float *Z, int dz, int64_t N,
+                           int R, int k, int S, uint64_t seed, uint32_t cand, int mode, double *cmi_out,
+                           double *surr_out) {
+    if (S < 1) return fail(MTE_EINVAL, "S=%d must be >= 1", S);
+    if (!surr_out || !cmi_out) return fail(MTE_EINVAL, "null output pointer");
+    if (R < 1 || N % R) return fail(MTE_EINVAL, "N=%lld is not a multiple of R=%d", (long long)N, R);
+    if (mode == MTE_SHUFFLE_AUTO) mode = shuffle_mode(R, S);
+    if (mode != MTE_SHUFFLE_WITHIN && mode != MTE_SHUFFLE_REPLICATIONS) return fail(MTE_EINVAL, "bad mode %d", mode);
+    if (mode == MTE_SHUFFLE_REPLICATIONS && R < 2) return fail(MTE_EINVAL, "a replication shuffle needs R >= 2");
+    std::vector<double> all((size_t)S + 1);
+    int rc = host_estimate(X, dx, Y, dy, Z, dz, N, k, 0, S, seed, cand, all.data(), nullptr, nullptr, nullptr,
+                           nullptr, R, mode == MTE_SHUFFLE_REPLICATIONS);
+    if (rc) return rc;
+    *cmi_out = all[0];
+    std::memcpy(surr_out, all.data() + 1, sizeof(double) * S);
     return MTE_OK;
 }
 

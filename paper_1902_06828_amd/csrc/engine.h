@@ -64,6 +64,8 @@ struct Job {
     int set;
     float *xt;
     int theiler;                  // Theiler window w: pairs with |i - j| <= w are left out
+    int reps;                     // replications R (rows: R blocks of n/R, replication-major)
+    int rep_shuffle;              // surrogates shuffle the replication order (else rows within each)
 };
 
 // Neighbour lists of one (Y, Z) sample, shared by every job of a launch whose
@@ -180,5 +182,12 @@ int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream);
 uint64_t mix64(uint64_t z);
 uint64_t surrogate_key(uint64_t seed, uint32_t cand, uint32_t s);
 void permutation_host(uint64_t h, int64_t n, uint32_t *out);
+// Source rows of one surrogate over R replications of n/R rows (the device's
+// definition; R = 1 without rep_shuffle is permutation_host).
+void replication_source_rows_host(uint64_t h, int64_t n, int reps, int rep_shuffle, uint32_t *out);
+// MTE_SHUFFLE_REPLICATIONS when R! >= S, else MTE_SHUFFLE_WITHIN.
+int shuffle_mode(int reps, int S);
+// Blocks of the permute kernel for one estimate of a job.
+inline int64_t permute_blocks(int64_t n, int reps) { return (int64_t)reps * ((n / reps + 1023) / 1024); }
 
 }  // namespace mte

@@ -10,6 +10,24 @@
 
 namespace mte {
 
+// One launch, bracketed by HIP events on its stream when kernel timing is on.
+template <class F>
+static int timed_launch(int stage, hipStream_t s, F launch) {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = ctx().timing;
+    if (timed) {
+        MTE_HIP(hipEventCreate(&ev[0]));
+        MTE_HIP(hipEventCreate(&ev[1]));
+        MTE_HIP(hipEventRecord(ev[0], s));
+    }
+    if (launch()) return hip_fail(hipGetLastError(), "Gaussian estimator launch");
+    if (timed) {
+        MTE_HIP(hipEventRecord(ev[1], s));
+        record_timing_pair(stage, ev[0], ev[1]);
+    }
+    return MTE_OK;
+}
+
 // P(chi^2_dof > x) = Q(dof/2, x/2), the regularised upper incomplete gamma
 // function, for integer dof (h = x/2):
 //   dof = 2m:    Q = e^{-h} sum_{i=0}^{m-1} h^i / i!
@@ -57,7 +75,7 @@ int gauss_covariance(const std::vector<const float *> &cols_dev, int64_t n, hipS
     if (n < 2 || n > 0x7fffffffLL) return fail(MTE_EINVAL, "N=%lld out of range", (long long)n);
     const GaussChunks ch = gauss_chunks(n);
     const size_t ptr_bytes = (sizeof(void *) * (size_t)D + 255) / 256 * 256;
-    const size_t mean_bytes = sizeof(double) * (size_t)ch.count * D;
+    const size_t mean_bytes = sizeof(double) * (size_t)(ch.count + 1) * D;
     const size_t part_bytes = sizeof(double) * (size_t)ch.count * D * D;
     int rc;
     if ((rc = work->ensure(ptr_bytes + mean_bytes + part_bytes))) return rc;
@@ -70,11 +88,16 @@ int gauss_covariance(const std::vector<const float *> &cols_dev, int64_t n, hipS
     a.n = (int)n;
     a.chunk_rows = ch.rows;
     a.n_chunks = ch.count;
-    a.n_tiles = (D + kGaussTile - 1) / kGaussTile;
+    a.tile = 64;
+    a.n_tiles = (D + a.tile - 1) / a.tile;
     a.part_mean = reinterpret_cast<double *>(w + ptr_bytes);
+    a.mean = a.part_mean + (size_t)ch.count * D;
     a.part = reinterpret_cast<double *>(w + ptr_bytes + mean_bytes);
     a.cov = cov->as<double>();
-    if (launch_gauss_cov(a, s)) return fail(MTE_EDEVICE, "covariance launch failed");
+    if (launch_gauss_colsum(a, s)) return hip_fail(hipGetLastError(), "column-sum launch");
+    int rc2;
+    if ((rc2 = timed_launch(kStageGaussGram, s, [&] { return launch_gauss_gram(a, s); }))) return rc2;
+    if (launch_gauss_cov_reduce(a, s)) return hip_fail(hipGetLastError(), "covariance reduce launch");
     MTE_HIP(hipStreamSynchronize(s));
     return MTE_OK;
 }
@@ -108,7 +131,7 @@ int gauss_estimates(const double *cov_dev, int D, const std::vector<GaussJob> &j
     a.out = reinterpret_cast<double *>(w + jb + ib);
     a.status = reinterpret_cast<int32_t *>(w + jb + ib + ob);
     a.n_jobs = n;
-    if (launch_gauss_cmi(a, s)) return fail(MTE_EDEVICE, "estimate launch failed");
+    if ((rc = timed_launch(kStageGaussCmi, s, [&] { return launch_gauss_cmi(a, s); }))) return rc;
     std::vector<int32_t> st((size_t)n);
     MTE_HIP(hipMemcpyAsync(out->data(), a.out, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s));
     MTE_HIP(hipMemcpyAsync(st.data(), a.status, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));

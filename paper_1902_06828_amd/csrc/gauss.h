@@ -22,7 +22,6 @@ namespace mte {
 
 constexpr int kGaussMaxD = 512;        // columns of one covariance matrix
 constexpr int kGaussMaxVars = 64;      // dx + dy + dz of one estimate
-constexpr int kGaussTile = 64;         // Gram tile (columns per side)
 constexpr int kGaussRowStage = 32;     // rows staged in LDS per step
 constexpr int kGaussMaxChunks = 256;
 
@@ -35,8 +34,10 @@ GaussChunks gauss_chunks(int64_t n);
 
 struct GaussCov {
     const float *const *cols;   // device array of D column pointers, N floats each
-    int D, n, chunk_rows, n_chunks, n_tiles;
+    int D, n, chunk_rows, n_chunks;
+    int tile, n_tiles;          // Gram tile side (64), tiles per side
     double *part_mean;          // [n_chunks][D]
+    double *mean;               // [D]
     double *part;               // [n_chunks][D][D]
     double *cov;                // [D][D], symmetric
 };
@@ -56,7 +57,9 @@ struct GaussJobs {
     int n_jobs;
 };
 
-int launch_gauss_cov(const GaussCov &a, hipStream_t s);
+int launch_gauss_colsum(const GaussCov &a, hipStream_t s);
+int launch_gauss_gram(const GaussCov &a, hipStream_t s);
+int launch_gauss_cov_reduce(const GaussCov &a, hipStream_t s);
 int launch_gauss_cmi(const GaussJobs &a, hipStream_t s);
 
 // Chi-squared survival function P(chi^2_dof > x) for integer dof >= 1.

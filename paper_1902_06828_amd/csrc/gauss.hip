@@ -1,9 +1,10 @@
 // Gaussian estimator kernels (gfx950): the float64 covariance of a set of
 // columns and, from it, I(X;Y|Z) of many (X, Y, Z) index sets.
 //
-//   colsum   per row chunk and column, the float64 sum of the chunk's rows
-//            (lane-strided, then a fixed butterfly);
-//   gram     per row chunk and 64x64 tile of the upper triangle, the centered
+//   colsum   per row chunk and column (one wave), the float64 sum of the
+//            chunk's rows (lane-strided partial sums, then a fixed butterfly),
+//            then per column the mean of the chunk sums (the same pattern);
+//   gram     per row chunk and tile of the upper triangle, the centered
 //            cross products sum_r (a_r - mean_a)(b_r - mean_b) in float64, one
 //            fma chain per entry over the chunk's rows in order;
 //   reduce   per entry, the chunk partials summed in chunk order, / N.
@@ -27,9 +28,8 @@ namespace mte {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kT = kGaussTile;
 constexpr int kRB = kGaussRowStage;
-constexpr int kLd = kT + 2;   // LDS row stride (doubles), keeps 16-byte alignment
+constexpr int kGramTM = 4;
 
 __device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
 __device__ __forceinline__ int bid_x() { return (int)__builtin_amdgcn_workgroup_id_x(); }
@@ -41,18 +41,39 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(kThreads) void gauss_colsum_kernel(GaussCov a) {
-    const int lane = tid_x() & 63, wave = tid_x() >> 6;
-    const int c = bid_x();
+// One wave per (row chunk, column): lane l keeps four partial sums over the
+// rows r0 + l + 64 (4m + u), u = 0..3 (four loads in flight per lane), adds
+// them as (s0 + s1) + (s2 + s3), and a fixed butterfly sums the lanes.
+__global__ __launch_bounds__(64) void gauss_colsum_kernel(GaussCov a) {
+    const int lane = tid_x();
+    const int c = bid_x(), col = bid_y();
     const int r0 = c * a.chunk_rows;
     const int r1 = min(a.n, r0 + a.chunk_rows);
-    for (int col = wave; col < a.D; col += kThreads / 64) {
-        const float *p = a.cols[col];
-        double s = 0.0;
-        for (int r = r0 + lane; r < r1; r += 64) s += (double)p[r];
-        s = wave_sum_f64(s);
-        if (lane == 0) a.part_mean[(int64_t)c * a.D + col] = s;
+    const float *p = a.cols[col];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int r = r0 + lane;
+    for (; r + 192 < r1; r += 256) {
+        const float v0 = p[r], v1 = p[r + 64], v2 = p[r + 128], v3 = p[r + 192];
+        s[0] += (double)v0;
+        s[1] += (double)v1;
+        s[2] += (double)v2;
+        s[3] += (double)v3;
     }
+    if (r < r1) s[0] += (double)p[r];
+    if (r + 64 < r1) s[1] += (double)p[r + 64];
+    if (r + 128 < r1) s[2] += (double)p[r + 128];
+    double t = wave_sum_f64((s[0] + s[1]) + (s[2] + s[3]));
+    if (lane == 0) a.part_mean[(int64_t)c * a.D + col] = t;
+}
+
+// Column means from the chunk sums: one wave per column, lane l adds the
+// chunks l, l+64, ... in order, a fixed butterfly adds the lanes.
+__global__ __launch_bounds__(64) void gauss_mean_kernel(GaussCov a) {
+    const int lane = tid_x(), col = bid_x();
+    double s = 0.0;
+    for (int h = lane; h < a.n_chunks; h += 64) s += a.part_mean[(int64_t)h * a.D + col];
+    s = wave_sum_f64(s);
+    if (lane == 0) a.mean[col] = s / (double)a.n;
 }
 
 // Upper-triangle tile pair y -> (tp, tq), tp <= tq.
@@ -66,37 +87,42 @@ __device__ __forceinline__ void tile_pair(int y, int n_tiles, int *tp, int *tq) 
     *tq = p + y;
 }
 
+// TM x TM entries per thread, tiles of 16 TM columns a side.  Each entry is
+// one fma chain over the chunk's rows in order, whatever the tile.  TM = 4
+// (64-column tiles, 124 VGPRs, 4 waves per SIMD) is used: TM = 8 needs 256
+// VGPRs, runs one wave per SIMD and leaves the tile loads unhidden (1.8x
+// slower at D = 512, N = 10^6).
+template <int TM>
 __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
-    __shared__ double mu[2][kT];
-    __shared__ __align__(16) double As[kRB][kLd];
-    __shared__ __align__(16) double Bs[kRB][kLd];
+    constexpr int T = 16 * TM;        // tile side
+    constexpr int LD = T + 2;         // LDS row stride (doubles), 16-byte aligned rows
+    __shared__ double mu[2][T];
+    __shared__ __align__(16) double As[kRB][LD];
+    __shared__ __align__(16) double Bs[kRB][LD];
     const int tid = tid_x();
     const int c = bid_x();
     int tp, tq;
     tile_pair(bid_y(), a.n_tiles, &tp, &tq);
-    const int p0 = tp * kT, q0 = tq * kT;
+    const int p0 = tp * T, q0 = tq * T;
     const int r0 = c * a.chunk_rows;
     const int r1 = min(a.n, r0 + a.chunk_rows);
 
-    if (tid < 2 * kT) {
-        const int col = (tid < kT ? p0 : q0 - kT) + tid;
-        double s = 0.0;
-        if (col < a.D)
-            for (int h = 0; h < a.n_chunks; ++h) s += a.part_mean[(int64_t)h * a.D + col];
-        mu[tid / kT][tid % kT] = s / (double)a.n;
+    for (int u = tid; u < 2 * T; u += kThreads) {
+        const int col = (u < T ? p0 : q0 - T) + u;
+        mu[u / T][u % T] = col < a.D ? a.mean[col] : 0.0;
     }
 
-    const int ty = tid >> 4, tx = tid & 15;   // rows ty*4.., columns tx*4.. of the tile
-    double acc[4][4];
+    const int ty = tid >> 4, tx = tid & 15;   // rows ty*TM.., columns tx*TM.. of the tile
+    double acc[TM][TM];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < TM; ++j) acc[i][j] = 0.0;
 
     for (int rs = r0; rs < r1; rs += kRB) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kRB * kT / kThreads; ++m) {
+        for (int m = 0; m < kRB * T / kThreads; ++m) {
             const int e = tid + m * kThreads;
             const int r = e % kRB, col = e / kRB;
             const int row = rs + r;
@@ -109,28 +135,32 @@ __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
             Bs[r][col] = vb;
         }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
         for (int r = 0; r < kRB; ++r) {
-            const double2 a01 = *reinterpret_cast<const double2 *>(&As[r][ty * 4]);
-            const double2 a23 = *reinterpret_cast<const double2 *>(&As[r][ty * 4 + 2]);
-            const double2 b01 = *reinterpret_cast<const double2 *>(&Bs[r][tx * 4]);
-            const double2 b23 = *reinterpret_cast<const double2 *>(&Bs[r][tx * 4 + 2]);
-            const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-            const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+            double av[TM], bv[TM];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int h = 0; h < TM; h += 2) {
+                const double2 x = *reinterpret_cast<const double2 *>(&As[r][ty * TM + h]);
+                const double2 y = *reinterpret_cast<const double2 *>(&Bs[r][tx * TM + h]);
+                av[h] = x.x;
+                av[h + 1] = x.y;
+                bv[h] = y.x;
+                bv[h + 1] = y.y;
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
         }
     }
     double *out = a.part + (int64_t)c * a.D * a.D;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int p = p0 + ty * 4 + i;
+    for (int i = 0; i < TM; ++i) {
+        const int p = p0 + ty * TM + i;
         if (p >= a.D) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int q = q0 + tx * 4 + j;
+        for (int j = 0; j < TM; ++j) {
+            const int q = q0 + tx * TM + j;
             if (q < a.D) out[(int64_t)p * a.D + q] = acc[i][j];
         }
     }
@@ -199,16 +229,29 @@ __global__ __launch_bounds__(64) void gauss_cmi_kernel(GaussJobs a) {
 
 GaussChunks gauss_chunks(int64_t n) {
     int64_t rows = (n + kGaussMaxChunks - 1) / kGaussMaxChunks;
-    if (rows < 256) rows = 256;
+    if (rows < 64) rows = 64;
     rows = (rows + kRB - 1) / kRB * kRB;
     return GaussChunks{(int)rows, (int)((n + rows - 1) / rows)};
 }
 
-int launch_gauss_cov(const GaussCov &a, hipStream_t s) {
+int launch_gauss_colsum(const GaussCov &a, hipStream_t s) {
     if (a.D < 1 || a.n < 1) return 0;
-    hipLaunchKernelGGL(gauss_colsum_kernel, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(gauss_colsum_kernel, dim3((unsigned)a.n_chunks, (unsigned)a.D), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(gauss_mean_kernel, dim3((unsigned)a.D), dim3(64), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gauss_gram(const GaussCov &a, hipStream_t s) {
+    if (a.D < 1 || a.n < 1) return 0;
+    if (a.tile != 16 * kGramTM) return -1;
     const int pairs = a.n_tiles * (a.n_tiles + 1) / 2;
-    hipLaunchKernelGGL(gauss_gram_kernel, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(gauss_gram_kernel<kGramTM>, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0,
+                       s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gauss_cov_reduce(const GaussCov &a, hipStream_t s) {
+    if (a.D < 1 || a.n < 1) return 0;
     const int64_t entries = (int64_t)a.D * a.D;
     hipLaunchKernelGGL(gauss_cov_reduce_kernel, dim3((unsigned)((entries + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, a);

@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "gauss.h"
+#include "greedy.h"
 #include "runtime.h"
 
 namespace mte {
@@ -97,12 +98,34 @@ public:
     double gpu_seconds = 0.0;
 };
 
+static int build_embedding(const float *dev_data, int R, int P, int64_t T, int l_m, hipStream_t s, DevBuf *buf,
+                           Columns *c) {
+    const int64_t nr = T - l_m, N = (int64_t)R * nr;
+    if (N > 0x7fffffffLL) return fail(MTE_EINVAL, "R*(T-L) exceeds 2^31-1 rows");
+    int rc;
+    if ((rc = buf->ensure(sizeof(float) * (size_t)P * (l_m + 1) * N))) return rc;
+    float *e = buf->as<float>();
+    for (int node = 0; node < P; ++node)
+        for (int lag = 0; lag <= l_m; ++lag)
+            MTE_HIP(hipMemcpy2DAsync(e + ((size_t)node * (l_m + 1) + lag) * N, sizeof(float) * nr,
+                                     dev_data + (size_t)node * T + (l_m - lag), sizeof(float) * (size_t)P * T,
+                                     sizeof(float) * nr, R, hipMemcpyDeviceToDevice, s));
+    MTE_HIP(hipStreamSynchronize(s));
+    c->series = dev_data;
+    c->T = T;
+    c->l_m = l_m;
+    c->emb = e;
+    c->N = N;
+    c->reps = R;
+    return MTE_OK;
+}
+
 // Direct executor: every round is one batched launch.
 class DirectExec : public RoundExec {
 public:
-    DirectExec(const float *dev_series, int64_t T, int l_m, int64_t N, int target, int k, int S,
-               uint64_t seed, int theiler)
-        : d_(dev_series), T_(T), lm_(l_m), N_(N), target_(target), k_(k), S_(S), w_(theiler), seed_(seed) {}
+    DirectExec(const Columns &cols, int64_t N, int target, int k, int S, uint64_t seed, int theiler)
+        : c_(cols), N_(N), target_(target), k_(k), S_(S), w_(theiler), seed_(seed),
+          rep_shuffle_(cols.reps > 1 && shuffle_mode(cols.reps, S) == MTE_SHUFFLE_REPLICATIONS) {}
     int run(const Round &r, uint32_t tid0, std::vector<double> *real, std::vector<double> *surr) override {
         const int n = (int)r.xs.size();
         const int E = S_ + 1;
@@ -121,6 +144,8 @@ public:
             sp.dz = (int)r.zs[j].size();
             sp.k = k_;
             sp.theiler = w_;
+            sp.reps = c_.reps;
+            sp.rep_shuffle = rep_shuffle_;
             sp.keys.resize((size_t)E);
             sp.keys[0] = EstKey{0, 1, 0};
             for (int s = 0; s < S_; ++s)
@@ -147,18 +172,17 @@ public:
         if (s_) (void)hipStreamDestroy(s_);
     }
 private:
-    const float *col(const Var &v) const { return d_ + (size_t)v.node * T_ + (lm_ - v.lag); }
+    const float *col(const Var &v) const { return c_.col(v.node, v.lag); }
     int stream(hipStream_t *s) {
         if (!s_) MTE_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
         *s = s_;
         return MTE_OK;
     }
-    const float *d_;
-    int64_t T_;
-    int lm_;
+    Columns c_;
     int64_t N_;
     int target_, k_, S_, w_;
     uint64_t seed_;
+    int rep_shuffle_;
     DevBuf out_;
     hipStream_t s_ = nullptr;
 };
@@ -220,9 +244,8 @@ private:
 // kernel over index sets into that matrix.  No surrogates.
 class GaussExec : public RoundExec {
 public:
-    GaussExec(const float *dev_series, int64_t T, int l_m, int64_t N, int target, const int32_t *cands,
-              int n_cands, int l_s, int l_t)
-        : d_(dev_series), T_(T), lm_(l_m), N_(N), target_(target), ls_(l_s), lt_(l_t) {
+    GaussExec(const Columns &cols, int64_t N, int target, const int32_t *cands, int n_cands, int l_s, int l_t)
+        : c_(cols), N_(N), target_(target), ls_(l_s), lt_(l_t) {
         for (int i = 0; i < n_cands; ++i) slot_[cands[i]] = i;
         cols_.push_back(col(Var{target, 0}));
         for (int l = 1; l <= l_t; ++l) cols_.push_back(col(Var{target, l}));
@@ -261,7 +284,7 @@ public:
         if (s_) (void)hipStreamDestroy(s_);
     }
 private:
-    const float *col(const Var &v) const { return d_ + (size_t)v.node * T_ + (lm_ - v.lag); }
+    const float *col(const Var &v) const { return c_.col(v.node, v.lag); }
     int index(const Var &v) const {
         if (v.node == target_) return v.lag;
         return 1 + lt_ + slot_.at(v.node) * ls_ + (v.lag - 1);
@@ -271,9 +294,7 @@ private:
         *s = s_;
         return MTE_OK;
     }
-    const float *d_;
-    int64_t T_;
-    int lm_;
+    Columns c_;
     int64_t N_;
     int target_, ls_, lt_;
     std::map<int, int> slot_;
@@ -426,12 +447,15 @@ static int check_greedy_args(int P, int64_t T, int target, const int32_t *cands,
             if (cands[j] == cands[i]) return fail(MTE_EINVAL, "duplicate candidate %d", cands[i]);
     }
     const int l_m = std::max(l_s, o.max_lag_target);
+    const int R = o.replications;
+    if (R < 1) return fail(MTE_EINVAL, "replications=%d must be >= 1", R);
+    if (R > 1 && o.theiler) return fail(MTE_EINVAL, "the Theiler window needs a single replication");
     if (T <= (int64_t)l_m + (gauss ? 1 : o.k)) return fail(MTE_EINVAL, "T=%lld too short", (long long)T);
     if (!gauss) {
         int rc = validate_theiler(T - l_m, o.k, o.theiler);
         if (rc) return rc;
     }
-    if (T - l_m > 0x7fffffffLL) return fail(MTE_EINVAL, "T too long");
+    if ((int64_t)R * (T - l_m) > 0x7fffffffLL) return fail(MTE_EINVAL, "R*(T-L) exceeds 2^31-1 rows");
     if (!out->target_past || (n_cands > 0 && !out->sources))
         return fail(MTE_EINVAL, "result arrays must be allocated by the caller");
     return MTE_OK;
@@ -445,11 +469,24 @@ static mte_opts opts_or_default(const mte_opts *o) {
     d.seed = 0;
     d.theiler = 0;
     d.estimator = MTE_ESTIMATOR_KSG;
+    d.replications = 1;
     return o ? *o : d;
 }
 
 int series_pin(int32_t sid, const float **dev, int *P, int64_t *T);
 void series_unpin(int32_t sid);
+
+// Greedy search of one target over resident columns (arguments checked).
+int select_sources_columns(const Columns &c, int target, const int32_t *candidates, int n_candidates,
+                           int max_lag_sources, double alpha, const mte_opts &o, mte_result *out) {
+    const int64_t N = (int64_t)c.reps * (c.T - c.l_m);
+    if (o.estimator == MTE_ESTIMATOR_GAUSS) {
+        GaussExec ex(c, N, target, candidates, n_candidates, max_lag_sources, o.max_lag_target);
+        return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
+    }
+    DirectExec ex(c, N, target, o.k, o.S, o.seed, o.theiler);
+    return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
+}
 
 int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32_t *candidates,
                           int n_candidates, int max_lag_sources, double alpha, const mte_opts *opts,
@@ -457,22 +494,53 @@ int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32
     const mte_opts o = opts_or_default(opts);
     int rc = check_greedy_args(P, T, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
     if (rc) return rc;
+    if (o.replications != 1)
+        return fail(MTE_EINVAL, "a registered series has one replication (use mte_select_sources or "
+                                "mte_infer_network for replications)");
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
     if (o.estimator == MTE_ESTIMATOR_GAUSS) {
         const float *dev;
         int P2;
         int64_t T2;
         if ((rc = series_pin(sid, &dev, &P2, &T2))) return rc;
-        {
-            GaussExec ex(dev, T, l_m, T - l_m, target, candidates, n_candidates, max_lag_sources, o.max_lag_target);
-            rc = greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
-        }
+        Columns c;
+        c.series = dev;
+        c.T = T;
+        c.l_m = l_m;
+        rc = select_sources_columns(c, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
         series_unpin(sid);
         return rc;
     }
     ServedExec ex(sid, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
     return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
 }
+
+// Device copy of a host series [R][P][T] (R = o.replications) and its
+// columns; with R > 1 the embedding of every (node, lag <= l_m) is gathered.
+int resident_columns(const float *data, int P, int64_t T, int l_m, int R, hipStream_t s, DevBuf *series,
+                     DevBuf *emb, Columns *c) {
+    int rc;
+    const size_t count = (size_t)R * P * T;
+    if ((rc = validate_host_finite(data, (int64_t)count, "data"))) return rc;
+    if ((rc = series->ensure(sizeof(float) * count))) return rc;
+    MTE_HIP(hipMemcpyAsync(series->p, data, sizeof(float) * count, hipMemcpyHostToDevice, s));
+    MTE_HIP(hipStreamSynchronize(s));
+    if (R > 1) return build_embedding(series->as<float>(), R, P, T, l_m, s, emb, c);
+    c->series = series->as<float>();
+    c->T = T;
+    c->l_m = l_m;
+    c->emb = nullptr;
+    c->N = T - l_m;
+    c->reps = 1;
+    return MTE_OK;
+}
+
+int greedy_check(int P, int64_t T, int target, const int32_t *cands, int n_cands, int l_s, double alpha,
+                 const mte_opts &o, mte_result *out) {
+    return check_greedy_args(P, T, target, cands, n_cands, l_s, alpha, o, out);
+}
+
+mte_opts greedy_opts(const mte_opts *o) { return opts_or_default(o); }
 
 }  // namespace mte
 
@@ -504,19 +572,16 @@ int mte_select_sources(const float *data, int P, int64_t T, int target, const in
     int rc = check_greedy_args(P, T, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
     if (rc) return rc;
     if (!data) return fail(MTE_EINVAL, "null data");
-    if ((rc = validate_host_finite(data, (int64_t)P * T, "data"))) return rc;
     if ((rc = ensure_init())) return rc;
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
-    DevBuf series;
-    if ((rc = series.ensure(sizeof(float) * (size_t)P * T))) return rc;
-    MTE_HIP(hipMemcpy(series.p, data, sizeof(float) * (size_t)P * T, hipMemcpyHostToDevice));
-    if (o.estimator == MTE_ESTIMATOR_GAUSS) {
-        GaussExec ex(series.as<float>(), T, l_m, T - l_m, target, candidates, n_candidates, max_lag_sources,
-                     o.max_lag_target);
-        return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
-    }
-    DirectExec ex(series.as<float>(), T, l_m, T - l_m, target, o.k, o.S, o.seed, o.theiler);
-    return greedy(ex, target, candidates, n_candidates, max_lag_sources, o.max_lag_target, alpha, o.S, out);
+    hipStream_t s;
+    MTE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    DevBuf series, emb;
+    Columns c;
+    rc = resident_columns(data, P, T, l_m, o.replications, s, &series, &emb, &c);
+    (void)hipStreamDestroy(s);
+    if (rc) return rc;
+    return select_sources_columns(c, target, candidates, n_candidates, max_lag_sources, alpha, o, out);
 }
 
 }  // extern "C"

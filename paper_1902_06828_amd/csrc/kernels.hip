@@ -32,14 +32,33 @@ __device__ __forceinline__ int n_rounds_dev(int64_t n) {
 }
 
 // ------------------------------------------------------------------ permute
-// xp[e][c][i] = X_c[pi_e(i)] (or, for the list path, xt[c][i][e]) for every
-// job, estimate and row.  One block per
-// (job, estimate, 1024-row chunk); the block derives the round keys in LDS.
+// xp[e][c][i] = X_c[src_e(i)] (or, for the list path, xt[c][i][e]) for every
+// job, estimate and row.  Rows are R = J.reps replications of nr = n/R rows
+// (R = 1: one block of all rows).  One thread block per (job, estimate,
+// replication, 1024-row chunk of the replication); the block derives one
+// swap-or-not key schedule in LDS:
+//   replication shuffle (rep_shuffle): row (r, t) takes (sigma(r), t), sigma
+//     the permutation of {0..R-1} keyed by the estimate's hash h;
+//   within-replication shuffle: row (r, t) takes (r, pi_r(t)), pi_r the
+//     permutation of {0..nr-1} keyed by h for R = 1 and by
+//     mix64(h ^ (r+1) G) for R > 1.
+__device__ __forceinline__ uint32_t swap_or_not(uint32_t x, uint32_t n, int rounds, const uint64_t *rk,
+                                                const uint32_t *kk) {
+    for (int r = 0; r < rounds; ++r) {
+        const uint32_t k = kk[r];
+        const uint32_t xp = (x <= k) ? (k - x) : (k - x + n);
+        const uint32_t hi = x > xp ? x : xp;
+        if (dmix64((uint64_t)hi ^ rk[r]) >> 63) x = xp;
+    }
+    return x;
+}
+
 __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
                                                      const int64_t *__restrict__ blk_off) {
     __shared__ uint64_t s_rk[192];
     __shared__ uint32_t s_k[192];
     __shared__ int s_job;
+    __shared__ uint32_t s_src_rep;
     const int64_t b = blockIdx.x;
     if (threadIdx.x == 0) {
         int lo = 0, hi = n_jobs - 1;
@@ -52,32 +71,41 @@ __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jo
     __syncthreads();
     const Job &J = jobs[s_job];
     const int64_t local = b - blk_off[s_job];
-    const int chunks = (J.n + 1023) / 1024;
-    const int e = (int)(local / chunks);
-    const int c0 = (int)(local % chunks) * 1024;
+    const int reps = J.reps;
+    const int nr = J.n / reps;
+    const int cpr = (nr + 1023) / 1024;
+    const int e = (int)(local / ((int64_t)reps * cpr));
+    const int rem = (int)(local % ((int64_t)reps * cpr));
+    const int rep = rem / cpr;
+    const int c0 = (rem % cpr) * 1024;
     const EstKey key = J.keys[e];
-    const int rounds = n_rounds_dev(J.n);
+    // key schedule: domain dn, hash hh
+    const uint32_t dn = J.rep_shuffle ? (uint32_t)reps : (uint32_t)nr;
+    const uint64_t hh = (J.rep_shuffle || reps == 1) ? key.h : dmix64(key.h ^ ((uint64_t)(rep + 1) * kGolden));
+    const int rounds = n_rounds_dev(dn);
     if (!key.ident) {
         for (int r = threadIdx.x; r < rounds; r += blockDim.x) {
-            uint64_t rk = dmix64(key.h + (uint64_t)(r + 1) * kGolden);
+            uint64_t rk = dmix64(hh + (uint64_t)(r + 1) * kGolden);
             s_rk[r] = rk;
-            s_k[r] = (uint32_t)(((rk >> 32) * (uint64_t)J.n) >> 32);
+            s_k[r] = (uint32_t)(((rk >> 32) * (uint64_t)dn) >> 32);
         }
     }
     __syncthreads();
-    const uint32_t n = (uint32_t)J.n;
+    if (J.rep_shuffle && threadIdx.x == 0)
+        s_src_rep = key.ident ? (uint32_t)rep : swap_or_not((uint32_t)rep, dn, rounds, s_rk, s_k);
+    __syncthreads();
+    const int64_t base = (int64_t)rep * nr;
     for (int ii = threadIdx.x; ii < 1024; ii += blockDim.x) {
-        const int i = c0 + ii;
-        if (i >= J.n) break;
-        uint32_t x = (uint32_t)i;
-        if (!key.ident) {
-            for (int r = 0; r < rounds; ++r) {
-                const uint32_t k = s_k[r];
-                const uint32_t xp = (x <= k) ? (k - x) : (k - x + n);
-                const uint32_t hi = x > xp ? x : xp;
-                if (dmix64((uint64_t)hi ^ s_rk[r]) >> 63) x = xp;
-            }
-        }
+        const int t = c0 + ii;
+        if (t >= nr) break;
+        const int64_t i = base + t;
+        int64_t x;
+        if (key.ident)
+            x = i;
+        else if (J.rep_shuffle)
+            x = (int64_t)s_src_rep * nr + t;
+        else
+            x = base + swap_or_not((uint32_t)t, dn, rounds, s_rk, s_k);
         if (J.xt) {
             for (int c = 0; c < J.dx; ++c)
                 J.xt[((int64_t)c * J.n + i) * J.n_est + e] = J.cols[c][x];

@@ -11,6 +11,7 @@
 #include <thread>
 #include <vector>
 
+#include "greedy.h"
 #include "runtime.h"
 
 namespace mte {
@@ -85,10 +86,30 @@ int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, 
     base.seed = 0;
     base.theiler = 0;
     base.estimator = MTE_ESTIMATOR_KSG;
+    base.replications = 1;
     if (opts) base = *opts;
+    // One replication: every target's search goes through the request loop
+    // (concurrent targets share batches).  Several: the embedding of all
+    // replications is gathered once and each target runs direct launches.
+    const int R = base.replications;
+    if (R < 1) return fail(MTE_EINVAL, "replications=%d must be >= 1", R);
+    const int l_m = std::max(max_lag_sources, base.max_lag_target);
     int32_t sid = -1;
-    int rc = mte_series_register(data, P, T, &sid);
-    if (rc) return rc;
+    DevBuf series, emb;
+    Columns cols;
+    int rc;
+    if (R == 1) {
+        if ((rc = mte_series_register(data, P, T, &sid))) return rc;
+    } else {
+        if (T <= l_m) return fail(MTE_EINVAL, "T=%lld too short", (long long)T);
+        if ((int64_t)R * (T - l_m) > 0x7fffffffLL) return fail(MTE_EINVAL, "R*(T-L) exceeds 2^31-1 rows");
+        if ((rc = ensure_init())) return rc;
+        hipStream_t s;
+        MTE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        rc = resident_columns(data, P, T, l_m, R, s, &series, &emb, &cols);
+        (void)hipStreamDestroy(s);
+        if (rc) return rc;
+    }
     if (n_threads <= 0) n_threads = std::min(P, 16);
     n_threads = std::min(n_threads, P);
 
@@ -115,15 +136,22 @@ int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, 
             o.res.sources = o.src.data();
             mte_opts mo = base;
             mo.seed = base.seed + (uint64_t)t;
-            o.rc = select_sources_served(sid, P, T, t, cands.data(), (int)cands.size(), max_lag_sources, alpha,
-                                         &mo, &o.res);
+            if (R == 1) {
+                o.rc = select_sources_served(sid, P, T, t, cands.data(), (int)cands.size(), max_lag_sources,
+                                             alpha, &mo, &o.res);
+            } else {
+                o.rc = greedy_check(P, T, t, cands.data(), (int)cands.size(), max_lag_sources, alpha, mo, &o.res);
+                if (!o.rc)
+                    o.rc = select_sources_columns(cols, t, cands.data(), (int)cands.size(), max_lag_sources, alpha,
+                                                  mo, &o.res);
+            }
             if (o.rc) o.err = last_error();
         }
     };
     std::vector<std::thread> pool;
     for (int i = 0; i < n_threads; ++i) pool.emplace_back(worker);
     for (auto &th : pool) th.join();
-    (void)mte_series_release(sid);
+    if (sid >= 0) (void)mte_series_release(sid);
     for (int t = 0; t < P; ++t)
         if (outs[(size_t)t].rc) return fail(outs[(size_t)t].rc, "target %d: %s", t, outs[(size_t)t].err.c_str());
 

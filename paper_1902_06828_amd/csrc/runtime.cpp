@@ -462,6 +462,9 @@ static int check_spec(const JobSpec &sp) {
     for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc)
         if (!sp.cols[cc]) return fail(MTE_EINVAL, "null column pointer");
     if (!sp.out) return fail(MTE_EINVAL, "null output pointer");
+    if (sp.reps < 1 || sp.n % sp.reps) return fail(MTE_EINVAL, "N=%d is not a multiple of R=%d", sp.n, sp.reps);
+    if (sp.reps > 1 && sp.theiler) return fail(MTE_EINVAL, "the Theiler window needs a single replication");
+    if (sp.rep_shuffle && sp.reps < 2) return fail(MTE_EINVAL, "a replication shuffle needs R >= 2");
     return MTE_OK;
 }
 
@@ -529,7 +532,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         if (set_rep[set_of[j]] < 0) set_rep[set_of[j]] = j;
         lane_off[j + 1] = lane_off[j] + (int64_t)sp.n * sp.n_est();
         est_off[j + 1] = est_off[j] + sp.n_est();
-        blk_off[j + 1] = blk_off[j] + (int64_t)sp.n_est() * ((sp.n + 1023) / 1024);
+        blk_off[j + 1] = blk_off[j] + (int64_t)sp.n_est() * permute_blocks(sp.n, sp.reps);
         kmax = std::max(kmax, sp.k);
         dxm = std::max(dxm, sp.dx);
         n_keys += sp.n_est();
@@ -622,6 +625,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.rs = 1;
         J.set = set_of[j];
         J.theiler = sp.theiler;
+        J.reps = sp.reps;
+        J.rep_shuffle = sp.rep_shuffle;
         J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
         J.eps = sp.diag_eps ? sp.diag_eps : reinterpret_cast<float *>(sb + offs[j].eps);
         J.cnt = sp.diag_cnt ? sp.diag_cnt : reinterpret_cast<int32_t *>(sb + offs[j].cnt);
@@ -707,6 +712,8 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
         for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
         J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
         J.theiler = sp.theiler;
+        J.reps = sp.reps;
+        J.rep_shuffle = sp.rep_shuffle;
         J.n_est = sp.n_est();
         J.n_tiles = (sp.n + qt - 1) / qt;
         J.n_groups = (J.n_est + cfg.g - 1) / cfg.g;
@@ -720,7 +727,7 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
         const int64_t items = (int64_t)J.n_groups * J.n_tiles * J.rs;
         a_off[j + 1] = a_off[j] + items;
         b_off[j + 1] = b_off[j] + (J.rs > 1 ? items : 0);
-        blk_off[j + 1] = blk_off[j] + (int64_t)J.n_est * ((sp.n + 1023) / 1024);
+        blk_off[j + 1] = blk_off[j] + (int64_t)J.n_est * permute_blocks(sp.n, sp.reps);
         J.a_off = a_off[j];
         J.b_off = b_off[j];
         const int64_t nch = (sp.n + kChunk - 1) / kChunk;

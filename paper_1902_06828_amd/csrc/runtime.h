@@ -72,6 +72,8 @@ struct JobSpec {
     const float *cols[kMaxCols] = {};
     int n = 0, dx = 0, dy = 0, dz = 0, k = 0;
     int theiler = 0;                   // Theiler window w (|i - j| <= w left out)
+    int reps = 1;                      // replications: rows are reps blocks of n/reps rows
+    int rep_shuffle = 0;               // surrogates shuffle the replication order
     std::vector<EstKey> keys;          // one per estimate
     double *out = nullptr;             // device [n_est]
     float *diag_eps = nullptr;         // device [n_est][n] or null
@@ -96,7 +98,7 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
 
 // Timed stages (HIP events around each launch when timing is enabled).
 enum Stage { kStageAllPairs = 0, kStageBuild, kStageScan, kStageFallback, kStageReduce, kStagePermute,
-             kStages };
+             kStageGaussGram, kStageGaussCmi, kStages };
 
 // One launch: its tables, scratch and (optionally) a captured graph.
 class Batch {

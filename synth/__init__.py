@@ -15,5 +15,6 @@ from .gen import (  # noqa: F401
     paper_var_network,
     random_points,
     var_network,
+    var_network_trials,
     window,
 )

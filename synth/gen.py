@@ -149,6 +149,17 @@ def _simulate_linear(p_nodes, n_rows, seed, self_coef, links, noise_sd):
     return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32))
 
 
+def var_network_trials(p_nodes: int, n_rows: int, reps: int, seed: int, radius: float = 0.9,
+                       self_coef: float = 0.4, noise_sd: float = 1.0):
+    """R replications (trials) of the same VAR network: the coefficients of
+    var_network(p_nodes, n_rows, seed), each trial simulated from its own
+    burn-in with its own noise (seeds seed*1000 + r).  Returns
+    (series [R][P][n_rows+MAX_LAG] float32, links)."""
+    _, links = var_network(p_nodes, 8, seed, radius, self_coef, noise_sd)
+    trials = [_simulate_linear(p_nodes, n_rows, seed * 1000 + r, self_coef, links, noise_sd) for r in range(reps)]
+    return np.ascontiguousarray(np.stack(trials)), links
+
+
 def empty_network(p_nodes: int, n_rows: int, seed: int, self_coef: float = 0.4, noise_sd: float = 1.0):
     """P independent AR(1) processes x_i(t) = self_coef * x_i(t-1) + noise: a
     network without links, where every inferred link is a false positive

@@ -184,3 +184,34 @@ def test_gauss_argument_validation():
         mte.mte_select_sources(s, 0, [1, 2], estimator="gauss", theiler=2)
     with pytest.raises(ValueError):
         mte.mte_select_sources(s, 0, [1, 2], estimator="nope")
+
+
+@pytest.mark.parametrize("n,R", [(12, 3), (1000, 8), (999, 27), (7, 7), (4096, 1), (5000, 2)])
+def test_replication_permutation_matches_oracle(n, R):
+    from oracle import perm
+    for mode in ("within", "replications"):
+        if mode == "replications" and R < 2:
+            continue
+        for s in range(3):
+            got = mte.mte_permutation_rep(11, 5, s, n, R, mode)
+            want = perm.replication_source_rows(11, 5, s, n, R, mode)
+            assert np.array_equal(got, want), (mode, s)
+
+
+def test_shuffle_mode_matches_oracle():
+    from oracle import perm
+    for R in range(1, 12):
+        for S in (1, 2, 6, 7, 24, 100, 200, 1000, 10 ** 6):
+            assert mte.mte_shuffle_mode(R, S) == perm.shuffle_mode(R, S), (R, S)
+
+
+def test_replication_argument_validation():
+    g = np.random.default_rng(2)
+    x = g.standard_normal((1, 100)).astype(np.float32)
+    with pytest.raises(mte.MteError):
+        mte.cmi_ksg_surrogates_rep(x, x, None, S=10, R=3)          # 100 rows do not split into 3
+    with pytest.raises(mte.MteError):
+        mte.mte_permutation_rep(0, 0, 0, 10, 1, "replications")      # needs R >= 2
+    s = g.standard_normal((4, 3, 60)).astype(np.float32)
+    with pytest.raises(mte.MteError, match="Theiler"):
+        mte.mte_select_sources(s, 0, [1, 2], max_lag_sources=2, max_lag_target=2, S=40, theiler=1)
