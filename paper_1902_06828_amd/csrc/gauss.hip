@@ -4,9 +4,9 @@
 //   colsum   per row chunk and column (one wave), the float64 sum of the
 //            chunk's rows (lane-strided partial sums, then a fixed butterfly),
 //            then per column the mean of the chunk sums (the same pattern);
-//   gram     per row chunk and tile of the upper triangle, the centered
-//            cross products sum_r (a_r - mean_a)(b_r - mean_b) in float64, one
-//            fma chain per entry over the chunk's rows in order;
+//   gram     per row chunk and 64x64 tile of the upper triangle, the centered
+//            cross products sum_r (a_r - mean_a)(b_r - mean_b) in float64 on the
+//            matrix cores, 4-row groups in order;
 //   reduce   per entry, the chunk partials summed in chunk order, / N.
 //
 // The chunking depends on N only and every entry is one fixed sequence of
@@ -29,7 +29,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRB = kGaussRowStage;
-constexpr int kGramTM = 4;
 
 __device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
 __device__ __forceinline__ int bid_x() { return (int)__builtin_amdgcn_workgroup_id_x(); }
@@ -87,18 +86,27 @@ __device__ __forceinline__ void tile_pair(int y, int n_tiles, int *tp, int *tq) 
     *tq = p + y;
 }
 
-// TM x TM entries per thread, tiles of 16 TM columns a side.  Each entry is
-// one fma chain over the chunk's rows in order, whatever the tile.  TM = 4
-// (64-column tiles, 124 VGPRs, 4 waves per SIMD) is used: TM = 8 needs 256
-// VGPRs, runs one wave per SIMD and leaves the tile loads unhidden (1.8x
-// slower at D = 512, N = 10^6).
-template <int TM>
+// Matrix-core Gram tile.  A block computes one 64x64 tile of the upper
+// triangle over its row chunk; wave w computes the 32x32 quarter
+// (32 (w & 1), 32 (w >> 1)) as 2x2 blocks of v_mfma_f64_16x16x4f64: for every
+// group of 4 rows, D[m][n] += sum_k A[m][k] B[k][n] with A[m][k] the centered
+// value of column p0+m at row k and B[k][n] that of column q0+n.  Operand
+// layout: lane l supplies row k = l/16 of column l%16; the 4 results of lane
+// l are D[l/16 + 4v][l%16], v = 0..3 (checked on the device).  Tiles are staged column-major in
+// LDS (34 doubles per column: a wave's 64 operand loads fall on distinct
+// banks in each half-wave, and the staging stores are consecutive).  Every
+// entry sees the same sequence of 4-row groups in the same order whatever the
+// tile, so its bits do not depend on the other columns.  On gfx950 the fp64
+// matrix rate equals the fp64 vector rate (78.6 TFLOP/s); the matrix cores
+// need 4x fewer LDS reads per fma than a 4x4 vector register tile.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
-    constexpr int T = 16 * TM;        // tile side
-    constexpr int LD = T + 2;         // LDS row stride (doubles), 16-byte aligned rows
+    constexpr int T = 64;
+    constexpr int LDC = kRB + 2;      // column stride in LDS (doubles)
     __shared__ double mu[2][T];
-    __shared__ __align__(16) double As[kRB][LD];
-    __shared__ __align__(16) double Bs[kRB][LD];
+    __shared__ __align__(16) double As[T][LDC];
+    __shared__ __align__(16) double Bs[T][LDC];
     const int tid = tid_x();
     const int c = bid_x();
     int tp, tq;
@@ -106,64 +114,75 @@ __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
     const int p0 = tp * T, q0 = tq * T;
     const int r0 = c * a.chunk_rows;
     const int r1 = min(a.n, r0 + a.chunk_rows);
-
-    for (int u = tid; u < 2 * T; u += kThreads) {
-        const int col = (u < T ? p0 : q0 - T) + u;
-        mu[u / T][u % T] = col < a.D ? a.mean[col] : 0.0;
+    if (tid < 2 * T) {
+        const int col = (tid < T ? p0 : q0 - T) + tid;
+        mu[tid / T][tid % T] = col < a.D ? a.mean[col] : 0.0;
     }
-
-    const int ty = tid >> 4, tx = tid & 15;   // rows ty*TM.., columns tx*TM.. of the tile
-    double acc[TM][TM];
+    const int lane = tid & 63, w = tid >> 6;
+    const int pw = (w & 1) * 32, qw = (w >> 1) * 32;
+    const int kk = lane >> 4, cc = lane & 15;
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+    // Staging: element m of this thread is row (tid + 256 m) % 32 of tile
+    // column (tid + 256 m) / 32.  The next step's values are loaded into
+    // registers while the matrix cores work on the current one.
+    constexpr int M = kRB * T / kThreads;
+    const int sr = tid % kRB;
+    const float *pa[M], *pb[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int col = tid / kRB + m * (kThreads / kRB);
+        pa[m] = p0 + col < a.D ? a.cols[p0 + col] : nullptr;
+        pb[m] = q0 + col < a.D ? a.cols[q0 + col] : nullptr;
+    }
+    float na[M], nb[M];
+    auto fetch = [&](int rs) {
+        const int row = rs + sr;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            na[m] = (pa[m] && row < r1) ? pa[m][row] : 0.0f;
+            nb[m] = (pb[m] && row < r1) ? pb[m][row] : 0.0f;
+        }
+    };
+    fetch(r0);
     for (int rs = r0; rs < r1; rs += kRB) {
         __syncthreads();
+        const bool in = rs + sr < r1;
 #pragma unroll
-        for (int m = 0; m < kRB * T / kThreads; ++m) {
-            const int e = tid + m * kThreads;
-            const int r = e % kRB, col = e / kRB;
-            const int row = rs + r;
-            double va = 0.0, vb = 0.0;
-            if (row < r1) {
-                if (p0 + col < a.D) va = (double)a.cols[p0 + col][row] - mu[0][col];
-                if (q0 + col < a.D) vb = (double)a.cols[q0 + col][row] - mu[1][col];
-            }
-            As[r][col] = va;
-            Bs[r][col] = vb;
+        for (int m = 0; m < M; ++m) {
+            const int col = tid / kRB + m * (kThreads / kRB);
+            As[col][sr] = (pa[m] && in) ? (double)na[m] - mu[0][col] : 0.0;
+            Bs[col][sr] = (pb[m] && in) ? (double)nb[m] - mu[1][col] : 0.0;
         }
         __syncthreads();
-#pragma unroll 2
-        for (int r = 0; r < kRB; ++r) {
-            double av[TM], bv[TM];
+        if (rs + kRB < r1) fetch(rs + kRB);
 #pragma unroll
-            for (int h = 0; h < TM; h += 2) {
-                const double2 x = *reinterpret_cast<const double2 *>(&As[r][ty * TM + h]);
-                const double2 y = *reinterpret_cast<const double2 *>(&Bs[r][tx * TM + h]);
-                av[h] = x.x;
-                av[h + 1] = x.y;
-                bv[h] = y.x;
-                bv[h + 1] = y.y;
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
+        for (int g = 0; g < kRB / 4; ++g) {
+            const int rr = 4 * g + kk;
+            const double a0 = As[pw + cc][rr], a1 = As[pw + 16 + cc][rr];
+            const double b0 = Bs[qw + cc][rr], b1 = Bs[qw + 16 + cc][rr];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
     double *out = a.part + (int64_t)c * a.D * a.D;
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int p = p0 + ty * TM + i;
-        if (p >= a.D) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) {
-            const int q = q0 + tx * TM + j;
-            if (q < a.D) out[(int64_t)p * a.D + q] = acc[i][j];
+        for (int j = 0; j < 2; ++j) {
+            const int q = q0 + qw + 16 * j + cc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = p0 + pw + 16 * i + kk + 4 * v;
+                if (p < a.D && q < a.D) out[(int64_t)p * a.D + q] = acc[i][j][v];
+            }
         }
-    }
 }
 
 __global__ __launch_bounds__(kThreads) void gauss_cov_reduce_kernel(GaussCov a) {
@@ -243,10 +262,9 @@ int launch_gauss_colsum(const GaussCov &a, hipStream_t s) {
 
 int launch_gauss_gram(const GaussCov &a, hipStream_t s) {
     if (a.D < 1 || a.n < 1) return 0;
-    if (a.tile != 16 * kGramTM) return -1;
+    if (a.tile != 64) return -1;
     const int pairs = a.n_tiles * (a.n_tiles + 1) / 2;
-    hipLaunchKernelGGL(gauss_gram_kernel<kGramTM>, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0,
-                       s, a);
+    hipLaunchKernelGGL(gauss_gram_kernel, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
