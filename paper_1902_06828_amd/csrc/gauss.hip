@@ -92,9 +92,11 @@ __device__ __forceinline__ void tile_pair(int y, int n_tiles, int *tp, int *tq) 
 // group of 4 rows, D[m][n] += sum_k A[m][k] B[k][n] with A[m][k] the centered
 // value of column p0+m at row k and B[k][n] that of column q0+n.  Operand
 // layout: lane l supplies row k = l/16 of column l%16; the 4 results of lane
-// l are D[l/16 + 4v][l%16], v = 0..3 (checked on the device).  Tiles are staged column-major in
-// LDS (34 doubles per column: a wave's 64 operand loads fall on distinct
-// banks in each half-wave, and the staging stores are consecutive).  Every
+// l are D[l/16 + 4v][l%16], v = 0..3 (checked on the device).  Tiles are
+// staged column-major in LDS, 33 doubles per column: the 16 columns one
+// operand load touches per row start 66 dwords apart, so each group of 16
+// lanes covers the 32 banks once (no bank conflicts in the counters; a
+// 34-double stride conflicted), and the staging stores are consecutive.  Every
 // entry sees the same sequence of 4-row groups in the same order whatever the
 // tile, so its bits do not depend on the other columns.  On gfx950 the fp64
 // matrix rate equals the fp64 vector rate (78.6 TFLOP/s); the matrix cores
@@ -103,7 +105,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
     constexpr int T = 64;
-    constexpr int LDC = kRB + 2;      // column stride in LDS (doubles)
+    constexpr int LDC = kRB + 1;      // column stride in LDS (doubles)
     __shared__ double mu[2][T];
     __shared__ __align__(16) double As[T][LDC];
     __shared__ __align__(16) double Bs[T][LDC];
