@@ -382,10 +382,47 @@ __device__ __forceinline__ void load_step(const Ent *l, Ent (&en)[kU]) {
     for (int u = 0; u < kU; ++u) en[u] = l[u];
 }
 
+// Wave-uniform helpers of the cooperative finish.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int lowest(uint64_t m) { return __builtin_amdgcn_readfirstlane(__builtin_ctzll(m)); }
+__device__ __forceinline__ float bcast(float v, int o) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), o));
+}
+__device__ __forceinline__ int bcast(int v, int o) { return __builtin_amdgcn_readlane(v, o); }
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int o) { return (uint32_t)__builtin_amdgcn_readlane((int)v, o); }
+template <class T>
+__device__ __forceinline__ T *bcast(T *v, int o) {
+    const uint64_t a = reinterpret_cast<uint64_t>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a, o);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a >> 32), o);
+    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
+// The scans' divergence: the 64 lanes of a wave stop at very different list
+// positions (a few estimates of a row have radii far above the others), and
+// a wave runs until its slowest lane is done.  So each phase runs lane by lane
+// only while more than kCoopLanes lanes are still scanning; the wave then
+// finishes the remaining lanes one after the other with all 64 lanes, 64
+// list entries per step (a ballot per test, the top-k kept wave-uniform).
+// Entries, distances and tests are the same, so the results are too: a scan
+// may stop at any position whose bucket floor reaches the current radius.
+// A cooperative step gathers X for 64 different rows (64 cache lines instead
+// of the 2-4 of a lane-by-lane step, whose lanes are adjacent estimates), so
+// it only pays for the last few lanes: on C2 (N = 10^4, 201 estimates) the scan
+// took 0.62 ms without it, 0.48 ms with kCoopLanes = 2, 0.50 ms with 4, 0.54
+// ms with 8, 0.67 ms with 16; 2 or 4 entries per lane per cooperative step
+// were slower still (more scattered gathers past the stop position).
+constexpr int kCoopLanes = 2;
+constexpr int kCoopU = 1;      // list entries per lane per cooperative step
+
 template <int KMAX, int DXM>
 __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
-    const int64_t g = bid_x() * kBlock + tid_x();
-    if (g >= L.lanes) return;
+    const int lane = tid_x() & 63;
+    const int64_t g0 = bid_x() * kBlock + tid_x();
+    // every lane of a wave takes part in the cooperative steps: lanes past
+    // the last pair mirror it and store nothing
+    const bool live = g0 < L.lanes;
+    const int64_t g = live ? g0 : L.lanes - 1;
     const int jb = find_job(L.lane_off, L.n_jobs, g);
     const Job &J = L.jobs[jb];
     const int64_t r = g - L.lane_off[jb];
@@ -395,6 +432,18 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const int n = J.n;
     Lane<KMAX, DXM> ln(J, i, e);
 
+    // X distance of one entry under lane o's estimate (cooperative steps)
+    auto coop_xdist = [&](const float *xt, uint32_t cs, uint32_t E, uint32_t eo, int dxo, const float (&xq)[DXM],
+                          int32_t j) {
+        const uint32_t oo = (uint32_t)j * E + eo;
+        float d = absdiff(xq[0], xt[oo]);
+        Unroll<1, DXM>::upto(dxo, [&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            d = fmax_(d, absdiff(xq[c], xt[c * cs + oo]));
+        });
+        return d;
+    };
+
     // k-NN radius over list 1
     float top[KMAX];
     const int pad_front = KMAX - J.k;
@@ -402,15 +451,21 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     for (int m = 0; m < KMAX; ++m) top[m] = m < pad_front ? -inf_f() : inf_f();
     const LEnt *l1 = S.l1 + (int64_t)i * S.s1;
     const int len1 = S.len[2 * (int64_t)i];
-    bool decided = false;
+    bool decided = false, act = live;
     int seen1 = 0, seen2 = 0;     // list entries read (statistics)
+    int m1 = 0;
     {
         LEnt cur[kU];
         load_step(l1, cur);
-        for (int m = 0; m <= len1; m += kU) {
-            seen1 = m + kU;
+        while (__builtin_popcountll(ballot(act)) > kCoopLanes) {
+            if (!act) continue;
+            if (m1 > len1) {          // list exhausted: undecided
+                act = false;
+                continue;
+            }
+            seen1 = m1 + kU;
             LEnt nxt[kU];
-            load_step(l1 + m + kU, nxt);
+            load_step(l1 + m1 + kU, nxt);
             float d[kU];
             ln.xdist(cur, d);
             float lo = inf_f();
@@ -423,9 +478,61 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
 #pragma unroll
                 for (int u = 0; u < kU; ++u) topk_insert<KMAX>(top, d[u]);
             }
-            if (bucket_floor(cur[kU - 1].d) >= top[KMAX - 1]) { decided = true; break; }
+            if (bucket_floor(cur[kU - 1].d) >= top[KMAX - 1]) {
+                decided = true;
+                act = false;
+                continue;
+            }
 #pragma unroll
             for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+            m1 += kU;
+        }
+    }
+    for (uint64_t rest = ballot(act); rest; rest &= rest - 1) {
+        const int o = lowest(rest);
+        const LEnt *pl = bcast(l1, o);
+        const int end = bcast(len1, o) + kListPad;
+        const float *xt = bcast(ln.xt, o);
+        const uint32_t cs = bcast(ln.cs, o), E = bcast(ln.E, o), eo = bcast(ln.e, o);
+        const int dxo = bcast(ln.dx, o);
+        float xq[DXM], pt[KMAX];
+#pragma unroll
+        for (int c = 0; c < DXM; ++c) xq[c] = bcast(ln.xq[c], o);
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) pt[q] = bcast(top[q], o);
+        bool dec = false;
+        int p = bcast(m1, o);
+        for (; p < end; p += 64 * kCoopU) {
+            // kCoopU entries per lane, all loads issued first
+            const int last = min(p + 64 * kCoopU - 1, end - 1);
+            const float stop = bucket_floor(pl[last].d);
+            LEnt en[kCoopU];
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u) {
+                const int idx = p + lane + 64 * u;
+                en[u] = pl[min(idx, end - 1)];
+            }
+            float d[kCoopU];
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u) {
+                d[u] = fmax_(coop_xdist(xt, cs, E, eo, dxo, xq, en[u].j), en[u].d);
+                if (p + lane + 64 * u >= end) d[u] = inf_f();
+            }
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u)
+                for (uint64_t cand = ballot(d[u] < pt[KMAX - 1]); cand; cand &= cand - 1)
+                    topk_insert<KMAX>(pt, bcast(d[u], lowest(cand)));
+            if (stop >= pt[KMAX - 1]) {
+                dec = true;
+                p = last + 1;
+                break;
+            }
+        }
+        if (lane == o) {
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q) top[q] = pt[q];
+            decided = dec;
+            seen1 = min(p, end);
         }
     }
     const float eps = top[KMAX - 1];
@@ -433,16 +540,23 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     // n_z, n_yz and n_xz from list 2 below eps (every row with d_z < eps, and
     // so every row with d_yz < eps, is listed when eps <= its bound)
     int cxz = 0, cyz = 0, cz = 0;
-    if (decided) {
-        decided = false;
-        const LEnt2 *l2 = S.l2 + (int64_t)i * S.s2;
-        const int len2 = S.len[2 * (int64_t)i + 1];
+    const LEnt2 *l2 = S.l2 + (int64_t)i * S.s2;
+    const int len2 = S.len[2 * (int64_t)i + 1];
+    act = live && decided;
+    decided = false;
+    int m2 = 0;
+    {
         LEnt2 cur[kU];
         load_step(l2, cur);
-        for (int m = 0; m <= len2; m += kU) {
-            seen2 = m + kU;
+        while (__builtin_popcountll(ballot(act)) > kCoopLanes) {
+            if (!act) continue;
+            if (m2 > len2) {
+                act = false;
+                continue;
+            }
+            seen2 = m2 + kU;
             LEnt2 nxt[kU];
-            load_step(l2 + m + kU, nxt);
+            load_step(l2 + m2 + kU, nxt);
             float dx[kU];
             ln.xdist(cur, dx);
 #pragma unroll
@@ -451,26 +565,77 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
                 cyz += cur[u].dyz < eps;
                 cxz += fmax_(dx[u], cur[u].dz) < eps;
             }
-            if (bucket_floor(cur[kU - 1].dz) >= eps) { decided = true; break; }
+            if (bucket_floor(cur[kU - 1].dz) >= eps) {
+                decided = true;
+                act = false;
+                continue;
+            }
 #pragma unroll
             for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+            m2 += kU;
         }
     }
-    if (!decided) {
-        const uint32_t pos = atomicAdd(&L.counters[0], 1u);
-        L.failq[pos] = ((uint64_t)jb << 40) | (uint64_t)r;
-    } else {
-        J.eps[(int64_t)e * n + i] = eps;
-        J.cnt[((int64_t)e * 3 + 0) * n + i] = cxz;
-        J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
-        J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
+    for (uint64_t rest = ballot(act); rest; rest &= rest - 1) {
+        const int o = lowest(rest);
+        const LEnt2 *pl = bcast(l2, o);
+        const int end = bcast(len2, o) + kListPad;
+        const float *xt = bcast(ln.xt, o);
+        const uint32_t cs = bcast(ln.cs, o), E = bcast(ln.E, o), eo = bcast(ln.e, o);
+        const int dxo = bcast(ln.dx, o);
+        const float pe = bcast(eps, o);
+        float xq[DXM];
+#pragma unroll
+        for (int c = 0; c < DXM; ++c) xq[c] = bcast(ln.xq[c], o);
+        int qz = 0, qyz = 0, qxz = 0;
+        bool dec = false;
+        int p = bcast(m2, o);
+        for (; p < end; p += 64 * kCoopU) {
+            const int last = min(p + 64 * kCoopU - 1, end - 1);
+            const float stop = bucket_floor(pl[last].dz);
+            LEnt2 en[kCoopU];
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u) en[u] = pl[min(p + lane + 64 * u, end - 1)];
+            float dxv[kCoopU];
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u) dxv[u] = coop_xdist(xt, cs, E, eo, dxo, xq, en[u].j);
+#pragma unroll
+            for (int u = 0; u < kCoopU; ++u) {
+                const bool in = p + lane + 64 * u < end;
+                qz += __builtin_popcountll(ballot(in && en[u].dz < pe));
+                qyz += __builtin_popcountll(ballot(in && en[u].dyz < pe));
+                qxz += __builtin_popcountll(ballot(in && fmax_(dxv[u], en[u].dz) < pe));
+            }
+            if (stop >= pe) {
+                dec = true;
+                p = last + 1;
+                break;
+            }
+        }
+        if (lane == o) {
+            cz += qz;
+            cyz += qyz;
+            cxz += qxz;
+            decided = dec;
+            seen2 = min(p, end);
+        }
     }
-    if (L.stats) {
-        const int slot = (int)((g >> 6) & (kListStatSlots - 1));
-        unsigned long long *st =
-            reinterpret_cast<unsigned long long *>(L.counters + kListStatWord + slot * kListStatStride);
-        atomicAdd(&st[0], (unsigned long long)seen1);
-        atomicAdd(&st[1], (unsigned long long)seen2);
+    if (live) {
+        if (!decided) {
+            const uint32_t pos = atomicAdd(&L.counters[0], 1u);
+            L.failq[pos] = ((uint64_t)jb << 40) | (uint64_t)r;
+        } else {
+            J.eps[(int64_t)e * n + i] = eps;
+            J.cnt[((int64_t)e * 3 + 0) * n + i] = cxz;
+            J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
+            J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
+        }
+        if (L.stats) {
+            const int slot = (int)((g >> 6) & (kListStatSlots - 1));
+            unsigned long long *st =
+                reinterpret_cast<unsigned long long *>(L.counters + kListStatWord + slot * kListStatStride);
+            atomicAdd(&st[0], (unsigned long long)seen1);
+            atomicAdd(&st[1], (unsigned long long)seen2);
+        }
     }
 }
 
