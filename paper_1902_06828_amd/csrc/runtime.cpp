@@ -500,10 +500,25 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     return MTE_OK;
 }
 
-// List capacities per row: MTE_LIST_CAP="m1,m2" overrides the defaults.
-static void list_caps(int *m1, int *m2) {
-    *m1 = 1024;
-    *m2 = 2048;
+// List capacities per row.  The Z list must hold every row with d_z below a
+// radius taken in the joint space, so the capacity it needs grows with the
+// dimensions outside Z: with e = dx + dy - dz, on the 10-node VAR at
+// N = 10^4 the 99th percentile of n_z is about 1000 for e = 0, 2000-3700
+// for e = 1 and 4700-6700 for e >= 2 (n_yz about a third to half of that),
+// and a pair beyond the capacity is redone over all rows, some 800 times the
+// cost of a list scan.  MTE_LIST_CAP="m1,m2" overrides (tests use it to force
+// the all-rows redo).
+// The lists of one set are kept within kListSetBytes (capacities halved until
+// they fit, down to 1024 and 2048).
+constexpr double kListSetBytes = 4.0 * (1 << 30);
+
+static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
+    const int e = dx + dy - dz;
+    *m1 = e >= 2 ? 8192 : e == 1 ? 4096 : e == 0 ? 2048 : 1024;
+    while (*m1 > 1024 && (double)n * (std::min(n - 1, *m1) * (double)sizeof(LEnt) +
+                                      std::min(n - 1, 2 * *m1) * (double)sizeof(LEnt2)) > kListSetBytes)
+        *m1 /= 2;
+    *m2 = 2 * *m1;
     const char *v = std::getenv("MTE_LIST_CAP");
     if (v && *v) {
         int a = 0, b = 0;
@@ -517,8 +532,6 @@ static void list_caps(int *m1, int *m2) {
 int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
                          hipStream_t s) {
     Ctx &c = ctx();
-    int cap1 = 0, cap2 = 0;
-    list_caps(&cap1, &cap2);
     n_ljobs_ = (int)specs.size();
     std::vector<Job> jobs(n_ljobs_);
     std::vector<ListSet> sets(n_sets);
@@ -541,10 +554,14 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     size_t bytes = 0;
     int nmax_set = 0;
     std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets);
+    std::vector<int> set_dx(n_sets, 0);
+    for (int j = 0; j < n_ljobs_; ++j) set_dx[set_of[j]] = std::max(set_dx[set_of[j]], specs[j].dx);
     for (int t = 0; t < n_sets; ++t) {
         const JobSpec &sp = specs[set_rep[t]];
         ListSet &S = sets[t];
         std::memset(&S, 0, sizeof S);
+        int cap1 = 0, cap2 = 0;
+        list_caps(set_dx[t], sp.dy, sp.dz, sp.n, &cap1, &cap2);
         for (int cc = 0; cc < sp.dy + sp.dz; ++cc) S.cols[cc] = sp.cols[sp.dx + cc];
         S.n = sp.n;
         S.dy = sp.dy;
