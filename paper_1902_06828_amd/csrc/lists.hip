@@ -332,6 +332,13 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
 // the k-NN list (bound + 1 ulp < k-th distance) leaves a radius above the
 // bound, i.e. an undecided pair, as it should.
 constexpr int kU = 8;   // list entries per step; the next step's are loaded ahead
+
+// Load through a global-address-space pointer: a generic (flat) load would
+// count against both the vector-memory and the LDS counters, and the wait for
+// the gathers would then also wait for the next step's entries loaded ahead.
+__device__ __forceinline__ float gload(const float *p, uint32_t off) {
+    return ((const __attribute__((address_space(1))) float *)p)[off];
+}
 static_assert(kU <= kListPad, "a step must stay within the sentinels");
 
 template <int KMAX, int DXM>
@@ -362,14 +369,14 @@ struct Lane {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             o[u] = (uint32_t)en[u].j * E + e;
-            v[u] = xt[o[u]];
+            v[u] = gload(xt, o[u]);
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) d[u] = absdiff(xq[0], v[u]);
         Unroll<1, DXM>::upto(dx, [&](auto cc) {
             constexpr int c = decltype(cc)::value;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = xt[c * cs + o[u]];
+            for (int u = 0; u < kU; ++u) v[u] = gload(xt, c * cs + o[u]);
 #pragma unroll
             for (int u = 0; u < kU; ++u) d[u] = fmax_(d[u], absdiff(xq[c], v[u]));
         });
@@ -436,10 +443,10 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     auto coop_xdist = [&](const float *xt, uint32_t cs, uint32_t E, uint32_t eo, int dxo, const float (&xq)[DXM],
                           int32_t j) {
         const uint32_t oo = (uint32_t)j * E + eo;
-        float d = absdiff(xq[0], xt[oo]);
+        float d = absdiff(xq[0], gload(xt, oo));
         Unroll<1, DXM>::upto(dxo, [&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            d = fmax_(d, absdiff(xq[c], xt[c * cs + oo]));
+            d = fmax_(d, absdiff(xq[c], gload(xt, c * cs + oo)));
         });
         return d;
     };
