@@ -44,7 +44,10 @@ def test_list_path_parity(monkeypatch, caps, n, dims, k, kind, S):
 
 
 @pytest.mark.parametrize("n,dims,kind,seed", [(3000, (1, 1, 5), "normal", 1), (2048, (2, 1, 3), "dup", 2),
-                                              (1000, (1, 2, 7), "grid", 3), (4097, (1, 1, 1), "wide", 4)])
+                                              (1000, (1, 2, 7), "grid", 3), (4097, (1, 1, 1), "wide", 4),
+                                              # more dimensions outside Z than in it: the capacities
+                                              # grow (to 8192 / 16384 entries) but stay below N - 1
+                                              (20000, (3, 1, 1), "normal", 5), (12000, (2, 1, 2), "normal", 6)])
 def test_list_equals_all_pairs(monkeypatch, n, dims, kind, seed):
     X, Y, Z = synth.random_points(n, dims, seed=seed, kind=kind)
     out = {}
