@@ -66,7 +66,13 @@ struct Job {
     int theiler;                  // Theiler window w: pairs with |i - j| <= w are left out
     int reps;                     // replications R (rows: R blocks of n/R, replication-major)
     int rep_shuffle;              // surrogates shuffle the replication order (else rows within each)
+    // list path without Z (dz = 0, dx = 1): the job's X column sorted
+    // ascending (n floats), for the n_x range counts; null otherwise
+    float *xs;
 };
+
+// Largest N of a list-path job without Z (its X column is sorted in LDS).
+constexpr int kNoZSortMax = 16384;
 
 // Neighbour lists of one (Y, Z) sample, shared by every job of a launch whose
 // Y and Z columns are the same.  For row i, list 1 holds the other rows j with
@@ -134,6 +140,7 @@ struct ListLaunch {
                                   // per launch
     int kmax, dxm;                // compile-time classes of the scan kernel
     int fb_grid;                  // blocks of the fallback kernel
+    int sortx;                    // some job has no Z: sort the X columns (Job::xs)
 };
 
 // Counter words of one job (all zero before a launch):
@@ -174,6 +181,7 @@ int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_o
                 const double *harm, void *stream);
 
 int launch_list_build(const ListLaunch &L, void *stream);
+int launch_list_sortx(const ListLaunch &L, void *stream);
 int launch_list_scan(const ListLaunch &L, void *stream);
 int launch_list_fallback(const ListLaunch &L, void *stream);
 int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream);

@@ -321,6 +321,39 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
     }
 }
 
+// ------------------------------------------------------------------ X sort
+// One block per job without Z: its X column sorted ascending (bitonic, in
+// LDS, padded with +inf to a power of two), for the n_x range counts.
+constexpr int kSortThreads = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void list_sortx_kernel(const ListLaunch L) {
+    __shared__ float v[kNoZSortMax];
+    const Job &J = L.jobs[bid_x()];
+    if (!J.xs) return;
+    const int tid = tid_x();
+    const int n = J.n;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int x = tid; x < P; x += kSortThreads) v[x] = x < n ? J.cols[0][x] : inf_f();
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int x = tid; x < P; x += kSortThreads) {
+                const int y = x ^ j;
+                if (y > x) {
+                    const float a = v[x], b = v[y];
+                    if ((a > b) == ((x & k) == 0)) {
+                        v[x] = b;
+                        v[y] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int x = tid; x < n; x += kSortThreads) J.xs[x] = v[x];
+}
+
 // ------------------------------------------------------------------ scan
 // Each list row is followed by kListPad sentinel entries (row = self, d_yz =
 // +inf) whose key distance lies in the bucket that starts at the row's bound:
@@ -549,7 +582,9 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     int cxz = 0, cyz = 0, cz = 0;
     const LEnt2 *l2 = S.l2 + (int64_t)i * S.s2;
     const int len2 = S.len[2 * (int64_t)i + 1];
-    act = live && decided;
+    const bool noz = J.dz == 0;
+    const bool knn_decided = decided;
+    act = live && decided && !noz;
     decided = false;
     int m2 = 0;
     {
@@ -626,6 +661,39 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
             seen2 = min(p, end);
         }
     }
+    if (noz && live && knn_decided) {
+        // Without Z: n_z is the number of rows outside the window; n_y comes
+        // from list 1 (its d is d_y, and every row with d_y < eps precedes the
+        // k-NN stop); n_x counts the rows j != i with |x_j - x_i| < eps.  The
+        // permuted values x_j run over the job's X column, so that count is
+        // the range of the sorted column around x_i: the s with
+        // -eps < fl(xs[s] - x_i) < eps (fl(. - x_i) is monotone), less row i
+        // itself and the rows of its Theiler window.
+        const int w = J.theiler;
+        cz = n - 1 - min(i, w) - min(n - 1 - i, w);
+        for (int m = 0;; ++m) {
+            const float d = l1[m].d;
+            if (bucket_floor(d) >= eps) break;
+            cyz += d < eps;
+        }
+        const float x = ln.xq[0];
+        const float *xs = J.xs;
+        int lo = 0, hi = n;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (gload(xs, mid) - x > -eps) hi = mid; else lo = mid + 1;
+        }
+        const int first = lo;
+        hi = n;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (gload(xs, mid) - x >= eps) hi = mid; else lo = mid + 1;
+        }
+        cxz = lo - first - (0.f < eps ? 1 : 0);
+        for (int j = max(0, i - w); j <= min(n - 1, i + w); ++j)
+            if (j != i && absdiff(x, gload(ln.xt, (uint32_t)j * ln.E + ln.e)) < eps) --cxz;
+        decided = true;
+    }
     if (live) {
         if (!decided) {
             const uint32_t pos = atomicAdd(&L.counters[0], 1u);
@@ -647,14 +715,139 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
 }
 
 // ------------------------------------------------------------------ fallback
-// One block of kFbThreads per undecided (row, estimate): every other row, as
-// in the definition.  Each thread keeps the KMAX smallest distances of its
-// rows; k pops of the wave-wide minimum give each wave's k smallest, and the
-// k-th smallest of the waves' lists is the radius.  Large blocks keep the
-// per-item latency short (the items are few and run side by side).
+// The undecided (row, estimate) pairs, over every other row as in the
+// definition: each thread keeps the KMAX smallest distances of its rows, k
+// pops of the minimum give the radius, then the threads count and a sum adds
+// the counts.  Two shapes, chosen from the queue length (a scalar, so the
+// choice is uniform): a few pairs (the usual case, e.g. 244 of 2 million on
+// C2) take a whole 1024-thread block each, which keeps the latency of a pair
+// short; many pairs (lists short for the data) take one wave each, with no
+// block synchronisation, for throughput.
 constexpr int kFbBatch = 4;
 constexpr int kFbThreads = 1024;
 constexpr int kFbWaves = kFbThreads / 64;
+constexpr uint32_t kFbBlockModeMax = 2048;   // queue length up to which a pair gets a block
+
+struct FbPair {
+    const Job *J;
+    int i, e, n, dx, dy, dz;
+    int64_t cs;
+};
+
+__device__ __forceinline__ FbPair fb_pair(const ListLaunch &L, uint32_t it) {
+    const uint64_t item = L.failq[it];
+    const int jb = (int)(item >> 40);
+    const int64_t r = (int64_t)(item & ((1ull << 40) - 1));
+    FbPair p;
+    p.J = &L.jobs[jb];
+    const int E = p.J->n_est;
+    p.i = (int)(r / E);
+    p.e = (int)(r - (int64_t)p.i * E);
+    p.n = p.J->n;
+    p.dx = p.J->dx;
+    p.dy = p.J->dy;
+    p.dz = p.J->dz;
+    p.cs = (int64_t)p.n * E;
+    return p;
+}
+
+// distances of rows j0, j0 + step, ... (kFbBatch of them; rows inside row i's
+// Theiler window and rows past the end get +inf in every subspace)
+__device__ __forceinline__ void fb_dists(const FbPair &p, int j0, int step, float (&ax)[kFbBatch],
+                                         float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
+    const Job &J = *p.J;
+    const int E = J.n_est;
+    int jj[kFbBatch];
+#pragma unroll
+    for (int u = 0; u < kFbBatch; ++u) {
+        const int j = j0 + u * step;
+        jj[u] = j < p.n ? j : p.i;
+        ax[u] = ay[u] = az[u] = 0.f;
+    }
+    for (int c = 0; c < p.dx; ++c) {
+        const float q = J.xt[c * p.cs + (int64_t)p.i * E + p.e];
+        float v[kFbBatch];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) v[u] = J.xt[c * p.cs + (int64_t)jj[u] * E + p.e];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) ax[u] = fmax_(ax[u], absdiff(q, v[u]));
+    }
+    const float *const *yc = J.cols + p.dx;
+    for (int c = 0; c < p.dy; ++c) {
+        const float q = yc[c][p.i];
+        float v[kFbBatch];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) v[u] = yc[c][jj[u]];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) ay[u] = fmax_(ay[u], absdiff(q, v[u]));
+    }
+    const float *const *zc = J.cols + p.dx + p.dy;
+    for (int c = 0; c < p.dz; ++c) {
+        const float q = zc[c][p.i];
+        float v[kFbBatch];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) v[u] = zc[c][jj[u]];
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) az[u] = fmax_(az[u], absdiff(q, v[u]));
+    }
+#pragma unroll
+    for (int u = 0; u < kFbBatch; ++u)
+        if (abs(jj[u] - p.i) <= J.theiler) ax[u] = ay[u] = az[u] = inf_f();
+}
+
+// top-k of this thread's rows j0, j0 + step, ..., and the counts below eps
+template <int KMAX>
+__device__ __forceinline__ void fb_topk(const FbPair &p, int j0, int step, float (&top)[KMAX]) {
+#pragma unroll
+    for (int m = 0; m < KMAX; ++m) top[m] = inf_f();
+    for (int j = j0; j < p.n; j += step * kFbBatch) {
+        float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
+        fb_dists(p, j, step, ax, ay, az);
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) topk_insert<KMAX>(top, fmax_(fmax_(ax[u], ay[u]), az[u]));
+    }
+}
+
+__device__ __forceinline__ void fb_counts(const FbPair &p, int j0, int step, float eps, int (&c3)[3]) {
+    c3[0] = c3[1] = c3[2] = 0;
+    for (int j = j0; j < p.n; j += step * kFbBatch) {
+        float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
+        fb_dists(p, j, step, ax, ay, az);
+#pragma unroll
+        for (int u = 0; u < kFbBatch; ++u) {
+            c3[0] += fmax_(ax[u], az[u]) < eps;
+            c3[1] += fmax_(ay[u], az[u]) < eps;
+            c3[2] += az[u] < eps;
+        }
+    }
+}
+
+__device__ __forceinline__ void fb_store(const FbPair &p, float eps, int (&c3)[3]) {
+    const Job &J = *p.J;
+    const int n = p.n, i = p.i, e = p.e;
+    if (p.dz == 0) c3[2] = n - 1 - min(i, J.theiler) - min(n - 1 - i, J.theiler);
+    J.eps[(int64_t)e * n + i] = eps;
+    for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
+}
+
+// k pops of the wave-wide minimum of the threads' sorted lists; the last
+// popped value is the wave's k-th smallest
+template <int KMAX>
+__device__ __forceinline__ float wave_kth(float (&top)[KMAX], int k, float *popped) {
+    const int lane = tid_x() & 63;
+    float mn = inf_f();
+    for (int t = 0; t < k; ++t) {
+        mn = wave_min(top[0]);
+        const uint64_t bal = __ballot(top[0] == mn);
+        if (lane == __builtin_ctzll(bal)) {
+#pragma unroll
+            for (int m = 0; m < KMAX - 1; ++m) top[m] = top[m + 1];
+            top[KMAX - 1] = inf_f();
+        }
+        if (popped && lane == 0) popped[t] = mn;
+    }
+    return mn;
+}
 
 template <int KMAX>
 __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLaunch L) {
@@ -664,118 +857,58 @@ __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLau
     const int tid = tid_x();
     const int lane = tid & 63;
     // The item count, the wave index and the block index are scalar values,
-    // so the item loop and everything derived from an item are uniform and
+    // so the item loops and everything derived from an item are uniform and
     // all lanes stay together through the cross-lane steps below.
     const uint32_t total = __builtin_amdgcn_readfirstlane(__atomic_load_n(&L.counters[0], __ATOMIC_RELAXED));
     const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
-    for (uint32_t it = (uint32_t)bid_x(); it < total; it += (uint32_t)L.fb_grid) {
-        const uint64_t item = L.failq[it];
-        const int jb = (int)(item >> 40);
-        const int64_t r = (int64_t)(item & ((1ull << 40) - 1));
-        const Job &J = L.jobs[jb];
-        const int E = J.n_est, n = J.n, dx = J.dx, dy = J.dy, dz = J.dz;
-        const int i = (int)(r / E), e = (int)(r - (int64_t)i * E);
-        const int64_t cs = (int64_t)n * E;
-        const float *const *yc = J.cols + dx;
-        const float *const *zc = J.cols + dx + dy;
-        // distances of kFbBatch rows j0, j0 + kFbThreads, ... (rows inside row
-        // i's Theiler window and rows past the end get +inf in every subspace)
-        auto dists = [&](int j0, float (&ax)[kFbBatch], float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
-            int jj[kFbBatch];
-#pragma unroll
-            for (int u = 0; u < kFbBatch; ++u) {
-                const int j = j0 + u * kFbThreads;
-                jj[u] = j < n ? j : i;
-                ax[u] = ay[u] = az[u] = 0.f;
+    if (total <= kFbBlockModeMax) {
+        for (uint32_t it = (uint32_t)bid_x(); it < total; it += (uint32_t)L.fb_grid) {
+            const FbPair p = fb_pair(L, it);
+            float top[KMAX];
+            fb_topk<KMAX>(p, tid, kFbThreads, top);
+            wave_kth<KMAX>(top, p.J->k, wtop[wave]);
+            __syncthreads();
+            if (tid == 0) {
+                int pos[kFbWaves] = {};
+                float kth = inf_f();
+                for (int t = 0; t < p.J->k; ++t) {
+                    int best = 0;
+                    float bv = inf_f();
+                    for (int w = 0; w < kFbWaves; ++w)
+                        if (pos[w] < p.J->k && wtop[w][pos[w]] < bv) { bv = wtop[w][pos[w]]; best = w; }
+                    ++pos[best];
+                    kth = bv;
+                }
+                s_eps = kth;
             }
-            for (int c = 0; c < dx; ++c) {
-                const float q = J.xt[c * cs + (int64_t)i * E + e];
-                float v[kFbBatch];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) v[u] = J.xt[c * cs + (int64_t)jj[u] * E + e];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) ax[u] = fmax_(ax[u], absdiff(q, v[u]));
-            }
-            for (int c = 0; c < dy; ++c) {
-                const float q = yc[c][i];
-                float v[kFbBatch];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) v[u] = yc[c][jj[u]];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) ay[u] = fmax_(ay[u], absdiff(q, v[u]));
-            }
-            for (int c = 0; c < dz; ++c) {
-                const float q = zc[c][i];
-                float v[kFbBatch];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) v[u] = zc[c][jj[u]];
-#pragma unroll
-                for (int u = 0; u < kFbBatch; ++u) az[u] = fmax_(az[u], absdiff(q, v[u]));
-            }
-#pragma unroll
-            for (int u = 0; u < kFbBatch; ++u)
-                if (abs(jj[u] - i) <= J.theiler) ax[u] = ay[u] = az[u] = inf_f();
-        };
-        float top[KMAX];
-#pragma unroll
-        for (int m = 0; m < KMAX; ++m) top[m] = inf_f();
-        for (int j0 = tid; j0 < n; j0 += kFbThreads * kFbBatch) {
-            float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
-            dists(j0, ax, ay, az);
-#pragma unroll
-            for (int u = 0; u < kFbBatch; ++u) topk_insert<KMAX>(top, fmax_(fmax_(ax[u], ay[u]), az[u]));
-        }
-        for (int t = 0; t < J.k; ++t) {
-            const float mn = wave_min(top[0]);
-            const uint64_t bal = __ballot(top[0] == mn);
-            const int first = __builtin_ctzll(bal);
-            if (lane == first) {
-#pragma unroll
-                for (int m = 0; m < KMAX - 1; ++m) top[m] = top[m + 1];
-                top[KMAX - 1] = inf_f();
-            }
-            if (lane == 0) wtop[wave][t] = mn;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int pos[kFbWaves] = {};
-            float kth = inf_f();
-            for (int t = 0; t < J.k; ++t) {
-                int best = 0;
-                float bv = inf_f();
+            __syncthreads();
+            const float eps = s_eps;
+            int c3[3];
+            fb_counts(p, tid, kFbThreads, eps, c3);
+            for (int t = 0; t < 3; ++t) c3[t] = wave_sum(c3[t]);
+            if (lane == 0) { wcnt[wave][0] = c3[0]; wcnt[wave][1] = c3[1]; wcnt[wave][2] = c3[2]; }
+            __syncthreads();
+            if (tid == 0) {
+                int s3[3] = {0, 0, 0};
                 for (int w = 0; w < kFbWaves; ++w)
-                    if (pos[w] < J.k && wtop[w][pos[w]] < bv) { bv = wtop[w][pos[w]]; best = w; }
-                ++pos[best];
-                kth = bv;
+                    for (int t = 0; t < 3; ++t) s3[t] += wcnt[w][t];
+                fb_store(p, eps, s3);
             }
-            s_eps = kth;
+            __syncthreads();
         }
-        __syncthreads();
-        const float eps = s_eps;
-        int cxz = 0, cyz = 0, cz = 0;
-        for (int j0 = tid; j0 < n; j0 += kFbThreads * kFbBatch) {
-            float ax[kFbBatch], ay[kFbBatch], az[kFbBatch];
-            dists(j0, ax, ay, az);
-#pragma unroll
-            for (int u = 0; u < kFbBatch; ++u) {
-                cxz += fmax_(ax[u], az[u]) < eps;
-                cyz += fmax_(ay[u], az[u]) < eps;
-                cz += az[u] < eps;
-            }
+    } else {
+        const uint32_t first = (uint32_t)bid_x() * kFbWaves + (uint32_t)wave;
+        const uint32_t n_waves = (uint32_t)L.fb_grid * kFbWaves;
+        for (uint32_t it = first; it < total; it += n_waves) {
+            const FbPair p = fb_pair(L, it);
+            float top[KMAX];
+            fb_topk<KMAX>(p, lane, 64, top);
+            const float eps = wave_kth<KMAX>(top, p.J->k, nullptr);
+            int c3[3];
+            fb_counts(p, lane, 64, eps, c3);
+            for (int t = 0; t < 3; ++t) c3[t] = wave_sum(c3[t]);
+            if (lane == 0) fb_store(p, eps, c3);
         }
-        cxz = wave_sum(cxz);
-        cyz = wave_sum(cyz);
-        cz = wave_sum(cz);
-        if (lane == 0) { wcnt[wave][0] = cxz; wcnt[wave][1] = cyz; wcnt[wave][2] = cz; }
-        __syncthreads();
-        if (tid == 0) {
-            int c3[3] = {0, 0, 0};
-            for (int w = 0; w < kFbWaves; ++w)
-                for (int t = 0; t < 3; ++t) c3[t] += wcnt[w][t];
-            J.eps[(int64_t)e * n + i] = eps;
-            for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
-        }
-        __syncthreads();
     }
 }
 
@@ -870,6 +1003,12 @@ int launch_list_fallback(const ListLaunch &L, void *stream) {
     else if (L.kmax == 8) hipLaunchKernelGGL(list_fallback_kernel<8>, grid, block, 0, (hipStream_t)stream, L);
     else if (L.kmax == 16) hipLaunchKernelGGL(list_fallback_kernel<16>, grid, block, 0, (hipStream_t)stream, L);
     else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_sortx(const ListLaunch &L, void *stream) {
+    if (L.n_jobs <= 0) return 0;
+    hipLaunchKernelGGL(list_sortx_kernel, dim3((unsigned)L.n_jobs), dim3(kSortThreads), 0, (hipStream_t)stream, L);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

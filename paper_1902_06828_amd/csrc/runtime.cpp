@@ -273,8 +273,11 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
     std::vector<int> gid(specs.size(), -1);
     for (size_t j = 0; j < specs.size(); ++j) {
         const JobSpec &sp = specs[j];
-        // the list kernels index the transposed X columns with 32-bit offsets
-        if (sp.dz <= 0 || force == 0 || (int64_t)sp.dx * sp.n * sp.n_est() >= ((int64_t)1 << 31)) continue;
+        // the list kernels index the transposed X columns with 32-bit offsets;
+        // without Z the list path needs one X column (its range counts use
+        // the sorted column) and N within the in-LDS sort
+        if (force == 0 || (int64_t)sp.dx * sp.n * sp.n_est() >= ((int64_t)1 << 31)) continue;
+        if (sp.dz == 0 && (sp.dx != 1 || sp.n > kNoZSortMax)) continue;
         std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz, (uintptr_t)sp.theiler};
         for (int c = 0; c < sp.dy + sp.dz; ++c) key.push_back((uintptr_t)sp.cols[sp.dx + c]);
         auto it = groups.emplace(key, (int)group_est.size()).first;
@@ -513,18 +516,25 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
 constexpr double kListSetBytes = 4.0 * (1 << 30);
 
 static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
-    const int e = dx + dy - dz;
-    *m1 = e >= 2 ? 8192 : e == 1 ? 4096 : e == 0 ? 2048 : 1024;
-    while (*m1 > 1024 && (double)n * (std::min(n - 1, *m1) * (double)sizeof(LEnt) +
-                                      std::min(n - 1, 2 * *m1) * (double)sizeof(LEnt2)) > kListSetBytes)
-        *m1 /= 2;
-    *m2 = 2 * *m1;
+    if (dz == 0) {
+        // no Z list; list 1 holds every row when it fits (an incomplete list
+        // leaves the surrogates whose permuted x is an outlier undecided)
+        *m1 = (int)std::max<double>(1024.0, std::min<double>(n - 1.0, kListSetBytes / ((double)n * sizeof(LEnt))));
+        *m2 = 0;
+    } else {
+        const int e = dx + dy - dz;
+        *m1 = e >= 2 ? 8192 : e == 1 ? 4096 : e == 0 ? 2048 : 1024;
+        while (*m1 > 1024 && (double)n * (std::min(n - 1, *m1) * (double)sizeof(LEnt) +
+                                          std::min(n - 1, 2 * *m1) * (double)sizeof(LEnt2)) > kListSetBytes)
+            *m1 /= 2;
+        *m2 = 2 * *m1;
+    }
     const char *v = std::getenv("MTE_LIST_CAP");
     if (v && *v) {
         int a = 0, b = 0;
         if (std::sscanf(v, "%d,%d", &a, &b) == 2 && a >= 1 && b >= 1) {
             *m1 = a;
-            *m2 = b;
+            *m2 = dz == 0 ? 0 : b;
         }
     }
 }
@@ -584,13 +594,15 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         o_bound[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * 2 * (size_t)sp.n, 256);
     }
-    struct Off { size_t xt, eps, cnt; };
+    struct Off { size_t xt, eps, cnt, xs; };
     std::vector<Off> offs(n_ljobs_);
     for (int j = 0; j < n_ljobs_; ++j) {
         const JobSpec &sp = specs[j];
         const size_t pairs = (size_t)sp.n * sp.n_est();
         offs[j].xt = bytes;
         bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
+        offs[j].xs = bytes;
+        if (sp.dz == 0) bytes = align_up(bytes + sizeof(float) * (size_t)sp.n, 256);
         if (!sp.diag_eps) {
             offs[j].eps = bytes;
             bytes = align_up(bytes + sizeof(float) * pairs, 256);
@@ -645,6 +657,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.reps = sp.reps;
         J.rep_shuffle = sp.rep_shuffle;
         J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
+        J.xs = sp.dz == 0 ? reinterpret_cast<float *>(sb + offs[j].xs) : nullptr;
         J.eps = sp.diag_eps ? sp.diag_eps : reinterpret_cast<float *>(sb + offs[j].eps);
         J.cnt = sp.diag_cnt ? sp.diag_cnt : reinterpret_cast<int32_t *>(sb + offs[j].cnt);
         J.out = sp.out;
@@ -685,7 +698,9 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.counters = lcounters_.as<uint32_t>();
     L.kmax = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
     L.dxm = dxm <= 1 ? 1 : kMaxDx;
-    L.fb_grid = std::max(1, c.n_cu);
+    L.fb_grid = std::max(1, 2 * c.n_cu);
+    L.sortx = 0;
+    for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
     if (L.lanes >= ((int64_t)1 << 40) || n_ljobs_ >= (1 << 23)) return fail(MTE_EINVAL, "batch too large");
     n_est_pairs_ = L.lanes;
     MTE_HIP(hipMemcpyAsync(tb, hs, tbytes, hipMemcpyHostToDevice, s));
@@ -866,6 +881,7 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         ll_.stats = ctx().list_stats ? 1 : 0;
         if ((rc = begin())) return rc;
         if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
+        if (ll_.sortx && launch_list_sortx(ll_, s)) return hip_fail(hipGetLastError(), "X sort launch");
         if ((rc = end(kStageBuild))) return rc;
         if ((rc = begin())) return rc;
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");

@@ -19,7 +19,10 @@ from test_gpu_parity import CASES, check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
-LIST_CASES = [c for c in CASES if c[1][2] > 0]
+# every case with Z, and the cases without Z with one X column (their n_x
+# comes from range counts on the sorted X column)
+LIST_CASES = [c for c in CASES if c[1][2] > 0 or c[1][0] == 1] + [
+    (3000, (1, 2, 0), 4, "grid", 3), (1000, (1, 1, 0), 4, "dup", 2), (4097, (1, 1, 0), 8, "wide", 1)]
 
 
 def say(*a):
@@ -47,7 +50,10 @@ def test_list_path_parity(monkeypatch, caps, n, dims, k, kind, S):
                                               (1000, (1, 2, 7), "grid", 3), (4097, (1, 1, 1), "wide", 4),
                                               # more dimensions outside Z than in it: the capacities
                                               # grow (to 8192 / 16384 entries) but stay below N - 1
-                                              (20000, (3, 1, 1), "normal", 5), (12000, (2, 1, 2), "normal", 6)])
+                                              (20000, (3, 1, 1), "normal", 5), (12000, (2, 1, 2), "normal", 6),
+                                              # without Z: up to the largest N of the in-LDS X sort
+                                              (4000, (1, 1, 0), "grid", 7), (16384, (1, 2, 0), "normal", 8),
+                                              (10000, (1, 1, 0), "dup", 9)])
 def test_list_equals_all_pairs(monkeypatch, n, dims, kind, seed):
     X, Y, Z = synth.random_points(n, dims, seed=seed, kind=kind)
     out = {}

@@ -38,6 +38,7 @@ CASES = [
     (600, (1, 1, 5), 4, "normal", 7),
     (300, (2, 1, 3), 3, "dup", 2),
     (130, (1, 2, 1), 1, "wide", 10),
+    (1000, (1, 2, 0), 4, "grid", 5),
 ]
 
 
@@ -57,6 +58,9 @@ def test_theiler_small_caps_and_full_size(monkeypatch):
     X, Y, Z = synth.random_points(400, (1, 1, 3), seed=77)
     say("theiler, tiny caps")
     check(X, Y, Z, 4, 9, 4)
+    X, Y, _ = synth.random_points(400, (1, 1, 0), seed=78)
+    say("theiler, tiny caps, no Z")
+    check(X, Y, None, 4, 9, 4)
     monkeypatch.delenv("MTE_LIST_CAP")
     # the benchmark's sample with a window of 5: both paths, same bits
     X, Y, Z, _ = synth.c2_te_inputs(10000, seed=2)
