@@ -19,9 +19,11 @@
 //            radius is exact when it stopped that way or when the k-th
 //            distance is at most the list's bound.  n_z, n_yz and n_xz scan
 //            list 2 (whose entries also carry d_yz) until its bucket floor
-//            reaches eps, exact when it stopped that way or eps <= its bound;
+//            reaches eps, exact when it stopped that way or eps <= its bound.
+//            Without Z (one X column) there is no list 2: n_y comes from list
+//            1 and n_x from range counts on the sorted X column;
 //   fallback the pairs the lists cannot decide (rare) are queued and redone
-//            by one wave each over all rows;
+//            over all rows (a block per pair, or a wave when they are many);
 //   reduce   the digamma sum per estimate in the same fixed order as the
 //            all-pairs kernel (64-row butterfly, then chunks in index order),
 //            so both paths return the same bits.

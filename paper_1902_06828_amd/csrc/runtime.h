@@ -88,9 +88,10 @@ struct TileChoice {
 
 // Which path runs each job of a batch: -1 = all-pairs kernel, otherwise the
 // index of the job's neighbour-list set (jobs with the same N and the same Y
-// and Z columns share one set).  The list path is used for jobs with Z
-// columns whose set carries at least kListMinEstimates estimates (and whose
-// permuted X columns hold fewer than 2^31 values); the
+// and Z columns share one set).  The list path is used for jobs whose set
+// carries at least kListMinEstimates estimates, that have Z columns or else
+// one X column and N <= kNoZSortMax, and whose permuted X columns hold fewer
+// than 2^31 values; the
 // environment variable MTE_FORCE_MODE=brute|list overrides that (results are
 // the same either way).
 constexpr int kListMinEstimates = 8;
