@@ -217,6 +217,15 @@ int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_
 /* The mode MTE_SHUFFLE_AUTO picks for R replications and S surrogates. */
 int mte_shuffle_mode(int R, int S, int *mode_out);
 
+/* Per-node z-score applied by the greedy search and network inference when
+ * mte_opts.standardise is set (the paper is silent on normalisation; KSG's
+ * max-norm is not scale invariant, so every node is put on one scale): for
+ * each node, over all its R*T samples in order (replications, then time),
+ * mean and variance (1/(R*T)) as float64 sums in that order, and each value
+ * (x - mean)/sd computed in float64 and rounded to float32; a constant node
+ * becomes all zeros.  in, out: host [R][P][T] (may be the same array). */
+int mte_standardise(const float *in, int R, int P, int64_t T, float *out);
+
 /* Source rows of surrogate s (host computation of the kernels' definition):
  * out[i] = the candidate row that row i takes.  N a multiple of R; mode
  * WITHIN or REPLICATIONS (REPLICATIONS needs R >= 2). */
@@ -271,6 +280,8 @@ typedef struct {
                            replication; the rows of all replications are pooled
                            (N = R*(T-L)) and the surrogates follow MTE_SHUFFLE_AUTO;
                            needs theiler = 0 when R > 1 (not for the _sid form) */
+    int standardise;    /* 1 (default): z-score each node series once before embedding
+                           (mte_standardise); 0: use the data as given */
 } mte_opts;
 
 /* Estimators of the greedy search.  KSG: every test is a surrogate test

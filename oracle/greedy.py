@@ -24,10 +24,10 @@ Readings fixed where the paper is silent (each also used by the library):
     every candidate of every max/min-statistic round takes the next tid, in
     candidate order, and draws its S surrogates with keys (seed, tid, s); the
     omnibus test takes the next tid after pruning;
+  * each node series is z-scored once before embedding (standardise());
   * alpha_max = alpha_min = alpha_omnibus = alpha;
   * the reported CMI and p of a selected variable are those of the test that
     selected it; an empty X^S skips the omnibus test (p = 1, not significant);
-  * no normalisation of the series.
 """
 
 from __future__ import annotations
@@ -35,6 +35,30 @@ from __future__ import annotations
 import numpy as np
 
 from . import gauss, ksg, perm, stats
+
+
+def standardise(series: np.ndarray) -> np.ndarray:
+    """Per-node z-score (reading: the paper is silent on normalisation; every
+    node is put on one scale before embedding).  For each node, over its
+    samples in order (replications, then time): mean = sum / count and
+    variance = sum((x - mean)^2) / count, both sums float64 and sequential
+    (np.cumsum), sd = sqrt(variance); each value (x - mean) / sd in float64,
+    rounded to float32; a constant node becomes 0."""
+    s = np.asarray(series)
+    out = np.empty(s.shape, dtype=np.float32)
+    nodes = s.shape[-2]
+    for p in range(nodes):
+        v = (s[:, p, :] if s.ndim == 3 else s[p]).astype(np.float64)
+        flat = v.reshape(-1)
+        mean = np.cumsum(flat)[-1] / flat.size
+        dev = flat - mean
+        sd = np.sqrt(np.cumsum(dev * dev)[-1] / flat.size)
+        z = (dev / sd if sd > 0 else np.zeros_like(dev)).astype(np.float32).reshape(v.shape)
+        if s.ndim == 3:
+            out[:, p, :] = z
+        else:
+            out[p] = z
+    return out
 
 
 def embed(series: np.ndarray, node: int, lag: int, l_m: int) -> np.ndarray:
@@ -96,7 +120,7 @@ def _numpy_estimator(x, y, z, k, theiler=0):
 def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
                    max_lag_target: int = 5, alpha: float = 0.05, k: int = 4,
                    n_surr: int = 200, seed: int = 0, estimator=None, theiler: int = 0,
-                   null: str = "surrogate"):
+                   null: str = "surrogate", standardise_series: bool = True):
     """null = "surrogate": the KSG estimator (or `estimator`) with the
     surrogate tests.  null = "analytic": the Gaussian estimator with the
     analytic (chi^2) null of oracle/gauss.py; no surrogates are drawn.
@@ -108,6 +132,8 @@ def select_sources(series, target: int, candidates, max_lag_sources: int = 5,
         raise TypeError("series must be float32")
     if series.ndim == 3 and theiler:
         raise ValueError("the Theiler window is defined for a single replication")
+    if standardise_series:
+        series = standardise(series)
     analytic = null == "analytic"
     if analytic:
         n_surr = 0

@@ -28,7 +28,7 @@ from . import greedy, stats
 
 def infer_network(series, max_lag_sources: int = 5, max_lag_target: int = 5, alpha: float = 0.05,
                   alpha_fdr: float | None = 0.05, k: int = 4, n_surr: int = 200, seed: int = 0,
-                  estimator=None, theiler: int = 0, null: str = "surrogate"):
+                  estimator=None, theiler: int = 0, null: str = "surrogate", standardise_series: bool = True):
     """Returns (adjacency uint8 [P][P] with A[s][t] = 1 for an inferred link
     s -> t, per-target results of greedy.select_sources, FDR keep mask [P])."""
     series = np.asarray(series)
@@ -39,7 +39,8 @@ def infer_network(series, max_lag_sources: int = 5, max_lag_target: int = 5, alp
         results.append(greedy.select_sources(series, t, cands, max_lag_sources=max_lag_sources,
                                              max_lag_target=max_lag_target, alpha=alpha, k=k,
                                              n_surr=n_surr, seed=(seed + t) % (1 << 64),
-                                             estimator=estimator, theiler=theiler, null=null))
+                                             estimator=estimator, theiler=theiler, null=null,
+                                             standardise_series=standardise_series))
     pvals = np.array([r["omnibus_p"] for r in results])
     if alpha_fdr is None:
         keep = np.ones(P, dtype=bool)

@@ -44,6 +44,7 @@ from ._lib import (  # noqa: F401
     mte_series_register,
     mte_series_release,
     mte_shuffle_mode,
+    mte_standardise,
     mte_shutdown,
     mte_submit,
     mte_tile_configs,

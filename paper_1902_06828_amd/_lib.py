@@ -29,7 +29,7 @@ class MteError(RuntimeError):
 class mte_opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("S", ctypes.c_int), ("max_lag_target", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("theiler", ctypes.c_int), ("estimator", ctypes.c_int),
-                ("replications", ctypes.c_int)]
+                ("replications", ctypes.c_int), ("standardise", ctypes.c_int)]
 
 
 class mte_var(ctypes.Structure):
@@ -112,6 +112,7 @@ SIGNATURES = {
     "mte_gauss_cmi_sets": [_P, _I, _I, _P, _P, _P, _P],
     "mte_chi2_sf": [_D, _I, _P],
     "mte_shuffle_mode": [_I, _I, _P],
+    "mte_standardise": [_P, _I, _I, _I64, _P],
     "mte_permutation_rep": [_U64, _U32, _U32, _I64, _I, _I, _P],
     "cmi_ksg_surrogates_rep": [_P, _I, _P, _I, _P, _I, _I64, _I, _I, _I, _U64, _U32, _I, _P, _P],
 }
@@ -320,11 +321,11 @@ def _result_dict(res, tp, src):
     }
 
 
-def _opts(k, S, max_lag_target, seed, theiler=0, estimator="ksg", replications=1):
+def _opts(k, S, max_lag_target, seed, theiler=0, estimator="ksg", replications=1, standardise=True):
     if estimator not in ESTIMATORS:
         raise ValueError(f"estimator must be one of {sorted(ESTIMATORS)}")
     return mte_opts(k=k, S=S, max_lag_target=max_lag_target, seed=seed, theiler=theiler,
-                    estimator=ESTIMATORS[estimator], replications=replications)
+                    estimator=ESTIMATORS[estimator], replications=replications, standardise=int(bool(standardise)))
 
 
 def _series(data):
@@ -339,14 +340,14 @@ def _series(data):
 
 def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, alpha: float = 0.05,
                        k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
-                       estimator: str = "ksg"):
+                       estimator: str = "ksg", standardise: bool = True):
     """data: float32 [P][T], or [R][P][T] for R replications."""
     data, R, P, T = _series(data)
     cands = np.ascontiguousarray(candidates, dtype=np.int32)
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R, standardise)
     _check(lib().mte_select_sources(_ptr(data), P, T, target, _ptr(cands),
                                     len(cands), max_lag_sources, alpha, ctypes.byref(o),
                                     ctypes.byref(res)))
@@ -355,12 +356,12 @@ def mte_select_sources(data, target: int, candidates, max_lag_sources: int = 5, 
 
 def mte_select_sources_sid(sid: int, target: int, candidates, max_lag_sources: int = 5,
                            alpha: float = 0.05, k: int = 4, S: int = 200, max_lag_target: int = 5,
-                           seed: int = 0, theiler: int = 0, estimator: str = "ksg"):
+                           seed: int = 0, theiler: int = 0, estimator: str = "ksg", standardise: bool = True):
     cands = np.ascontiguousarray(candidates, dtype=np.int32)
     tp = (mte_var * max(1, max_lag_target))()
     src = (mte_var * max(1, len(cands) * max_lag_sources))()
     res = mte_result(target_past=tp, sources=src)
-    o = _opts(k, S, max_lag_target, seed, theiler, estimator)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator, 1, standardise)
     _check(lib().mte_select_sources_sid(sid, target, _ptr(cands), len(cands), max_lag_sources, alpha,
                                         ctypes.byref(o), ctypes.byref(res)))
     return _result_dict(res, tp, src)
@@ -479,13 +480,13 @@ def mte_link_metrics(inferred, truth):
 
 def mte_infer_network(data, max_lag_sources: int = 5, alpha: float = 0.05, alpha_fdr: float = 0.05,
                       k: int = 4, S: int = 200, max_lag_target: int = 5, seed: int = 0, theiler: int = 0,
-                      n_threads: int = 0, estimator: str = "ksg"):
+                      n_threads: int = 0, estimator: str = "ksg", standardise: bool = True):
     """data: float32 [P][T], or [R][P][T] for R replications.  Returns
     (adjacency uint8 [P][P], per-target summaries as dicts)."""
     data, R, P, T = _series(data)
     adj = np.zeros((P, P), np.uint8)
     tgt = (mte_target_summary * P)()
-    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R)
+    o = _opts(k, S, max_lag_target, seed, theiler, estimator, R, standardise)
     _check(lib().mte_infer_network(_ptr(data), P, T, max_lag_sources, alpha,
                                    alpha_fdr if alpha_fdr else 0.0, ctypes.byref(o), n_threads, _ptr(adj), tgt))
     summ = [{name: getattr(tgt[t], name) for name, _ in mte_target_summary._fields_} for t in range(P)]
@@ -558,3 +559,12 @@ def cmi_ksg_surrogates_rep(X, Y, Z=None, k: int = 4, S: int = 20, R: int = 1, se
     _check(lib().cmi_ksg_surrogates_rep(_ptr(X), dx, _ptr(Y), dy, _ptr(Z), dz, n, R, k, S, seed, cand,
                                         SHUFFLE[mode], ctypes.byref(out), _ptr(surr)))
     return out.value, surr
+
+
+def mte_standardise(data):
+    """Per-node z-score of float32 [P][T] or [R][P][T] data (the greedy search's
+    normalisation)."""
+    data, R, P, T = _series(data)
+    out = np.empty_like(data)
+    _check(lib().mte_standardise(_ptr(data), R, P, T, _ptr(out)))
+    return out

@@ -325,6 +325,14 @@ int mte_permutation(uint64_t seed, uint32_t cand, uint32_t s, int64_t N, uint32_
     return MTE_OK;
 }
 
+int mte_standardise(const float *in, int R, int P, int64_t T, float *out) {
+    if (!in || !out || R < 1 || P < 1 || T < 1) return fail(MTE_EINVAL, "bad arguments");
+    int rc;
+    if ((rc = validate_host_finite(in, (int64_t)R * P * T, "data"))) return rc;
+    standardise_host(in, R, P, T, out);
+    return MTE_OK;
+}
+
 int mte_shuffle_mode(int R, int S, int *mode_out) {
     if (!mode_out || R < 1 || S < 1) return fail(MTE_EINVAL, "bad arguments");
     *mode_out = shuffle_mode(R, S);

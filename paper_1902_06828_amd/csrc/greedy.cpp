@@ -470,11 +470,13 @@ static mte_opts opts_or_default(const mte_opts *o) {
     d.theiler = 0;
     d.estimator = MTE_ESTIMATOR_KSG;
     d.replications = 1;
+    d.standardise = 1;
     return o ? *o : d;
 }
 
 int series_pin(int32_t sid, const float **dev, int *P, int64_t *T);
 void series_unpin(int32_t sid);
+int series_standardised(int32_t sid, int32_t *std_sid);
 
 // Greedy search of one target over resident columns (arguments checked).
 int select_sources_columns(const Columns &c, int target, const int32_t *candidates, int n_candidates,
@@ -497,6 +499,7 @@ int select_sources_served(int32_t sid, int P, int64_t T, int target, const int32
     if (o.replications != 1)
         return fail(MTE_EINVAL, "a registered series has one replication (use mte_select_sources or "
                                 "mte_infer_network for replications)");
+    if (o.standardise && (rc = series_standardised(sid, &sid))) return rc;
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
     if (o.estimator == MTE_ESTIMATOR_GAUSS) {
         const float *dev;
@@ -574,6 +577,13 @@ int mte_select_sources(const float *data, int P, int64_t T, int target, const in
     if (!data) return fail(MTE_EINVAL, "null data");
     if ((rc = ensure_init())) return rc;
     const int l_m = std::max(max_lag_sources, o.max_lag_target);
+    std::vector<float> z;
+    if (o.standardise) {
+        if ((rc = validate_host_finite(data, (int64_t)o.replications * P * T, "data"))) return rc;
+        z.resize((size_t)o.replications * P * T);
+        standardise_host(data, o.replications, P, T, z.data());
+        data = z.data();
+    }
     hipStream_t s;
     MTE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     DevBuf series, emb;

@@ -87,6 +87,7 @@ int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, 
     base.theiler = 0;
     base.estimator = MTE_ESTIMATOR_KSG;
     base.replications = 1;
+    base.standardise = 1;
     if (opts) base = *opts;
     // One replication: every target's search goes through the request loop
     // (concurrent targets share batches).  Several: the embedding of all
@@ -98,6 +99,14 @@ int mte_infer_network(const float *data, int P, int64_t T, int max_lag_sources, 
     DevBuf series, emb;
     Columns cols;
     int rc;
+    std::vector<float> z;
+    if (base.standardise) {
+        if ((rc = validate_host_finite(data, (int64_t)R * P * T, "data"))) return rc;
+        z.resize((size_t)R * P * T);
+        standardise_host(data, R, P, T, z.data());
+        data = z.data();
+        base.standardise = 0;        // the targets' searches use the z-scored copy
+    }
     if (R == 1) {
         if ((rc = mte_series_register(data, P, T, &sid))) return rc;
     } else {

@@ -251,6 +251,33 @@ int validate_host_finite(const float *p, int64_t count, const char *name) {
     return MTE_OK;
 }
 
+// z-score of each node over all its samples (replications, then time):
+// mean and variance (1/count) as float64 sums in sample order, each value
+// (x - mean) / sd in float64 rounded to float32; a constant node becomes 0.
+void standardise_host(const float *in, int R, int P, int64_t T, float *out) {
+#pragma clang fp contract(off)
+    const double count = (double)R * (double)T;
+    for (int p = 0; p < P; ++p) {
+        double sum = 0.0;
+        for (int r = 0; r < R; ++r)
+            for (int64_t t = 0; t < T; ++t) sum += (double)in[((int64_t)r * P + p) * T + t];
+        const double mean = sum / count;
+        double ss = 0.0;
+        for (int r = 0; r < R; ++r)
+            for (int64_t t = 0; t < T; ++t) {
+                const double d = (double)in[((int64_t)r * P + p) * T + t] - mean;
+                const double sq = d * d;
+                ss += sq;
+            }
+        const double sd = std::sqrt(ss / count);
+        for (int r = 0; r < R; ++r)
+            for (int64_t t = 0; t < T; ++t) {
+                const int64_t x = ((int64_t)r * P + p) * T + t;
+                out[x] = sd > 0.0 ? (float)(((double)in[x] - mean) / sd) : 0.0f;
+            }
+    }
+}
+
 void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b) {
     Ctx &c = ctx();
     std::lock_guard<std::mutex> lk(c.mu);

@@ -199,4 +199,7 @@ double harmonic_host(int64_t n);
 
 void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b);
 
+// Per-node z-score of a host series [R][P][T] (see runtime.cpp).
+void standardise_host(const float *in, int R, int P, int64_t T, float *out);
+
 }  // namespace mte

@@ -32,6 +32,7 @@ struct Series {
     int P = 0;
     int64_t T = 0;
     int pending = 0;
+    int32_t std_sid = -1;   // its per-node z-scored copy, made on first use
 };
 
 struct Req {
@@ -309,6 +310,45 @@ int series_pin(int32_t sid, const float **dev, int *P, int64_t *T) {
     return MTE_OK;
 }
 
+// The z-scored copy of a registered series (mte_standardise), registered
+// as a series of its own on first use and released with the original.
+int series_standardised(int32_t sid, int32_t *std_sid) {
+    Server &sv = server();
+    int P;
+    int64_t T;
+    std::vector<float> host;
+    {
+        std::lock_guard<std::mutex> lk(sv.mu);
+        auto it = sv.series.find(sid);
+        if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+        if (it->second.std_sid >= 0) {
+            *std_sid = it->second.std_sid;
+            return MTE_OK;
+        }
+        P = it->second.P;
+        T = it->second.T;
+        host.resize((size_t)P * T);
+        MTE_HIP(hipMemcpy(host.data(), it->second.buf->p, sizeof(float) * host.size(), hipMemcpyDeviceToHost));
+    }
+    standardise_host(host.data(), 1, P, T, host.data());
+    int32_t made = -1;
+    int rc = mte_series_register(host.data(), P, T, &made);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it == sv.series.end()) {
+        sv.series.erase(made);
+        return fail(MTE_EINVAL, "series %d was released", sid);
+    }
+    if (it->second.std_sid >= 0) {
+        sv.series.erase(made);       // another thread made it first
+    } else {
+        it->second.std_sid = made;
+    }
+    *std_sid = it->second.std_sid;
+    return MTE_OK;
+}
+
 void series_unpin(int32_t sid) {
     Server &sv = server();
     std::lock_guard<std::mutex> lk(sv.mu);
@@ -347,7 +387,14 @@ int mte_series_release(int32_t sid) {
     auto it = sv.series.find(sid);
     if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
     if (it->second.pending > 0) return fail(MTE_EBUSY, "series %d has pending requests", sid);
-    sv.series.erase(it);
+    const int32_t std_sid = it->second.std_sid;
+    if (std_sid >= 0) {
+        auto st = sv.series.find(std_sid);
+        if (st != sv.series.end() && st->second.pending > 0)
+            return fail(MTE_EBUSY, "series %d has pending requests", sid);
+        if (st != sv.series.end()) sv.series.erase(st);
+    }
+    sv.series.erase(sid);
     return MTE_OK;
 }
 

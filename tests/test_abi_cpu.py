@@ -215,3 +215,13 @@ def test_replication_argument_validation():
     s = g.standard_normal((4, 3, 60)).astype(np.float32)
     with pytest.raises(mte.MteError, match="Theiler"):
         mte.mte_select_sources(s, 0, [1, 2], max_lag_sources=2, max_lag_target=2, S=40, theiler=1)
+
+
+def test_standardise_matches_oracle():
+    from oracle import greedy
+    g = np.random.default_rng(9)
+    s = (g.standard_normal((5, 2003)) * 3 + 11).astype(np.float32)
+    s[2] = -1.5                                     # constant node
+    assert np.array_equal(mte.mte_standardise(s).view(np.uint32), greedy.standardise(s).view(np.uint32))
+    r = (g.standard_normal((3, 4, 700)) * 0.01).astype(np.float32)
+    assert np.array_equal(mte.mte_standardise(r).view(np.uint32), greedy.standardise(r).view(np.uint32))

@@ -75,3 +75,27 @@ def test_analytic_null_on_independent_series_selects_little():
                                     alpha=0.05, null="analytic")
         hits += len(res["sources"]) > 0
     assert hits <= 3
+
+
+def test_standardise_definition():
+    # mean 0 and variance 1 (float32 rounding), constant node -> zeros,
+    # scaling a node by a power of two leaves its z-scores bit-identical
+    # (mean and sd scale exactly), and replications are pooled per node.
+    g = np.random.default_rng(3)
+    s = (g.standard_normal((4, 3001)) * [[3.0], [0.01], [100.0], [1.0]] + [[5], [-2], [0], [1e3]])
+    s = s.astype(np.float32)
+    s[3] = 7.25
+    z = greedy.standardise(s)
+    for p in range(3):
+        assert abs(z[p].astype(np.float64).mean()) < 1e-6
+        assert abs(z[p].astype(np.float64).var() - 1.0) < 1e-5
+    assert np.all(z[3] == 0)
+    s2 = s.copy()
+    s2[0] *= np.float32(8.0)
+    s2[1] *= np.float32(0.125)
+    z2 = greedy.standardise(s2)
+    assert np.array_equal(z2.view(np.uint32), z.view(np.uint32))
+    r = g.standard_normal((3, 2, 500)).astype(np.float32)
+    zr = greedy.standardise(r)
+    pooled = greedy.standardise(np.concatenate([r[0], r[1], r[2]], axis=1))
+    assert np.array_equal(np.concatenate([zr[0], zr[1], zr[2]], axis=1), pooled)
