@@ -59,8 +59,9 @@ struct Job {
     int32_t *diag_cnt;            // optional [n_est][3][n] (n_xz, n_yz, n_z)
     // neighbour-list path only (see ListSet): list set index, and the
     // permuted X columns transposed so that the estimates of one row are
-    // adjacent: xt[c][i][e] = X_c[pi_e(i)] ([dx][n][n_est]).  eps and cnt
-    // hold the per-row radii and counts ([n_est][n], [n_est][3][n]).
+    // adjacent: xt[c][i][e] = X_c[pi_e(i)] ([dx][n][n_est]).  The per-row
+    // counts go to pk; eps and cnt are the caller's diagnostics ([n_est][n],
+    // [n_est][3][n]) or null.
     int set;
     float *xt;
     int theiler;                  // Theiler window w: pairs with |i - j| <= w are left out
@@ -69,7 +70,14 @@ struct Job {
     // list path without Z (dz = 0, dx = 1): the job's X column sorted
     // ascending (n floats), for the n_x range counts; null otherwise
     float *xs;
+    // list path: each (row, estimate)'s counts in one word,
+    // n_xz | n_yz << kPackBits | n_z << 2 kPackBits ([n_est][n])
+    uint64_t *pk;
 };
+
+// Counts of the list path are packed kPackBits to a field: N <= kListMaxN.
+constexpr int kPackBits = 21;
+constexpr int kListMaxN = 1 << kPackBits;
 
 // Largest N of a list-path job without Z (its X column is sorted in LDS).
 constexpr int kNoZSortMax = 16384;
@@ -99,6 +107,7 @@ constexpr int kListPad = 8;                   // sentinel entries after each row
 
 struct ListSet {
     const float *cols[kMaxDy + kMaxDz];   // Y columns, then Z columns
+    float *zy;                    // [dz + dy][n] contiguous copy: Z columns, then Y (build input)
     int n, dy, dz;
     int theiler;                  // Theiler window of the rows (|i - j| <= w left out)
     int m1, m2;                   // list capacities per row

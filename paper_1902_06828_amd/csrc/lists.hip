@@ -57,8 +57,29 @@ constexpr uint32_t kFloorMask = ~((1u << kKeyShift) - 1u);
 __device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
 __device__ __forceinline__ int64_t bid_x() { return (int64_t)__builtin_amdgcn_workgroup_id_x(); }
 
+// Load through a global-address-space pointer: a generic (flat) load would
+// count against both the vector-memory and the LDS counters, and the wait for
+// the gathers would then also wait for the next step's entries loaded ahead.
+__device__ __forceinline__ float gload(const float *p, uint32_t off) {
+    return ((const __attribute__((address_space(1))) float *)p)[off];
+}
+
+// The same with a byte offset: the address is then a uniform base plus one
+// 32-bit register, the form the global loads take without address arithmetic.
+__device__ __forceinline__ float gload_b(const float *p, uint32_t byte_off) {
+    return *(const __attribute__((address_space(1))) float *)((const __attribute__((address_space(1))) char *)p +
+                                                              byte_off);
+}
+
+constexpr uint64_t kPackMask = (uint64_t(1) << kPackBits) - 1;
+
+__device__ __forceinline__ uint64_t pack_counts(int cxz, int cyz, int cz) {
+    return (uint64_t)(uint32_t)cxz | ((uint64_t)(uint32_t)cyz << kPackBits) |
+           ((uint64_t)(uint32_t)cz << (2 * kPackBits));
+}
+
 __device__ __forceinline__ uint32_t key_of(float d) {
-    return (__float_as_uint(d) >> kKeyShift) & kKeyMask;
+    return __builtin_amdgcn_ubfe(__float_as_uint(d), kKeyShift, 32 - kKeyShift - 1);
 }
 
 // Smallest value of d's bucket (d >= 0).
@@ -78,7 +99,16 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
-// Inclusive scan over the 256 threads of a block; returns the block total.
+// Threads per build block: 8 waves, so that the 4 blocks whose histograms fit
+// in LDS keep 8 waves on every SIMD (the kernel waits mostly on LDS atomics
+// and L2 loads, and needs the waves to hide them).
+#ifndef MTE_BUILD_THREADS
+#define MTE_BUILD_THREADS 512
+#endif
+constexpr int kBT = MTE_BUILD_THREADS;
+constexpr int kBW = kBT / 64;
+
+// Inclusive scan over the kBT threads of a build block; returns the block total.
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint32_t *wtot) {
     const int lane = tid_x() & 63, wave = tid_x() >> 6;
 #pragma unroll
@@ -90,7 +120,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint3
     __syncthreads();
     uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kBW; ++w) {
         before += w < wave ? wtot[w] : 0u;
         total += wtot[w];
     }
@@ -113,20 +143,21 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint3
 template <int QB>
 constexpr int row_batch() { return QB == 1 ? 8 : 4; }   // reference rows per thread per step
 
-// Bucket b of a histogram lives at word b + b/16: a thread's 16 consecutive
-// buckets then start 17 words after its neighbour's, so the selection's
-// per-thread walks fall into different LDS banks.
-constexpr int kHistWords = kKeyBins + kKeyBins / 16;
+// The selection gives each thread kPer consecutive buckets (read and written
+// as 16-byte words).  Bucket b of a histogram is word b: the passes over the
+// pairs then take a bucket's address straight from the distance's bits.
+constexpr int kPer = kKeyBins / kBT;
+constexpr int kHistWords = kKeyBins;
 
-__device__ __forceinline__ uint32_t hist_slot(uint32_t key) { return key + (key >> 4); }
+__device__ __forceinline__ uint32_t hist_slot(uint32_t key) { return key; }
 
 template <int QB, int C, bool PACK>
 struct BuildSmem {
     static constexpr int kCopy = PACK ? kHistWords : 2 * kHistWords;   // words of one copy
-    uint32_t h[QB][C][kCopy];
+    alignas(16) uint32_t h[QB][C][kCopy];
     float q[QB][kMaxDy + kMaxDz];
-    uint32_t wtot[kWaves];
-    uint32_t red[2][kWaves];
+    uint32_t wtot[kBW];
+    uint32_t red[2][kBW];
     uint32_t kept_bins[QB][2], kept_rows[QB][2];
     int set;
 };
@@ -152,33 +183,31 @@ __device__ __forceinline__ void bin_set(uint32_t *wd, int w, uint32_t v) {
     else *wd = v;
 }
 
-// Max-norm over columns [c_lo, c_hi) of `cols` into acc[r][u] for the block
-// rows r and reference rows j0 + u*kBlock; the loads of up to kColChunk
-// columns are issued together before they are used.
+// Max-norm over coordinates [c_lo, c_hi) of the contiguous column copy
+// (column c at zy + c * n) into acc[r][u] for the block rows r and the
+// reference rows whose byte offsets within a column are boff[u]; the loads of
+// up to kColChunk coordinates are issued together before they are used.
 constexpr int kColChunk = 4;
 
 template <int QB, int R>
-__device__ __forceinline__ void acc_cols(const float *const *cols, const float (*q)[kMaxDy + kMaxDz], int qoff,
-                                         int ncols, int n, int i0, int j0, float (&acc)[QB][R]) {
-    for (int c0 = 0; c0 < ncols; c0 += kColChunk) {
+__device__ __forceinline__ void acc_cols(const float *zy, int n, const float (*q)[kMaxDy + kMaxDz], int c_lo,
+                                         int c_hi, const uint32_t (&boff)[R], float (&acc)[QB][R]) {
+    for (int c0 = c_lo; c0 < c_hi; c0 += kColChunk) {
         float v[kColChunk][R];
 #pragma unroll
         for (int cc = 0; cc < kColChunk; ++cc) {
-            if (c0 + cc < ncols) {
-                const float *col = cols[c0 + cc];
+            if (c0 + cc < c_hi) {
+                const float *col = zy + (size_t)(c0 + cc) * n;
 #pragma unroll
-                for (int u = 0; u < R; ++u) {
-                    const int j = j0 + u * kBlock;
-                    v[cc][u] = col[j < n ? j : i0];
-                }
+                for (int u = 0; u < R; ++u) v[cc][u] = gload_b(col, boff[u]);
             }
         }
 #pragma unroll
         for (int cc = 0; cc < kColChunk; ++cc) {
-            if (c0 + cc < ncols) {
+            if (c0 + cc < c_hi) {
 #pragma unroll
                 for (int r = 0; r < QB; ++r) {
-                    const float qc = q[r][qoff + c0 + cc];
+                    const float qc = q[r][c0 + cc];
 #pragma unroll
                     for (int u = 0; u < R; ++u) acc[r][u] = fmax_(acc[r][u], absdiff(qc, v[cc][u]));
                 }
@@ -187,39 +216,53 @@ __device__ __forceinline__ void acc_cols(const float *const *cols, const float (
     }
 }
 
+// Geometry of one list set, held in registers for the whole block.
+struct BuildGeo {
+    const float *zy;
+    int n, dy, dz, w;
+};
+
 // Calls f(r, j, d_z, d_yz) for every block row r (valid rows only) and every
 // row j outside its Theiler window (|j - i| > w; j != i when w = 0),
 // row_batch<QB>() reference rows per thread at a time.
 template <int QB, class F>
-__device__ __forceinline__ void for_each_pair(const ListSet &S, const float (*q)[kMaxDy + kMaxDz], int i0,
+__device__ __forceinline__ void for_each_pair(const BuildGeo &G, const float (*q)[kMaxDy + kMaxDz], int i0,
                                               int nq, int tid, F &&f) {
     constexpr int kRowBatch = row_batch<QB>();
-    const int n = S.n;
-    for (int j0 = tid; j0 < n; j0 += kBlock * kRowBatch) {
+    const int n = G.n, D = G.dy + G.dz;
+    // |j - i| > w  <=>  (unsigned)(j - i + w) > 2w
+    const uint32_t w2 = 2u * (uint32_t)G.w;
+    for (int j0 = tid; j0 < n; j0 += kBT * kRowBatch) {
         float a[QB][kRowBatch], b[QB][kRowBatch];
+        uint32_t boff[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+            const int j = j0 + u * kBT;
+            boff[u] = (uint32_t)(j < n ? j : i0) * 4u;
+        }
 #pragma unroll
         for (int r = 0; r < QB; ++r)
 #pragma unroll
             for (int u = 0; u < kRowBatch; ++u) a[r][u] = 0.f;
-        acc_cols<QB, kRowBatch>(S.cols + S.dy, q, S.dy, S.dz, n, i0, j0, a);
+        acc_cols<QB, kRowBatch>(G.zy, n, q, 0, G.dz, boff, a);
 #pragma unroll
         for (int r = 0; r < QB; ++r)
 #pragma unroll
             for (int u = 0; u < kRowBatch; ++u) b[r][u] = a[r][u];
-        acc_cols<QB, kRowBatch>(S.cols, q, 0, S.dy, n, i0, j0, b);
+        acc_cols<QB, kRowBatch>(G.zy, n, q, G.dz, D, boff, b);
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u) {
-            const int j = j0 + u * kBlock;
+            const int j = j0 + u * kBT;
             if (j >= n) continue;
 #pragma unroll
             for (int r = 0; r < QB; ++r)
-                if (r < nq && abs(j - (i0 + r)) > S.theiler) f(r, j, a[r][u], b[r][u]);
+                if (r < nq && (uint32_t)(j + (G.w - i0 - r)) > w2) f(r, j, a[r][u], b[r][u]);
         }
     }
 }
 
 template <int QB, int C, bool PACK>
-__global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__restrict__ sets, int n_sets,
+__global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restrict__ sets, int n_sets,
                                                            const int64_t *__restrict__ blk_off) {
     using Sm = BuildSmem<QB, C, PACK>;
     __shared__ Sm sm;
@@ -227,19 +270,20 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
     const int copy = tid & (C - 1);
     const int64_t b = bid_x();
     if (tid == 0) sm.set = find_job(blk_off, n_sets, b);
-    for (int x = tid; x < QB * C * Sm::kCopy; x += kBlock) (&sm.h[0][0][0])[x] = 0u;
+    for (int x = tid; x < QB * C * Sm::kCopy; x += kBT) (&sm.h[0][0][0])[x] = 0u;
     __syncthreads();
     const ListSet &S = sets[sm.set];
-    const int n = S.n;
+    const BuildGeo G{S.zy, S.n, S.dy, S.dz, S.theiler};
+    const int n = G.n;
     const int i0 = (int)(b - blk_off[sm.set]) * QB;
     const int nq = min(QB, n - i0);
-    for (int x = tid; x < QB * (S.dy + S.dz); x += kBlock) {
-        const int r = x / (S.dy + S.dz), c = x - r * (S.dy + S.dz);
-        sm.q[r][c] = S.cols[c][min(i0 + r, n - 1)];
+    for (int x = tid; x < QB * (G.dy + G.dz); x += kBT) {
+        const int r = x / (G.dy + G.dz), c = x - r * (G.dy + G.dz);
+        sm.q[r][c] = G.zy[(size_t)c * n + min(i0 + r, n - 1)];
     }
     __syncthreads();
 
-    for_each_pair<QB>(S, sm.q, i0, nq, tid, [&](int r, int, float a, float c) {
+    for_each_pair<QB>(G, sm.q, i0, nq, tid, [&](int r, int, float a, float c) {
         atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, key_of(c)), bin_inc<PACK>(0));
         atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, key_of(a)), bin_inc<PACK>(1));
     });
@@ -248,7 +292,6 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
     // per row and list: keep the largest bucket prefix with at most m entries
     // (bucket keys below kept_bins are listed: the prefix is contiguous
     // because the cumulative counts grow with the key)
-    constexpr int kPer = kKeyBins / kBlock;
 #pragma unroll
     for (int r = 0; r < QB; ++r) {
 #pragma unroll
@@ -283,29 +326,41 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
             __syncthreads();
             if (tid == 0) {
                 uint32_t kb = 0, kr = 0;
-                for (int v = 0; v < kWaves; ++v) { kb += sm.red[0][v]; kr += sm.red[1][v]; }
+                for (int v = 0; v < kBW; ++v) { kb += sm.red[0][v]; kr += sm.red[1][v]; }
                 sm.kept_bins[r][w] = kb;
                 sm.kept_rows[r][w] = kr;
             }
             __syncthreads();
         }
     }
-    for_each_pair<QB>(S, sm.q, i0, nq, tid, [&](int r, int j, float a, float c) {
-        const int64_t i = i0 + r;
+    // pass 2 with the kept prefixes and the rows' list bases in registers
+    uint32_t keep[QB][2];
+    LEnt *out1[QB];
+    LEnt2 *out2[QB];
+#pragma unroll
+    for (int r = 0; r < QB; ++r) {
+        keep[r][0] = sm.kept_bins[r][0];
+        keep[r][1] = sm.kept_bins[r][1];
+        const int64_t i = min(i0 + r, n - 1);
+        out1[r] = S.l1 + i * S.s1;
+        out2[r] = S.l2 + i * S.s2;
+    }
+    const uint32_t m1 = (uint32_t)S.m1, m2 = (uint32_t)S.m2;
+    for_each_pair<QB>(G, sm.q, i0, nq, tid, [&](int r, int j, float a, float c) {
         const uint32_t k1 = key_of(c), k2 = key_of(a);
-        if (k1 < sm.kept_bins[r][0]) {
+        if (k1 < keep[r][0]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1), bin_inc<PACK>(0)), 0);
-            if (pos < (uint32_t)S.m1) S.l1[i * S.s1 + pos] = LEnt{c, j};
+            if (pos < m1) out1[r][pos] = LEnt{c, j};
         }
-        if (k2 < sm.kept_bins[r][1]) {
+        if (k2 < keep[r][1]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1)), 1);
-            if (pos < (uint32_t)S.m2) S.l2[i * S.s2 + pos] = LEnt2{a, c, j};
+            if (pos < m2) out2[r][pos] = LEnt2{a, c, j};
         }
     });
     // lengths, bounds and the sentinels after each list
-    for (int x = tid; x < QB * 2 * kListPad; x += kBlock) {
+    for (int x = tid; x < QB * 2 * kListPad; x += kBT) {
         const int r = x / (2 * kListPad), w = (x / kListPad) & 1, u = x % kListPad;
         if (r >= nq) continue;
         const int64_t i = i0 + r;
@@ -321,6 +376,21 @@ __global__ __launch_bounds__(kBlock) void list_build_kernel(const ListSet *__res
             S.bound[2 * i + w] = bound;
         }
     }
+}
+
+// ------------------------------------------------------------------ columns
+// One thread per (set, row): the row's Z then Y coordinates into the set's
+// contiguous column copy, so that the build addresses every column from one
+// base pointer.
+__global__ __launch_bounds__(kBlock) void list_zy_kernel(const ListLaunch L) {
+    const int64_t g = bid_x() * kBlock + tid_x();
+    if (g >= L.rows) return;
+    const int t = find_job(L.row_off, L.n_sets, g);
+    const ListSet &S = L.sets[t];
+    const int64_t j = g - L.row_off[t], n = S.n;
+    const int dy = S.dy, dz = S.dz;
+    for (int c = 0; c < dz; ++c) S.zy[c * n + j] = S.cols[dy + c][j];
+    for (int c = 0; c < dy; ++c) S.zy[(dz + c) * n + j] = S.cols[c][j];
 }
 
 // ------------------------------------------------------------------ X sort
@@ -368,12 +438,6 @@ __global__ __launch_bounds__(kSortThreads) void list_sortx_kernel(const ListLaun
 // bound, i.e. an undecided pair, as it should.
 constexpr int kU = 8;   // list entries per step; the next step's are loaded ahead
 
-// Load through a global-address-space pointer: a generic (flat) load would
-// count against both the vector-memory and the LDS counters, and the wait for
-// the gathers would then also wait for the next step's entries loaded ahead.
-__device__ __forceinline__ float gload(const float *p, uint32_t off) {
-    return ((const __attribute__((address_space(1))) float *)p)[off];
-}
 static_assert(kU <= kListPad, "a step must stay within the sentinels");
 
 template <int KMAX, int DXM>
@@ -701,10 +765,13 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
             const uint32_t pos = atomicAdd(&L.counters[0], 1u);
             L.failq[pos] = ((uint64_t)jb << 40) | (uint64_t)r;
         } else {
-            J.eps[(int64_t)e * n + i] = eps;
-            J.cnt[((int64_t)e * 3 + 0) * n + i] = cxz;
-            J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
-            J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
+            J.pk[(int64_t)e * n + i] = pack_counts(cxz, cyz, cz);
+            if (J.eps) J.eps[(int64_t)e * n + i] = eps;
+            if (J.cnt) {
+                J.cnt[((int64_t)e * 3 + 0) * n + i] = cxz;
+                J.cnt[((int64_t)e * 3 + 1) * n + i] = cyz;
+                J.cnt[((int64_t)e * 3 + 2) * n + i] = cz;
+            }
         }
         if (L.stats) {
             const int slot = (int)((g >> 6) & (kListStatSlots - 1));
@@ -828,8 +895,10 @@ __device__ __forceinline__ void fb_store(const FbPair &p, float eps, int (&c3)[3
     const Job &J = *p.J;
     const int n = p.n, i = p.i, e = p.e;
     if (p.dz == 0) c3[2] = n - 1 - min(i, J.theiler) - min(n - 1 - i, J.theiler);
-    J.eps[(int64_t)e * n + i] = eps;
-    for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
+    J.pk[(int64_t)e * n + i] = pack_counts(c3[0], c3[1], c3[2]);
+    if (J.eps) J.eps[(int64_t)e * n + i] = eps;
+    if (J.cnt)
+        for (int t = 0; t < 3; ++t) J.cnt[((int64_t)e * 3 + t) * n + i] = c3[t];
 }
 
 // k pops of the wave-wide minimum of the threads' sorted lists; the last
@@ -929,9 +998,7 @@ __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L,
     const int e = (int)(g - L.est_off[jb]);
     const int n = J.n, tid = tid_x(), lane = tid & 63;
     const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
-    const int32_t *cx = J.cnt + ((int64_t)e * 3 + 0) * n;
-    const int32_t *cy = J.cnt + ((int64_t)e * 3 + 1) * n;
-    const int32_t *cz = J.cnt + ((int64_t)e * 3 + 2) * n;
+    const uint64_t *pk = J.pk + (int64_t)e * n;
     const int nch = (n + kChunk - 1) / kChunk;
     constexpr int kRound = kWaves * kRedChunks;
     if (tid == 0) s_acc = 0.0;
@@ -940,7 +1007,12 @@ __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L,
 #pragma unroll
         for (int u = 0; u < kRedChunks; ++u) {
             const int i = (c0 + wave * kRedChunks + u) * kChunk + lane;
-            v[u] = i < n ? (harm[cx[i]] + harm[cy[i]]) - harm[cz[i]] : 0.0;
+            if (i < n) {
+                const uint64_t c = pk[i];
+                v[u] = (harm[c & kPackMask] + harm[(c >> kPackBits) & kPackMask]) - harm[c >> (2 * kPackBits)];
+            } else {
+                v[u] = 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kRedChunks; ++u)
@@ -970,7 +1042,9 @@ void *scan_fn() {
 
 int launch_list_build(const ListLaunch &L, void *stream) {
     if (L.build_blocks <= 0) return 0;
-    const dim3 grid((unsigned)L.build_blocks), block(kBlock);
+    hipLaunchKernelGGL(list_zy_kernel, dim3((unsigned)((L.rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, L);
+    const dim3 grid((unsigned)L.build_blocks), block(kBT);
     if (L.build_pack && L.build_qb == kBuildRows)
         hipLaunchKernelGGL((list_build_kernel<kBuildRows, kBuildCopies, true>), grid, block, 0,
                            (hipStream_t)stream, L.sets, L.n_sets, L.build_off);

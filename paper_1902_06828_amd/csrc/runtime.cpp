@@ -138,6 +138,7 @@ static int init_locked(int device, size_t budget) {
     MTE_HIP(hipMemGetInfo(&fr, &tot));
     c.budget = budget ? budget : (size_t)(0.9 * (double)fr);
     MTE_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+    MTE_HIP(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
     c.inited = true;
     return MTE_OK;
 }
@@ -200,6 +201,8 @@ int shutdown_all() {
     c.alloc.trim();
     if (c.capture_stream) (void)hipStreamDestroy(c.capture_stream);
     c.capture_stream = nullptr;
+    if (c.side_stream) (void)hipStreamDestroy(c.side_stream);
+    c.side_stream = nullptr;
     c.tuned.clear();
     c.inited = false;
     c.device = -1;
@@ -300,10 +303,13 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
     std::vector<int> gid(specs.size(), -1);
     for (size_t j = 0; j < specs.size(); ++j) {
         const JobSpec &sp = specs[j];
-        // the list kernels index the transposed X columns with 32-bit offsets;
+        // the list kernels index the transposed X columns with 32-bit
+        // element offsets and a column of the build's copy of Y and Z with
+        // 32-bit byte offsets, and pack a row's counts kPackBits to a field;
         // without Z the list path needs one X column (its range counts use
         // the sorted column) and N within the in-LDS sort
         if (force == 0 || (int64_t)sp.dx * sp.n * sp.n_est() >= ((int64_t)1 << 31)) continue;
+        if (sp.n > kListMaxN) continue;
         if (sp.dz == 0 && (sp.dx != 1 || sp.n > kNoZSortMax)) continue;
         std::vector<uintptr_t> key{(uintptr_t)sp.n, (uintptr_t)sp.dy, (uintptr_t)sp.dz, (uintptr_t)sp.theiler};
         for (int c = 0; c < sp.dy + sp.dz; ++c) key.push_back((uintptr_t)sp.cols[sp.dx + c]);
@@ -476,6 +482,8 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 Batch::~Batch() {
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
+    if (fork_) (void)hipEventDestroy(fork_);
+    if (join_) (void)hipEventDestroy(join_);
 }
 
 size_t Batch::device_bytes() const {
@@ -590,7 +598,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     // scratch layout: per set its lists, per job xt, eps, cnt; then the queue
     size_t bytes = 0;
     int nmax_set = 0;
-    std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets);
+    std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets), o_zy(n_sets);
     std::vector<int> set_dx(n_sets, 0);
     for (int j = 0; j < n_ljobs_; ++j) set_dx[set_of[j]] = std::max(set_dx[set_of[j]], specs[j].dx);
     for (int t = 0; t < n_sets; ++t) {
@@ -620,8 +628,10 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         bytes = align_up(bytes + sizeof(int32_t) * 2 * (size_t)sp.n, 256);
         o_bound[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * 2 * (size_t)sp.n, 256);
+        o_zy[t] = bytes;
+        bytes = align_up(bytes + sizeof(float) * (size_t)(sp.dy + sp.dz) * sp.n, 256);
     }
-    struct Off { size_t xt, eps, cnt, xs; };
+    struct Off { size_t xt, pk, xs; };
     std::vector<Off> offs(n_ljobs_);
     for (int j = 0; j < n_ljobs_; ++j) {
         const JobSpec &sp = specs[j];
@@ -630,14 +640,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
         offs[j].xs = bytes;
         if (sp.dz == 0) bytes = align_up(bytes + sizeof(float) * (size_t)sp.n, 256);
-        if (!sp.diag_eps) {
-            offs[j].eps = bytes;
-            bytes = align_up(bytes + sizeof(float) * pairs, 256);
-        }
-        if (!sp.diag_cnt) {
-            offs[j].cnt = bytes;
-            bytes = align_up(bytes + sizeof(int32_t) * 3 * pairs, 256);
-        }
+        offs[j].pk = bytes;
+        bytes = align_up(bytes + sizeof(uint64_t) * pairs, 256);
     }
     const size_t o_failq = bytes;
     bytes = align_up(bytes + sizeof(uint64_t) * (size_t)lane_off[n_ljobs_], 256);
@@ -651,6 +655,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.l2 = reinterpret_cast<LEnt2 *>(sb + o_l2[t]);
         S.len = reinterpret_cast<int32_t *>(sb + o_len[t]);
         S.bound = reinterpret_cast<float *>(sb + o_bound[t]);
+        S.zy = reinterpret_cast<float *>(sb + o_zy[t]);
     }
     // tables: jobs, sets, keys, offsets
     const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
@@ -685,8 +690,9 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.rep_shuffle = sp.rep_shuffle;
         J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
         J.xs = sp.dz == 0 ? reinterpret_cast<float *>(sb + offs[j].xs) : nullptr;
-        J.eps = sp.diag_eps ? sp.diag_eps : reinterpret_cast<float *>(sb + offs[j].eps);
-        J.cnt = sp.diag_cnt ? sp.diag_cnt : reinterpret_cast<int32_t *>(sb + offs[j].cnt);
+        J.eps = sp.diag_eps;
+        J.cnt = sp.diag_cnt;
+        J.pk = reinterpret_cast<uint64_t *>(sb + offs[j].pk);
         J.out = sp.out;
         J.keys = keys_dev + kpos;
         std::memcpy(keys_host + kpos, sp.keys.data(), sizeof(EstKey) * J.n_est);
@@ -870,55 +876,64 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
 }
 
 // Launch sequence: the all-pairs part (reset, permute, main kernel), then
-// the list part (reset, permute into xt, build, scan, fallback, reduce).
+// the list part (reset; permute into xt on the side stream beside the build
+// and the X sort, which read only the unpermuted columns; joined before the
+// scan; then scan, fallback, reduce).
 int Batch::launch_all(hipStream_t s, bool timed) {
     hipEvent_t ev[2] = {nullptr, nullptr};
-    auto begin = [&]() -> int {
+    auto begin = [&](hipStream_t st) -> int {
         if (!timed) return MTE_OK;
         MTE_HIP(hipEventCreate(&ev[0]));
         MTE_HIP(hipEventCreate(&ev[1]));
-        MTE_HIP(hipEventRecord(ev[0], s));
+        MTE_HIP(hipEventRecord(ev[0], st));
         return MTE_OK;
     };
-    auto end = [&](int stage) -> int {
+    auto end = [&](int stage, hipStream_t st) -> int {
         if (!timed) return MTE_OK;
-        MTE_HIP(hipEventRecord(ev[1], s));
+        MTE_HIP(hipEventRecord(ev[1], st));
         record_timing_pair(stage, ev[0], ev[1]);
         return MTE_OK;
     };
     int rc;
     if (n_jobs_ > 0) {
         if (launch_reset(sync_.as<uint32_t>(), sync_total_, s)) return hip_fail(hipGetLastError(), "reset launch");
-        if ((rc = begin())) return rc;
+        if ((rc = begin(s))) return rc;
         if (launch_permute(jobs_dev_, n_jobs_, permute_blocks_, blk_off_, s))
             return hip_fail(hipGetLastError(), "permute launch");
-        if ((rc = end(kStagePermute))) return rc;
-        if ((rc = begin())) return rc;
+        if ((rc = end(kStagePermute, s))) return rc;
+        if ((rc = begin(s))) return rc;
         if (launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), s))
             return hip_fail(hipGetLastError(), "main kernel launch");
-        if ((rc = end(kStageAllPairs))) return rc;
+        if ((rc = end(kStageAllPairs, s))) return rc;
     }
     if (n_ljobs_ > 0) {
+        const hipStream_t side = ctx().side_stream;
+        if (!fork_) MTE_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+        if (!join_) MTE_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
         if (launch_reset(lcounters_.as<uint32_t>(), kListCounterWords, s))
             return hip_fail(hipGetLastError(), "reset launch");
-        if ((rc = begin())) return rc;
-        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, s))
+        MTE_HIP(hipEventRecord(fork_, s));
+        MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
+        if ((rc = begin(side))) return rc;
+        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side))
             return hip_fail(hipGetLastError(), "permute launch");
-        if ((rc = end(kStagePermute))) return rc;
+        if ((rc = end(kStagePermute, side))) return rc;
+        MTE_HIP(hipEventRecord(join_, side));
         ll_.stats = ctx().list_stats ? 1 : 0;
-        if ((rc = begin())) return rc;
+        if ((rc = begin(s))) return rc;
         if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
         if (ll_.sortx && launch_list_sortx(ll_, s)) return hip_fail(hipGetLastError(), "X sort launch");
-        if ((rc = end(kStageBuild))) return rc;
-        if ((rc = begin())) return rc;
+        if ((rc = end(kStageBuild, s))) return rc;
+        MTE_HIP(hipStreamWaitEvent(s, join_, 0));
+        if ((rc = begin(s))) return rc;
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
-        if ((rc = end(kStageScan))) return rc;
-        if ((rc = begin())) return rc;
+        if ((rc = end(kStageScan, s))) return rc;
+        if ((rc = begin(s))) return rc;
         if (launch_list_fallback(ll_, s)) return hip_fail(hipGetLastError(), "list fallback launch");
-        if ((rc = end(kStageFallback))) return rc;
-        if ((rc = begin())) return rc;
+        if ((rc = end(kStageFallback, s))) return rc;
+        if ((rc = begin(s))) return rc;
         if (launch_list_reduce(ll_, harm_table(), s)) return hip_fail(hipGetLastError(), "list reduce launch");
-        if ((rc = end(kStageReduce))) return rc;
+        if ((rc = end(kStageReduce, s))) return rc;
     }
     return MTE_OK;
 }

@@ -144,6 +144,8 @@ private:
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
     bool graph_failed_ = false;
+    // fork/join of the list part's permutation onto the side stream
+    hipEvent_t fork_ = nullptr, join_ = nullptr;
 };
 
 // ---------------------------------------------------------------- context
@@ -154,6 +156,7 @@ struct Ctx {
     int n_cu = 0;
     size_t budget = 0;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;   // work that runs beside a launch's main stream
     DeviceAllocator alloc;
     // harmonic numbers H[0..harm_n]; old tables stay alive until shutdown
     double *harm = nullptr;
