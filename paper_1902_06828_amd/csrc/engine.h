@@ -183,12 +183,16 @@ int kernel_variant_count();
 bool kernel_variant(int i, TileCfg *cfg);
 int variant_blocks_per_cu(int variant);
 int launch_reset(uint32_t *words, int64_t n_words, void *stream);
-int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_rows, const int64_t *row_off,
-                   void *stream);
+// Permuted X columns: total_blocks work items (blk_off: [n_jobs+1] prefix
+// sums of each job's items), on a grid of at most max_grid blocks (0: one
+// block per item) that take the items in turn.
+int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_blocks, const int64_t *blk_off,
+                   void *stream, int64_t max_grid = 0);
 int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_off_dev,
                 const int64_t *b_off_dev, const LaunchInfo &li, uint32_t *work,
                 const double *harm, void *stream);
 
+int launch_list_zy(const ListLaunch &L, void *stream);      // the sets' contiguous Y,Z copies
 int launch_list_build(const ListLaunch &L, void *stream);
 int launch_list_sortx(const ListLaunch &L, void *stream);
 int launch_list_scan(const ListLaunch &L, void *stream);

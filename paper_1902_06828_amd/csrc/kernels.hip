@@ -54,12 +54,13 @@ __device__ __forceinline__ uint32_t swap_or_not(uint32_t x, uint32_t n, int roun
 }
 
 __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
-                                                     const int64_t *__restrict__ blk_off) {
+                                                     const int64_t *__restrict__ blk_off, int64_t total) {
     __shared__ uint64_t s_rk[192];
     __shared__ uint32_t s_k[192];
     __shared__ int s_job;
     __shared__ uint32_t s_src_rep;
-    const int64_t b = blockIdx.x;
+    // a grid smaller than the work takes the blocks' items in turn
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
     if (threadIdx.x == 0) {
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
@@ -113,6 +114,8 @@ __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jo
             for (int c = 0; c < J.dx; ++c)
                 J.xp[((int64_t)e * J.dx + c) * J.n + i] = J.cols[c][x];
         }
+    }
+    __syncthreads();   // the next item rewrites the key schedule
     }
 }
 
@@ -175,10 +178,11 @@ int launch_reset(uint32_t *words, int64_t n_words, void *stream) {
 }
 
 int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_blocks, const int64_t *blk_off,
-                   void *stream) {
+                   void *stream, int64_t max_grid) {
     if (total_blocks <= 0) return 0;
-    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)total_blocks), dim3(256), 0, (hipStream_t)stream,
-                       jobs_dev, n_jobs, blk_off);
+    const int64_t grid = max_grid > 0 && max_grid < total_blocks ? max_grid : total_blocks;
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, jobs_dev,
+                       n_jobs, blk_off, total_blocks);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -284,8 +284,17 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
     __syncthreads();
 
     for_each_pair<QB>(G, sm.q, i0, nq, tid, [&](int r, int, float a, float c) {
-        atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, key_of(c)), bin_inc<PACK>(0));
-        atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, key_of(a)), bin_inc<PACK>(1));
+        const uint32_t k1 = key_of(c), k2 = key_of(a);
+        if (PACK) {
+            // d_yz and d_z often share a bucket (when d_y <= d_z): one atomic
+            // then counts both lists
+            atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1),
+                      k1 == k2 ? bin_inc<PACK>(0) + bin_inc<PACK>(1) : bin_inc<PACK>(0));
+            if (k1 != k2) atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1));
+        } else {
+            atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1), bin_inc<PACK>(0));
+            atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1));
+        }
     });
     __syncthreads();
 
@@ -792,7 +801,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
 // C2) take a whole 1024-thread block each, which keeps the latency of a pair
 // short; many pairs (lists short for the data) take one wave each, with no
 // block synchronisation, for throughput.
-constexpr int kFbBatch = 4;
+constexpr int kFbBatch = 12;
 constexpr int kFbThreads = 1024;
 constexpr int kFbWaves = kFbThreads / 64;
 constexpr uint32_t kFbBlockModeMax = 2048;   // queue length up to which a pair gets a block
@@ -1040,10 +1049,15 @@ void *scan_fn() {
 
 }  // namespace
 
-int launch_list_build(const ListLaunch &L, void *stream) {
-    if (L.build_blocks <= 0) return 0;
+int launch_list_zy(const ListLaunch &L, void *stream) {
+    if (L.rows <= 0) return 0;
     hipLaunchKernelGGL(list_zy_kernel, dim3((unsigned)((L.rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        (hipStream_t)stream, L);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_build(const ListLaunch &L, void *stream) {
+    if (L.build_blocks <= 0) return 0;
     const dim3 grid((unsigned)L.build_blocks), block(kBT);
     if (L.build_pack && L.build_qb == kBuildRows)
         hipLaunchKernelGGL((list_build_kernel<kBuildRows, kBuildCopies, true>), grid, block, 0,

@@ -875,10 +875,15 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
     return MTE_OK;
 }
 
+// Blocks per CU of the permutation that runs beside the build: a few, so
+// that the build keeps nearly all its waves and the permutation's ALU work
+// fills the build's waits on LDS and L2.
+constexpr int kPermuteBlocksPerCu = 2;
+
 // Launch sequence: the all-pairs part (reset, permute, main kernel), then
-// the list part (reset; permute into xt on the side stream beside the build
-// and the X sort, which read only the unpermuted columns; joined before the
-// scan; then scan, fallback, reduce).
+// the list part (reset, Y,Z copy; permute into xt on the side stream beside
+// the build and the X sort, which read only the unpermuted columns; joined
+// before the scan; then scan, fallback, reduce).
 int Batch::launch_all(hipStream_t s, bool timed) {
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto begin = [&](hipStream_t st) -> int {
@@ -912,10 +917,12 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (!join_) MTE_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
         if (launch_reset(lcounters_.as<uint32_t>(), kListCounterWords, s))
             return hip_fail(hipGetLastError(), "reset launch");
+        if (launch_list_zy(ll_, s)) return hip_fail(hipGetLastError(), "Y,Z copy launch");
         MTE_HIP(hipEventRecord(fork_, s));
         MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
         if ((rc = begin(side))) return rc;
-        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side))
+        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side,
+                           (int64_t)kPermuteBlocksPerCu * ctx().n_cu))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute, side))) return rc;
         MTE_HIP(hipEventRecord(join_, side));
