@@ -178,6 +178,33 @@ def test_device_api_and_graph_replay():
         mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, S, seed, cand, out)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), ref), rep
+    # direct launches with per-stage events (the timing path) on the same shape
+    say("device call with kernel timing")
+    mte.mte_kernel_timing(True)
+    try:
+        out.zero_()
+        mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, S, seed, cand, out)
+        torch.cuda.synchronize()
+    finally:
+        mte.mte_kernel_timing(False)
+        for st in mte._lib.STAGES:
+            mte.mte_kernel_timing_stage(st, reset=True)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    # inputs changed in place reach the next replay: every launch rebuilds the
+    # permuted X and the build's copy of Y and Z
+    X2, _, Z2 = synth.random_points(2500, (1, 1, 5), seed=45)
+    dX.copy_(torch.from_numpy(X2))
+    dZ.copy_(torch.from_numpy(Z2))
+    ref3 = mte.cmi_ksg_diag(X2, Y, Z2, 4, S, seed, cand)[0]
+    assert abs(ref3[0] - cksg.cmi_ksg(X2, Y, Z2, 4)) <= TOL
+    for rep in range(2):
+        say("device call after an in-place update", rep)
+        out.zero_()
+        mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, S, seed, cand, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref3), rep
+    dX.copy_(torch.from_numpy(X))
+    dZ.copy_(torch.from_numpy(Z))
     one = torch.zeros(1, dtype=torch.float64, device=dev)
     mte.cmi_ksg_dev(dX, dY, dZ, 4, one)
     torch.cuda.synchronize()
