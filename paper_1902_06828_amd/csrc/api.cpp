@@ -403,10 +403,12 @@ int mte_kernel_timing_stage(int stage, int64_t *launches_out, double *total_ms_o
         MTE_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
         add[pe.stage] += ms;
         cnt[pe.stage] += 1;
-        (void)hipEventDestroy(pe.a);
-        (void)hipEventDestroy(pe.b);
     }
     std::lock_guard<std::mutex> lk(c.mu);
+    for (auto &pe : ev) {
+        c.event_pool.push_back(pe.a);
+        c.event_pool.push_back(pe.b);
+    }
     for (int t = 0; t < kStages; ++t) {
         c.timed_ms[t] += add[t];
         c.timed_launches[t] += cnt[t];

@@ -149,6 +149,7 @@ struct ListLaunch {
                                   // per launch
     int kmax, dxm;                // compile-time classes of the scan kernel
     int fb_grid;                  // blocks of the fallback kernel
+    int max_chunks;               // largest ceil(n / kChunk) of the jobs (reduction grid)
     int sortx;                    // some job has no Z: sort the X columns (Job::xs)
 };
 

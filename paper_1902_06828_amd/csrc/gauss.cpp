@@ -16,8 +16,8 @@ static int timed_launch(int stage, hipStream_t s, F launch) {
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = ctx().timing;
     if (timed) {
-        MTE_HIP(hipEventCreate(&ev[0]));
-        MTE_HIP(hipEventCreate(&ev[1]));
+        int rc;
+        if ((rc = timing_event(&ev[0])) || (rc = timing_event(&ev[1]))) return rc;
         MTE_HIP(hipEventRecord(ev[0], s));
     }
     if (launch()) return hip_fail(hipGetLastError(), "Gaussian estimator launch");

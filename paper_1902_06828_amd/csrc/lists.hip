@@ -993,53 +993,54 @@ __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLau
 }
 
 // ------------------------------------------------------------------ reduce
-// One block per (job, estimate): (H[n_xz] + H[n_yz]) - H[n_z] per row, 64-row
-// butterfly sums (the four waves take 16 chunks each per round), then the
-// chunk sums added in index order: the all-pairs kernel's order.
-constexpr int kRedChunks = 16;
-
-__global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L, const double *__restrict__ harm) {
-    __shared__ double part[kWaves * kRedChunks];
-    __shared__ double s_acc;
+// (H[n_xz] + H[n_yz]) - H[n_z] per row, summed in the all-pairs kernel's order
+// so that both paths return the same bits: a 64-row butterfly per chunk, then
+// the chunk sums added in index order.  Phase 1: one wave per (estimate,
+// chunk), blocks of kWaves chunks of one estimate; phase 2: one thread per
+// estimate adds its chunk sums.
+__global__ __launch_bounds__(kBlock) void list_chunk_kernel(const ListLaunch L, const double *__restrict__ harm) {
     const int64_t g = bid_x();
     const int jb = find_job(L.est_off, L.n_jobs, g);
     const Job &J = L.jobs[jb];
     const int e = (int)(g - L.est_off[jb]);
-    const int n = J.n, tid = tid_x(), lane = tid & 63;
-    const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
-    const uint64_t *pk = J.pk + (int64_t)e * n;
+    const int n = J.n, lane = tid_x() & 63;
+    const int wave = (int)__builtin_amdgcn_readfirstlane((uint32_t)tid_x() >> 6);
+    const int c = (int)__builtin_amdgcn_workgroup_id_y() * kWaves + wave;
     const int nch = (n + kChunk - 1) / kChunk;
-    constexpr int kRound = kWaves * kRedChunks;
-    if (tid == 0) s_acc = 0.0;
-    for (int c0 = 0; c0 < nch; c0 += kRound) {
-        double v[kRedChunks];
-#pragma unroll
-        for (int u = 0; u < kRedChunks; ++u) {
-            const int i = (c0 + wave * kRedChunks + u) * kChunk + lane;
-            if (i < n) {
-                const uint64_t c = pk[i];
-                v[u] = (harm[c & kPackMask] + harm[(c >> kPackBits) & kPackMask]) - harm[c >> (2 * kPackBits)];
-            } else {
-                v[u] = 0.0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kRedChunks; ++u)
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v[u] = v[u] + __shfl_xor(v[u], off, 64);
-        if (lane == 0)
-#pragma unroll
-            for (int u = 0; u < kRedChunks; ++u) part[wave * kRedChunks + u] = v[u];
-        __syncthreads();
-        if (tid == 0) {
-            double acc = s_acc;
-            const int m = min(kRound, nch - c0);
-            for (int c = 0; c < m; ++c) acc += part[c];
-            s_acc = acc;
-        }
-        __syncthreads();
+    if (c >= nch) return;
+    const int i = c * kChunk + lane;
+    double v = 0.0;
+    if (i < n) {
+        const uint64_t w = J.pk[(int64_t)e * n + i];
+        v = (harm[w & kPackMask] + harm[(w >> kPackBits) & kPackMask]) - harm[w >> (2 * kPackBits)];
     }
-    if (tid == 0) J.out[e] = harm[J.k - 1] - s_acc / (double)n;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    if (lane == 0) J.chunk[(int64_t)e * nch + c] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L, const double *__restrict__ harm) {
+    const int64_t g = bid_x() * kBlock + tid_x();
+    if (g >= L.ests) return;
+    const int jb = find_job(L.est_off, L.n_jobs, g);
+    const Job &J = L.jobs[jb];
+    const int e = (int)(g - L.est_off[jb]);
+    const int n = J.n;
+    const int nch = (n + kChunk - 1) / kChunk;
+    const double *part = J.chunk + (int64_t)e * nch;
+    // in index order; the loads of 16 chunk sums are issued before their adds
+    constexpr int kU = 16;
+    double acc = 0.0;
+    int c = 0;
+    for (; c + kU <= nch; c += kU) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = part[c + u];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc += v[u];
+    }
+    for (; c < nch; ++c) acc += part[c];
+    J.out[e] = harm[J.k - 1] - acc / (double)n;
 }
 
 template <int KMAX, int DXM>
@@ -1103,8 +1104,11 @@ int launch_list_sortx(const ListLaunch &L, void *stream) {
 }
 
 int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream) {
-    if (L.ests <= 0) return 0;
-    hipLaunchKernelGGL(list_reduce_kernel, dim3((unsigned)L.ests), dim3(kBlock), 0, (hipStream_t)stream, L, harm);
+    if (L.ests <= 0 || L.max_chunks <= 0) return 0;
+    const dim3 grid1((unsigned)L.ests, (unsigned)((L.max_chunks + kWaves - 1) / kWaves));
+    hipLaunchKernelGGL(list_chunk_kernel, grid1, dim3(kBlock), 0, (hipStream_t)stream, L, harm);
+    hipLaunchKernelGGL(list_reduce_kernel, dim3((unsigned)((L.ests + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, L, harm);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -193,6 +193,8 @@ int shutdown_all() {
         (void)hipEventDestroy(pe.b);
     }
     c.pending_events.clear();
+    for (hipEvent_t e : c.event_pool) (void)hipEventDestroy(e);
+    c.event_pool.clear();
     if (c.harm) (void)hipFree(c.harm);
     for (double *p : c.retired) (void)hipFree(p);
     c.retired.clear();
@@ -279,6 +281,20 @@ void standardise_host(const float *in, int R, int P, int64_t T, float *out) {
                 out[x] = sd > 0.0 ? (float)(((double)in[x] - mean) / sd) : 0.0f;
             }
     }
+}
+
+int timing_event(hipEvent_t *e) {
+    Ctx &c = ctx();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (!c.event_pool.empty()) {
+            *e = c.event_pool.back();
+            c.event_pool.pop_back();
+            return MTE_OK;
+        }
+    }
+    MTE_HIP(hipEventCreate(e));
+    return MTE_OK;
 }
 
 void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b) {
@@ -631,7 +647,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         o_zy[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * (size_t)(sp.dy + sp.dz) * sp.n, 256);
     }
-    struct Off { size_t xt, pk, xs; };
+    struct Off { size_t xt, pk, xs, chunk; };
     std::vector<Off> offs(n_ljobs_);
     for (int j = 0; j < n_ljobs_; ++j) {
         const JobSpec &sp = specs[j];
@@ -642,6 +658,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         if (sp.dz == 0) bytes = align_up(bytes + sizeof(float) * (size_t)sp.n, 256);
         offs[j].pk = bytes;
         bytes = align_up(bytes + sizeof(uint64_t) * pairs, 256);
+        offs[j].chunk = bytes;
+        bytes = align_up(bytes + sizeof(double) * (size_t)sp.n_est() * ((sp.n + kChunk - 1) / kChunk), 256);
     }
     const size_t o_failq = bytes;
     bytes = align_up(bytes + sizeof(uint64_t) * (size_t)lane_off[n_ljobs_], 256);
@@ -693,6 +711,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.eps = sp.diag_eps;
         J.cnt = sp.diag_cnt;
         J.pk = reinterpret_cast<uint64_t *>(sb + offs[j].pk);
+        J.chunk = reinterpret_cast<double *>(sb + offs[j].chunk);
         J.out = sp.out;
         J.keys = keys_dev + kpos;
         std::memcpy(keys_host + kpos, sp.keys.data(), sizeof(EstKey) * J.n_est);
@@ -732,6 +751,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.kmax = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
     L.dxm = dxm <= 1 ? 1 : kMaxDx;
     L.fb_grid = std::max(1, 2 * c.n_cu);
+    L.max_chunks = 0;
+    for (const JobSpec &sp : specs) L.max_chunks = std::max(L.max_chunks, (sp.n + kChunk - 1) / kChunk);
     L.sortx = 0;
     for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
     if (L.lanes >= ((int64_t)1 << 40) || n_ljobs_ >= (1 << 23)) return fail(MTE_EINVAL, "batch too large");
@@ -888,8 +909,8 @@ int Batch::launch_all(hipStream_t s, bool timed) {
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto begin = [&](hipStream_t st) -> int {
         if (!timed) return MTE_OK;
-        MTE_HIP(hipEventCreate(&ev[0]));
-        MTE_HIP(hipEventCreate(&ev[1]));
+        int rc;
+        if ((rc = timing_event(&ev[0])) || (rc = timing_event(&ev[1]))) return rc;
         MTE_HIP(hipEventRecord(ev[0], st));
         return MTE_OK;
     };

@@ -168,6 +168,7 @@ struct Ctx {
     bool timing = false;
     struct Pending { int stage; hipEvent_t a, b; };
     std::vector<Pending> pending_events;
+    std::vector<hipEvent_t> event_pool;   // read timing events, for reuse
     int64_t timed_launches[kStages] = {};
     double timed_ms[kStages] = {};
     // list path statistics (from checked launches)
@@ -177,6 +178,8 @@ struct Ctx {
 };
 
 Ctx &ctx();
+// A timing event: from the pool of read ones, else a new one.
+int timing_event(hipEvent_t *e);
 int ensure_init();                     // lazily initialises device 0
 int ensure_harm(int64_t n);            // H table covers 0..n
 const double *harm_table();
