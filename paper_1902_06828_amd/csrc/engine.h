@@ -49,7 +49,8 @@ struct Job {
     int64_t a_off, b_off;         // first item index in phase A and phase B
     const EstKey *keys;           // [n_est]
     float *xp;                    // [n_est][dx][n] permuted X (scratch)
-    double *chunk;                // [n_est][ceil(n/64)] partial sums (scratch)
+    double *chunk;                // partial sums per 64-row chunk (scratch): [n_est][ceil(n/64)],
+                                  // list path [ceil(n/64)][n_est]
     float *part;                  // [rs][n_est][n][KMAX] partial top-k (rs > 1)
     float *eps;                   // [n_est][n] radii (rs > 1, or diagnostics)
     int32_t *cnt;                 // [rs][n_est][3][n] per-split counts (rs > 1)
@@ -59,7 +60,8 @@ struct Job {
     int32_t *diag_cnt;            // optional [n_est][3][n] (n_xz, n_yz, n_z)
     // neighbour-list path only (see ListSet): list set index, and the
     // permuted X columns transposed so that the estimates of one row are
-    // adjacent: xt[c][i][e] = X_c[pi_e(i)] ([dx][n][n_est]).  The per-row
+    // adjacent: xt[c][i][e] = X_c[pi_e(i)] ([dx][n][n_est]) for the scan (xp
+    // holds the same values estimate-major for the fallback).  The per-row
     // counts go to pk; eps and cnt are the caller's diagnostics ([n_est][n],
     // [n_est][3][n]) or null.
     int set;

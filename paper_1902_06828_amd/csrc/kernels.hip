@@ -32,8 +32,8 @@ __device__ __forceinline__ int n_rounds_dev(int64_t n) {
 }
 
 // ------------------------------------------------------------------ permute
-// xp[e][c][i] = X_c[src_e(i)] (or, for the list path, xt[c][i][e]) for every
-// job, estimate and row.  Rows are R = J.reps replications of nr = n/R rows
+// xp[e][c][i] = X_c[src_e(i)] (and, for the list path, also xt[c][i][e]) for
+// every job, estimate and row.  Rows are R = J.reps replications of nr = n/R rows
 // (R = 1: one block of all rows).  One thread block per (job, estimate,
 // replication, 1024-row chunk of the replication); the block derives one
 // swap-or-not key schedule in LDS:
@@ -107,12 +107,10 @@ __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jo
             x = (int64_t)s_src_rep * nr + t;
         else
             x = base + swap_or_not((uint32_t)t, dn, rounds, s_rk, s_k);
-        if (J.xt) {
-            for (int c = 0; c < J.dx; ++c)
-                J.xt[((int64_t)c * J.n + i) * J.n_est + e] = J.cols[c][x];
-        } else {
-            for (int c = 0; c < J.dx; ++c)
-                J.xp[((int64_t)e * J.dx + c) * J.n + i] = J.cols[c][x];
+        for (int c = 0; c < J.dx; ++c) {
+            const float v = J.cols[c][x];
+            if (J.xt) J.xt[((int64_t)c * J.n + i) * J.n_est + e] = v;
+            J.xp[((int64_t)e * J.dx + c) * J.n + i] = v;
         }
     }
     __syncthreads();   // the next item rewrites the key schedule

@@ -809,7 +809,6 @@ constexpr uint32_t kFbBlockModeMax = 2048;   // queue length up to which a pair 
 struct FbPair {
     const Job *J;
     int i, e, n, dx, dy, dz;
-    int64_t cs;
 };
 
 __device__ __forceinline__ FbPair fb_pair(const ListLaunch &L, uint32_t it) {
@@ -825,7 +824,6 @@ __device__ __forceinline__ FbPair fb_pair(const ListLaunch &L, uint32_t it) {
     p.dx = p.J->dx;
     p.dy = p.J->dy;
     p.dz = p.J->dz;
-    p.cs = (int64_t)p.n * E;
     return p;
 }
 
@@ -834,7 +832,6 @@ __device__ __forceinline__ FbPair fb_pair(const ListLaunch &L, uint32_t it) {
 __device__ __forceinline__ void fb_dists(const FbPair &p, int j0, int step, float (&ax)[kFbBatch],
                                          float (&ay)[kFbBatch], float (&az)[kFbBatch]) {
     const Job &J = *p.J;
-    const int E = J.n_est;
     int jj[kFbBatch];
 #pragma unroll
     for (int u = 0; u < kFbBatch; ++u) {
@@ -843,10 +840,13 @@ __device__ __forceinline__ void fb_dists(const FbPair &p, int j0, int step, floa
         ax[u] = ay[u] = az[u] = 0.f;
     }
     for (int c = 0; c < p.dx; ++c) {
-        const float q = J.xt[c * p.cs + (int64_t)p.i * E + p.e];
+        // the estimate-major copy: consecutive rows are adjacent words (in the
+        // transposed one they are n_est words apart, a page apart in big launches)
+        const float *xe = J.xp + ((int64_t)p.e * p.dx + c) * p.n;
+        const float q = xe[p.i];
         float v[kFbBatch];
 #pragma unroll
-        for (int u = 0; u < kFbBatch; ++u) v[u] = J.xt[c * p.cs + (int64_t)jj[u] * E + p.e];
+        for (int u = 0; u < kFbBatch; ++u) v[u] = xe[jj[u]];
 #pragma unroll
         for (int u = 0; u < kFbBatch; ++u) ax[u] = fmax_(ax[u], absdiff(q, v[u]));
     }
@@ -996,8 +996,8 @@ __global__ __launch_bounds__(kFbThreads) void list_fallback_kernel(const ListLau
 // (H[n_xz] + H[n_yz]) - H[n_z] per row, summed in the all-pairs kernel's order
 // so that both paths return the same bits: a 64-row butterfly per chunk, then
 // the chunk sums added in index order.  Phase 1: one wave per (estimate,
-// chunk), blocks of kWaves chunks of one estimate; phase 2: one thread per
-// estimate adds its chunk sums.
+// chunk), blocks of kWaves chunks of one estimate, sums stored [chunk][estimate];
+// phase 2: one thread per estimate adds its chunk sums.
 __global__ __launch_bounds__(kBlock) void list_chunk_kernel(const ListLaunch L, const double *__restrict__ harm) {
     const int64_t g = bid_x();
     const int jb = find_job(L.est_off, L.n_jobs, g);
@@ -1016,7 +1016,7 @@ __global__ __launch_bounds__(kBlock) void list_chunk_kernel(const ListLaunch L, 
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
-    if (lane == 0) J.chunk[(int64_t)e * nch + c] = v;
+    if (lane == 0) J.chunk[(int64_t)c * J.n_est + e] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L, const double *__restrict__ harm) {
@@ -1027,19 +1027,22 @@ __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L,
     const int e = (int)(g - L.est_off[jb]);
     const int n = J.n;
     const int nch = (n + kChunk - 1) / kChunk;
-    const double *part = J.chunk + (int64_t)e * nch;
-    // in index order; the loads of 16 chunk sums are issued before their adds
+    // chunk sums are [chunk][estimate], so the threads of a wave (consecutive
+    // estimates) load adjacent words; added in index order, the loads of 16
+    // chunk sums issued before their adds
+    const double *part = J.chunk + e;
+    const int64_t st = J.n_est;
     constexpr int kU = 16;
     double acc = 0.0;
     int c = 0;
     for (; c + kU <= nch; c += kU) {
         double v[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = part[c + u];
+        for (int u = 0; u < kU; ++u) v[u] = part[(c + u) * st];
 #pragma unroll
         for (int u = 0; u < kU; ++u) acc += v[u];
     }
-    for (; c < nch; ++c) acc += part[c];
+    for (; c < nch; ++c) acc += part[c * st];
     J.out[e] = harm[J.k - 1] - acc / (double)n;
 }
 

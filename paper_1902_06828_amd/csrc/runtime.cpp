@@ -647,12 +647,14 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         o_zy[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * (size_t)(sp.dy + sp.dz) * sp.n, 256);
     }
-    struct Off { size_t xt, pk, xs, chunk; };
+    struct Off { size_t xt, xp, pk, xs, chunk; };
     std::vector<Off> offs(n_ljobs_);
     for (int j = 0; j < n_ljobs_; ++j) {
         const JobSpec &sp = specs[j];
         const size_t pairs = (size_t)sp.n * sp.n_est();
         offs[j].xt = bytes;
+        bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
+        offs[j].xp = bytes;
         bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
         offs[j].xs = bytes;
         if (sp.dz == 0) bytes = align_up(bytes + sizeof(float) * (size_t)sp.n, 256);
@@ -707,6 +709,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.reps = sp.reps;
         J.rep_shuffle = sp.rep_shuffle;
         J.xt = reinterpret_cast<float *>(sb + offs[j].xt);
+        J.xp = reinterpret_cast<float *>(sb + offs[j].xp);
         J.xs = sp.dz == 0 ? reinterpret_cast<float *>(sb + offs[j].xs) : nullptr;
         J.eps = sp.diag_eps;
         J.cnt = sp.diag_cnt;
