@@ -72,6 +72,7 @@ __device__ __forceinline__ float gload_b(const float *p, uint32_t byte_off) {
 }
 
 constexpr uint64_t kPackMask = (uint64_t(1) << kPackBits) - 1;
+constexpr int kXcds = 8;   // accelerator complex dies (one L2 each) of an MI355X
 
 __device__ __forceinline__ uint64_t pack_counts(int cxz, int cyz, int cz) {
     return (uint64_t)(uint32_t)cxz | ((uint64_t)(uint32_t)cyz << kPackBits) |
@@ -533,16 +534,47 @@ constexpr int kCoopU = 1;      // list entries per lane per cooperative step
 template <int KMAX, int DXM>
 __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const int lane = tid_x() & 63;
-    const int64_t g0 = bid_x() * kBlock + tid_x();
+    // Lane order.  A launch of one job runs its lanes over estimate groups:
+    // group c holds rows x estimates 64c .. 64c + E_c - 1, row-major, with
+    // E_c = 64 but for the last group, which takes the remainder too (64 to
+    // 127 estimates; all E when E < 64), so that a wave takes one row and 64
+    // consecutive estimates, or two rows.  The hardware deals blocks to the
+    // XCDs in turn; block b is renumbered so that each XCD takes a contiguous
+    // range of lanes, i.e. one or two groups, and its L2 holds those groups'
+    // columns of xt (n * 256 bytes each) instead of all of them.  A launch of
+    // several jobs keeps the hardware order and lane = row * E + estimate:
+    // unequal jobs then spread over all XCDs, and the waves of a row are
+    // neighbours, sharing its list entries in L1 and L2.
+    const bool grouped = L.n_jobs == 1;
+    int64_t b = bid_x();
+    if (grouped) {
+        const int64_t nb = (int64_t)__builtin_amdgcn_grid_size_x() / kBlock, hb = b;
+        const int64_t q = nb / kXcds, rem = nb % kXcds, x = hb % kXcds;
+        b = x * q + min(x, rem) + hb / kXcds;
+    }
+    const int64_t g0 = b * kBlock + tid_x();
     // every lane of a wave takes part in the cooperative steps: lanes past
     // the last pair mirror it and store nothing
     const bool live = g0 < L.lanes;
     const int64_t g = live ? g0 : L.lanes - 1;
     const int jb = find_job(L.lane_off, L.n_jobs, g);
     const Job &J = L.jobs[jb];
-    const int64_t r = g - L.lane_off[jb];
-    const int i = (int)(r / J.n_est);
-    const int e = (int)(r - (int64_t)i * J.n_est);
+    int i, e;
+    {
+        const int64_t r = g - L.lane_off[jb];
+        if (grouped) {
+            const int64_t gsz = (int64_t)J.n * 64;
+            const int ng = max(1, J.n_est / 64);
+            const int grp = (int)min(r / gsz, (int64_t)(ng - 1));
+            const int64_t rr = r - grp * gsz;
+            const int eg = grp == ng - 1 ? J.n_est - 64 * grp : 64;
+            i = (int)(rr / eg);
+            e = 64 * grp + (int)(rr - (int64_t)i * eg);
+        } else {
+            i = (int)(r / J.n_est);
+            e = (int)(r - (int64_t)i * J.n_est);
+        }
+    }
     const ListSet &S = L.sets[J.set];
     const int n = J.n;
     Lane<KMAX, DXM> ln(J, i, e);
@@ -772,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     if (live) {
         if (!decided) {
             const uint32_t pos = atomicAdd(&L.counters[0], 1u);
-            L.failq[pos] = ((uint64_t)jb << 40) | (uint64_t)r;
+            L.failq[pos] = ((uint64_t)jb << 40) | ((uint64_t)i * J.n_est + e);
         } else {
             J.pk[(int64_t)e * n + i] = pack_counts(cxz, cyz, cz);
             if (J.eps) J.eps[(int64_t)e * n + i] = eps;
