@@ -65,6 +65,22 @@ def test_list_equals_all_pairs(monkeypatch, n, dims, kind, seed):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("S", [63, 99, 127, 130])
+def test_estimate_groups(monkeypatch, S):
+    # a launch of one job runs its lanes over groups of 64 estimates, the last
+    # group taking the remainder (E = 64, 100, 128, 131: one group, one group
+    # of 100, two groups, two groups of 64 and 67), and renumbers the blocks
+    # across the XCDs; every (row, estimate) result must be unchanged
+    X, Y, Z = synth.random_points(1500, (1, 1, 3), seed=S)
+    out = {}
+    for mode in ("brute", "list"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("estimate groups, S", S, "mode", mode)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, 4, S, 3, 1)
+    for a, b in zip(out["brute"], out["list"]):
+        assert np.array_equal(a, b)
+
+
 def test_full_size_c2_list_equals_all_pairs(monkeypatch):
     # the benchmark's workload (N = 10000, 201 estimates) on both paths
     X, Y, Z, _ = synth.c2_te_inputs(10000, seed=2)
