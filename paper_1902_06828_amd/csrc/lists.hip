@@ -103,10 +103,7 @@ __device__ __forceinline__ int wave_sum(int v) {
 // Threads per build block: 8 waves, so that the 4 blocks whose histograms fit
 // in LDS keep 8 waves on every SIMD (the kernel waits mostly on LDS atomics
 // and L2 loads, and needs the waves to hide them).
-#ifndef MTE_BUILD_THREADS
-#define MTE_BUILD_THREADS 512
-#endif
-constexpr int kBT = MTE_BUILD_THREADS;
+constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 
 // Inclusive scan over the kBT threads of a build block; returns the block total.
