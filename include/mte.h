@@ -440,12 +440,15 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
 
 /* --------------------------------------------------------------------------
  * Kernel timing: when enabled, launches are made directly (no graph replay)
- * and HIP events are recorded on the launch stream around every kernel
- * launch of the stages below; the elapsed times are accumulated per stage
- * (reading waits for the recorded events).  mte_kernel_timing_read reads
- * stage MTE_STAGE_ALL_PAIRS.  reset = 1 clears the stage after reading.
- *   MTE_STAGE_ALL_PAIRS  all-pairs KSG kernel (jobs without Z columns, or
- *                        with too few estimates per (Y,Z) sample)
+ * and HIP events are recorded around every kernel launch of the stages
+ * below, on the stream the kernel runs on (the list path's permutation runs
+ * on a library stream beside the build, so those two stages overlap); the
+ * elapsed times are accumulated per stage (reading waits for the recorded
+ * events).  mte_kernel_timing_read reads stage MTE_STAGE_ALL_PAIRS.
+ * reset = 1 clears the stage after reading.
+ *   MTE_STAGE_ALL_PAIRS  all-pairs KSG kernel (jobs the list path does not
+ *                        take: fewer than 8 estimates per (Y,Z) sample, no Z
+ *                        with several X columns or N > 16384, or N > 2^21)
  *   MTE_STAGE_BUILD      neighbour-list build, once per (Y,Z) sample
  *   MTE_STAGE_SCAN       per (row, estimate) k-NN radius and counts over the lists
  *   MTE_STAGE_FALLBACK   all-rows redo of the pairs the lists cannot decide
