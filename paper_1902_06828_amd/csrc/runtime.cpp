@@ -945,8 +945,10 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         MTE_HIP(hipEventRecord(fork_, s));
         MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
         if ((rc = begin(side))) return rc;
-        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side,
-                           (int64_t)kPermuteBlocksPerCu * ctx().n_cu))
+        // capped only while the permutation is the smaller part: a launch of
+        // many estimates over few list sets has more permutation than build
+        const int64_t pgrid = lpermute_blocks_ <= ll_.build_blocks ? (int64_t)kPermuteBlocksPerCu * ctx().n_cu : 0;
+        if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side, pgrid))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute, side))) return rc;
         MTE_HIP(hipEventRecord(join_, side));
