@@ -611,7 +611,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         dxm = std::max(dxm, sp.dx);
         n_keys += sp.n_est();
     }
-    // scratch layout: per set its lists, per job xt, eps, cnt; then the queue
+    // scratch layout: per set its lists and Y,Z copy; per job xt, xp, the
+    // packed counts and the chunk sums; then the queue
     size_t bytes = 0;
     int nmax_set = 0;
     std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets), o_zy(n_sets);
