@@ -76,6 +76,8 @@ __global__ __launch_bounds__(64) void gauss_mean_kernel(GaussCov a) {
 }
 
 // Upper-triangle tile pair y -> (tp, tq), tp <= tq.
+constexpr int kXcds = 8;   // accelerator complex dies (one L2 each) of an MI355X
+
 __device__ __forceinline__ void tile_pair(int y, int n_tiles, int *tp, int *tq) {
     int p = 0;
     while (y >= n_tiles - p) {
@@ -110,9 +112,22 @@ __global__ __launch_bounds__(kThreads) void gauss_gram_kernel(GaussCov a) {
     __shared__ __align__(16) double As[T][LDC];
     __shared__ __align__(16) double Bs[T][LDC];
     const int tid = tid_x();
-    const int c = bid_x();
+    // One block per (row chunk, tile pair), numbered chunk-major.  With
+    // several tile pairs, the blocks, which the hardware deals to the XCDs in
+    // turn, are renumbered so that each XCD takes a contiguous range, i.e. all
+    // tile pairs of its chunks together: they read the same rows of the same
+    // columns step by step, so a column tile comes from HBM about once per
+    // chunk instead of once per pair.
+    const int pairs = a.n_tiles * (a.n_tiles + 1) / 2;
+    int b = bid_x();
+    if (pairs > 1) {
+        const int nb = (int)(__builtin_amdgcn_grid_size_x() / kThreads), hb = b;
+        const int q = nb / kXcds, rem = nb % kXcds, x = hb % kXcds;
+        b = x * q + min(x, rem) + hb / kXcds;
+    }
+    const int c = b / pairs;
     int tp, tq;
-    tile_pair(bid_y(), a.n_tiles, &tp, &tq);
+    tile_pair(b - c * pairs, a.n_tiles, &tp, &tq);
     const int p0 = tp * T, q0 = tq * T;
     const int r0 = c * a.chunk_rows;
     const int r1 = min(a.n, r0 + a.chunk_rows);
@@ -265,8 +280,8 @@ int launch_gauss_colsum(const GaussCov &a, hipStream_t s) {
 int launch_gauss_gram(const GaussCov &a, hipStream_t s) {
     if (a.D < 1 || a.n < 1) return 0;
     if (a.tile != 64) return -1;
-    const int pairs = a.n_tiles * (a.n_tiles + 1) / 2;
-    hipLaunchKernelGGL(gauss_gram_kernel, dim3((unsigned)a.n_chunks, (unsigned)pairs), dim3(kThreads), 0, s, a);
+    const int64_t blocks = (int64_t)a.n_chunks * (a.n_tiles * (a.n_tiles + 1) / 2);
+    hipLaunchKernelGGL(gauss_gram_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
