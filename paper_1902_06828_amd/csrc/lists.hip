@@ -64,6 +64,22 @@ __device__ __forceinline__ float gload(const float *p, uint32_t off) {
     return ((const __attribute__((address_space(1))) float *)p)[off];
 }
 
+// List entries stored through global-address-space pointers: a generic
+// (flat) store counts against the LDS counter too, so the next wait for an
+// LDS atomic's return would also wait for the store to reach memory.
+__device__ __forceinline__ void gstore(LEnt *p, uint32_t idx, const LEnt &v) {
+    auto *q = (__attribute__((address_space(1))) uint32_t *)(p + idx);
+    q[0] = __float_as_uint(v.d);
+    q[1] = (uint32_t)v.j;
+}
+
+__device__ __forceinline__ void gstore(LEnt2 *p, uint32_t idx, const LEnt2 &v) {
+    auto *q = (__attribute__((address_space(1))) uint32_t *)(p + idx);
+    q[0] = __float_as_uint(v.dz);
+    q[1] = __float_as_uint(v.dyz);
+    q[2] = (uint32_t)v.j;
+}
+
 // The same with a byte offset: the address is then a uniform base plus one
 // 32-bit register, the form the global loads take without address arithmetic.
 __device__ __forceinline__ float gload_b(const float *p, uint32_t byte_off) {
@@ -358,12 +374,12 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
         if (k1 < keep[r][0]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 0, k1), bin_inc<PACK>(0)), 0);
-            if (pos < m1) out1[r][pos] = LEnt{c, j};
+            if (pos < m1) gstore(out1[r], pos, LEnt{c, j});
         }
         if (k2 < keep[r][1]) {
             const uint32_t pos =
                 bin_get<PACK>(atomicAdd(bin_word<PACK>(sm.h[r][copy], 1, k2), bin_inc<PACK>(1)), 1);
-            if (pos < m2) out2[r][pos] = LEnt2{a, c, j};
+            if (pos < m2) gstore(out2[r], pos, LEnt2{a, c, j});
         }
     });
     // lengths, bounds and the sentinels after each list
@@ -872,28 +888,28 @@ __device__ __forceinline__ void fb_dists(const FbPair &p, int j0, int step, floa
         // the estimate-major copy: consecutive rows are adjacent words (in the
         // transposed one they are n_est words apart, a page apart in big launches)
         const float *xe = J.xp + ((int64_t)p.e * p.dx + c) * p.n;
-        const float q = xe[p.i];
+        const float q = gload(xe, (uint32_t)p.i);
         float v[kFbBatch];
 #pragma unroll
-        for (int u = 0; u < kFbBatch; ++u) v[u] = xe[jj[u]];
+        for (int u = 0; u < kFbBatch; ++u) v[u] = gload(xe, (uint32_t)jj[u]);
 #pragma unroll
         for (int u = 0; u < kFbBatch; ++u) ax[u] = fmax_(ax[u], absdiff(q, v[u]));
     }
     const float *const *yc = J.cols + p.dx;
     for (int c = 0; c < p.dy; ++c) {
-        const float q = yc[c][p.i];
+        const float q = gload(yc[c], (uint32_t)p.i);
         float v[kFbBatch];
 #pragma unroll
-        for (int u = 0; u < kFbBatch; ++u) v[u] = yc[c][jj[u]];
+        for (int u = 0; u < kFbBatch; ++u) v[u] = gload(yc[c], (uint32_t)jj[u]);
 #pragma unroll
         for (int u = 0; u < kFbBatch; ++u) ay[u] = fmax_(ay[u], absdiff(q, v[u]));
     }
     const float *const *zc = J.cols + p.dx + p.dy;
     for (int c = 0; c < p.dz; ++c) {
-        const float q = zc[c][p.i];
+        const float q = gload(zc[c], (uint32_t)p.i);
         float v[kFbBatch];
 #pragma unroll
-        for (int u = 0; u < kFbBatch; ++u) v[u] = zc[c][jj[u]];
+        for (int u = 0; u < kFbBatch; ++u) v[u] = gload(zc[c], (uint32_t)jj[u]);
 #pragma unroll
         for (int u = 0; u < kFbBatch; ++u) az[u] = fmax_(az[u], absdiff(q, v[u]));
     }
