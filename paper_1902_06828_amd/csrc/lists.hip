@@ -537,11 +537,14 @@ __device__ __forceinline__ T *bcast(T *v, int o) {
 // may stop at any position whose bucket floor reaches the current radius.
 // A cooperative step gathers X for 64 different rows (64 cache lines instead
 // of the 2-4 of a lane-by-lane step, whose lanes are adjacent estimates), so
-// it only pays for the last few lanes: on C2 (N = 10^4, 201 estimates) the scan
-// took 0.62 ms without it, 0.48 ms with kCoopLanes = 2, 0.50 ms with 4, 0.54
-// ms with 8, 0.67 ms with 16; 2 or 4 entries per lane per cooperative step
-// were slower still (more scattered gathers past the stop position).
-constexpr int kCoopLanes = 2;
+// it only pays for the last few lanes: on C2 (N = 10^4, 201 estimates), in the
+// hardware block order, the scan took 0.62 ms without it, 0.48 ms with
+// kCoopLanes = 2, 0.50 ms with 4, 0.54 ms with 8, 0.67 ms with 16; with the
+// XCD-aware order (below), whose gathers mostly hit L2, 0.343 ms with 2,
+// 0.335 ms with 4, 0.350 ms with 6, 0.372 ms with 8.  2 or 4 entries per lane
+// per cooperative step were slower still (more scattered gathers past the
+// stop position).
+constexpr int kCoopLanes = 4;
 constexpr int kCoopU = 1;      // list entries per lane per cooperative step
 
 template <int KMAX, int DXM>
