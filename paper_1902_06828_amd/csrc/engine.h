@@ -110,6 +110,8 @@ constexpr int kListPad = 8;                   // sentinel entries after each row
 struct ListSet {
     const float *cols[kMaxDy + kMaxDz];   // Y columns, then Z columns
     float *zy;                    // [dz + dy][n] contiguous copy: Z columns, then Y (build input)
+    int32_t *order;               // [n] the scan's row order in launches of several jobs: rows
+                                  // grouped by Morton cell of their Z, Y coordinates; null: identity
     int n, dy, dz;
     int theiler;                  // Theiler window of the rows (|i - j| <= w left out)
     int m1, m2;                   // list capacities per row
@@ -196,6 +198,7 @@ int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_o
                 const double *harm, void *stream);
 
 int launch_list_zy(const ListLaunch &L, void *stream);      // the sets' contiguous Y,Z copies
+int launch_list_order(const ListLaunch &L, void *stream);  // the scan's row order (several jobs)
 int launch_list_build(const ListLaunch &L, void *stream);
 int launch_list_sortx(const ListLaunch &L, void *stream);
 int launch_list_scan(const ListLaunch &L, void *stream);

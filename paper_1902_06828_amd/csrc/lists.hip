@@ -123,6 +123,7 @@ constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 
 // Inclusive scan over the kBT threads of a build block; returns the block total.
+template <int NW = kBW>
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint32_t *wtot) {
     const int lane = tid_x() & 63, wave = tid_x() >> 6;
 #pragma unroll
@@ -134,7 +135,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t &incl, uint3
     __syncthreads();
     uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kBW; ++w) {
+    for (int w = 0; w < NW; ++w) {
         before += w < wave ? wtot[w] : 0u;
         total += wtot[w];
     }
@@ -449,6 +450,112 @@ __global__ __launch_bounds__(kSortThreads) void list_sortx_kernel(const ListLaun
     for (int x = tid; x < n; x += kSortThreads) J.xs[x] = v[x];
 }
 
+// ------------------------------------------------------------------ row order
+// One block per list set with an order array: its rows grouped by Morton
+// (Z-curve) cell of their first D <= 6 coordinates in the contiguous copy (Z
+// columns, then Y).  Each coordinate is cut into 2^(12/D) equal steps between
+// the column's minimum and maximum and the step indices' bits are interleaved
+// from the top into a cell code below 2^12; a counting sort over the codes in
+// LDS (histogram, block scan, scatter) then lists the rows cell by cell.  The
+// cell codes stay in registers (a thread takes rows tid + u * 1024) and the
+// block takes 17 KB of LDS, so it finds room beside the build's blocks.
+// Rows next to each other in this order are near in (Y,Z) and share list
+// entries.  The order of the rows within a cell follows the scatter's LDS
+// atomics and may differ between launches: only the order in which the scan
+// visits rows depends on it, not any result.
+constexpr int kOrderDims = 6;
+constexpr int kOrderBits = 12;
+constexpr int kOrderCells = 1 << kOrderBits;
+
+__global__ __launch_bounds__(kSortThreads) void list_order_kernel(const ListLaunch L) {
+    constexpr int NW = kSortThreads / 64, PER = kOrderCells / kSortThreads;
+    constexpr int ROWS = kNoZSortMax / kSortThreads;   // rows per thread
+    __shared__ uint32_t h[kOrderCells];
+    __shared__ float red[2][kOrderDims][NW];
+    __shared__ uint32_t wtot[NW];
+    const ListSet &S = L.sets[bid_x()];
+    const int n = S.n;
+    if (!S.order || n > kNoZSortMax) return;    // the host sets no order array then
+    const int tid = tid_x(), lane = tid & 63, w = tid >> 6;
+    const int D = min(kOrderDims, S.dy + S.dz);
+    const int bpd = kOrderBits / D;
+    for (int c = tid; c < kOrderCells; c += kSortThreads) h[c] = 0;
+    // column ranges
+    float lo[kOrderDims], hi[kOrderDims];
+#pragma unroll
+    for (int q = 0; q < kOrderDims; ++q) {
+        lo[q] = inf_f();
+        hi[q] = -inf_f();
+        if (q < D)
+            for (int x = tid; x < n; x += kSortThreads) {
+                const float c = S.zy[(int64_t)q * n + x];
+                lo[q] = __builtin_fminf(lo[q], c);
+                hi[q] = __builtin_fmaxf(hi[q], c);
+            }
+        lo[q] = wave_min(lo[q]);
+        hi[q] = -wave_min(-hi[q]);
+        if (lane == 0) {
+            red[0][q][w] = lo[q];
+            red[1][q][w] = hi[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kOrderDims; ++q) {
+        lo[q] = red[0][q][0];
+        hi[q] = red[1][q][0];
+        for (int u = 1; u < NW; ++u) {
+            lo[q] = __builtin_fminf(lo[q], red[0][q][u]);
+            hi[q] = __builtin_fmaxf(hi[q], red[1][q][u]);
+        }
+    }
+    const float steps = (float)(1 << bpd);
+    uint32_t code[ROWS];                        // each row's cell, computed once
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) {
+        const int x = tid + u * kSortThreads;
+        code[u] = 0;
+        if (x >= n) continue;
+        uint32_t cell[kOrderDims];
+#pragma unroll
+        for (int q = 0; q < kOrderDims; ++q) {
+            cell[q] = 0;
+            if (q < D && hi[q] > lo[q]) {
+                const float t = (S.zy[(int64_t)q * n + x] - lo[q]) / (hi[q] - lo[q]) * steps;
+                cell[q] = t >= 1.0f ? (t < steps ? (uint32_t)t : (uint32_t)steps - 1u) : 0u;
+            }
+        }
+        uint32_t c = 0;
+        for (int bit = bpd - 1; bit >= 0; --bit)
+            for (int q = 0; q < D; ++q) c = c << 1 | ((cell[q] >> bit) & 1u);
+        code[u] = c;              // < 2^(D * bpd) <= kOrderCells
+        atomicAdd(&h[c], 1u);
+    }
+    __syncthreads();
+    // exclusive offsets: each thread owns PER consecutive cells
+    uint32_t loc[PER], sum = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        loc[u] = h[tid * PER + u];
+        sum += loc[u];
+    }
+    uint32_t incl;
+    block_scan<NW>(sum, incl, wtot);
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        h[tid * PER + u] = run;
+        run += loc[u];
+    }
+    __syncthreads();
+    // the counts add up to n, so every position is below n
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) {
+        const int x = tid + u * kSortThreads;
+        if (x < n) S.order[atomicAdd(&h[code[u]], 1u)] = x;
+    }
+}
+
 // ------------------------------------------------------------------ scan
 // Each list row is followed by kListPad sentinel entries (row = self, d_yz =
 // +inf) whose key distance lies in the bucket that starts at the row's bound:
@@ -558,9 +665,11 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     // XCDs in turn; block b is renumbered so that each XCD takes a contiguous
     // range of lanes, i.e. one or two groups, and its L2 holds those groups'
     // columns of xt (n * 256 bytes each) instead of all of them.  A launch of
-    // several jobs keeps the hardware order and lane = row * E + estimate:
-    // unequal jobs then spread over all XCDs, and the waves of a row are
-    // neighbours, sharing its list entries in L1 and L2.
+    // several jobs keeps the hardware order and lane = row * E + estimate,
+    // rows taken in the set's Morton order: unequal jobs then spread over all
+    // XCDs, the waves of a row are neighbours, sharing its list entries, and
+    // rows that run together are near in (Y,Z), so that many of the X values
+    // they gather are the same.
     const bool grouped = L.n_jobs == 1;
     int64_t b = bid_x();
     if (grouped) {
@@ -575,6 +684,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const int64_t g = live ? g0 : L.lanes - 1;
     const int jb = find_job(L.lane_off, L.n_jobs, g);
     const Job &J = L.jobs[jb];
+    const ListSet &S = L.sets[J.set];
     int i, e;
     {
         const int64_t r = g - L.lane_off[jb];
@@ -587,11 +697,11 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
             i = (int)(rr / eg);
             e = 64 * grp + (int)(rr - (int64_t)i * eg);
         } else {
-            i = (int)(r / J.n_est);
-            e = (int)(r - (int64_t)i * J.n_est);
+            const int il = (int)(r / J.n_est);
+            e = (int)(r - (int64_t)il * J.n_est);
+            i = S.order ? S.order[il] : il;
         }
     }
-    const ListSet &S = L.sets[J.set];
     const int n = J.n;
     Lane<KMAX, DXM> ln(J, i, e);
 
@@ -1105,6 +1215,12 @@ int launch_list_zy(const ListLaunch &L, void *stream) {
     if (L.rows <= 0) return 0;
     hipLaunchKernelGGL(list_zy_kernel, dim3((unsigned)((L.rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        (hipStream_t)stream, L);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_order(const ListLaunch &L, void *stream) {
+    if (L.n_jobs <= 1) return 0;
+    hipLaunchKernelGGL(list_order_kernel, dim3((unsigned)L.n_sets), dim3(kSortThreads), 0, (hipStream_t)stream, L);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -615,7 +615,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     // packed counts and the chunk sums; then the queue
     size_t bytes = 0;
     int nmax_set = 0;
-    std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets), o_zy(n_sets);
+    std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets), o_zy(n_sets),
+        o_order(n_sets, 0);
     std::vector<int> set_dx(n_sets, 0);
     for (int j = 0; j < n_ljobs_; ++j) set_dx[set_of[j]] = std::max(set_dx[set_of[j]], specs[j].dx);
     for (int t = 0; t < n_sets; ++t) {
@@ -647,6 +648,13 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         bytes = align_up(bytes + sizeof(float) * 2 * (size_t)sp.n, 256);
         o_zy[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * (size_t)(sp.dy + sp.dz) * sp.n, 256);
+        // a launch of several jobs scans rows in the order of their first
+        // coordinate: rows with close Y,Z points share list entries, so their
+        // permuted-X gathers meet in L2
+        if (n_ljobs_ > 1 && sp.n <= kNoZSortMax) {
+            o_order[t] = bytes;
+            bytes = align_up(bytes + sizeof(int32_t) * (size_t)sp.n, 256);
+        }
     }
     struct Off { size_t xt, xp, pk, xs, chunk; };
     std::vector<Off> offs(n_ljobs_);
@@ -677,6 +685,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.len = reinterpret_cast<int32_t *>(sb + o_len[t]);
         S.bound = reinterpret_cast<float *>(sb + o_bound[t]);
         S.zy = reinterpret_cast<float *>(sb + o_zy[t]);
+        S.order = o_order[t] ? reinterpret_cast<int32_t *>(sb + o_order[t]) : nullptr;
     }
     // tables: jobs, sets, keys, offsets
     const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
@@ -952,6 +961,9 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side, pgrid))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute, side))) return rc;
+        // the scan's row order (launches of several jobs) is needed by the
+        // scan only, so it waits on the side stream too
+        if (launch_list_order(ll_, side)) return hip_fail(hipGetLastError(), "row order launch");
         MTE_HIP(hipEventRecord(join_, side));
         ll_.stats = ctx().list_stats ? 1 : 0;
         if ((rc = begin(s))) return rc;

@@ -98,10 +98,15 @@ def test_full_size_c2_list_equals_all_pairs(monkeypatch):
         assert np.array_equal(a, b)
 
 
-def test_shared_lists_across_jobs(monkeypatch):
+@pytest.mark.parametrize("quantised", [False, True])
+def test_shared_lists_across_jobs(monkeypatch, quantised):
     # several candidates with the same Y and Z (one list set) in one launch:
-    # the greedy driver's batches; each must equal its own single-job result
+    # the greedy driver's batches; each must equal its own single-job result.
+    # Such launches scan rows in a Morton order of (Y,Z); quantised values
+    # put many rows in one cell (equal codes, told apart by the row index)
     series, links = synth.var_network(6, 1500, seed=6)
+    if quantised:
+        series = np.round(series * 2.0) / 2.0
     monkeypatch.setenv("MTE_FORCE_MODE", "list")
     target = min(i for (i, _, _, _) in links)
     cands = [j for j in range(6) if j != target]
