@@ -444,7 +444,9 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
  * below, on the stream the kernel runs on (the list path's permutation runs
  * on a library stream beside the build, so those two stages overlap); the
  * elapsed times are accumulated per stage (reading waits for the recorded
- * events).  mte_kernel_timing_read reads stage MTE_STAGE_ALL_PAIRS.
+ * events).  In a list-path launch of several jobs, the kernel that orders
+ * the rows for the scan follows the permutation on that stream and falls in
+ * no stage.  mte_kernel_timing_read reads stage MTE_STAGE_ALL_PAIRS.
  * reset = 1 clears the stage after reading.
  *   MTE_STAGE_ALL_PAIRS  all-pairs KSG kernel (jobs the list path does not
  *                        take: fewer than 8 estimates per (Y,Z) sample, no Z
