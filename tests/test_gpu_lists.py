@@ -119,6 +119,26 @@ def test_shared_lists_across_jobs(monkeypatch, quantised):
     assert res["omnibus_te"] == ref["omnibus_te"] and res["omnibus_p"] == ref["omnibus_p"]
 
 
+@pytest.mark.parametrize("n", [16384, 16385])
+def test_row_order_size_limit(monkeypatch, n):
+    # launches of several jobs order the rows of sets with N <= 16384 (one
+    # block, counting sort) and keep the index order above; both sides of the
+    # limit against the all-pairs kernel (the series hold n + 5 samples, so
+    # with a largest lag of 5 the embedding has N = n rows)
+    series, links = synth.var_network(4, n, seed=7)
+    assert series.shape[1] == n + 5
+    target = min(i for (i, _, _, _) in links)
+    cands = [j for j in range(4) if j != target]
+    out = {}
+    for mode in ("list", "brute"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("row order limit, N", n, "mode", mode)
+        out[mode] = mte.mte_select_sources(series, target, cands, max_lag_sources=3, max_lag_target=5,
+                                           alpha=0.05, S=40, seed=7)
+    for key in ("target_past", "sources", "sources_before_omnibus", "omnibus_te", "omnibus_p", "n_estimates"):
+        assert out["list"][key] == out["brute"][key]
+
+
 def test_large_n_unpacked_histograms(monkeypatch):
     # N above 2^16 takes the build variant with 32-bit histograms; rows sampled
     # against the oracle, and the whole output against the all-pairs kernel
