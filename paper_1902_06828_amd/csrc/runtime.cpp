@@ -648,8 +648,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         bytes = align_up(bytes + sizeof(float) * 2 * (size_t)sp.n, 256);
         o_zy[t] = bytes;
         bytes = align_up(bytes + sizeof(float) * (size_t)(sp.dy + sp.dz) * sp.n, 256);
-        // a launch of several jobs scans rows in the order of their first
-        // coordinate: rows with close Y,Z points share list entries, so their
+        // a launch of several jobs scans rows grouped by Morton cell of their
+        // Z,Y point: rows with close points share list entries, so their
         // permuted-X gathers meet in L2
         if (n_ljobs_ > 1 && sp.n <= kNoZSortMax) {
             o_order[t] = bytes;
