@@ -383,7 +383,13 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
             if (pos < m2) gstore(out2[r], pos, LEnt2{a, c, j});
         }
     });
-    // lengths, bounds and the sentinels after each list
+    // lengths, bounds and the sentinels after each list.  A list is whole
+    // when it holds every row outside the window, or when the first bucket
+    // left out is the +inf bucket (every row at a finite distance fitted and
+    // the others' differences overflow): a row at +inf can enter neither a
+    // radius (every listed distance is at most +inf) nor a strict count below
+    // any radius, so leaving it out changes nothing.  Whole lists get +inf
+    // for the bound and the sentinels; bound + 1 ulp would be a NaN there.
     for (int x = tid; x < QB * 2 * kListPad; x += kBT) {
         const int r = x / (2 * kListPad), w = (x / kListPad) & 1, u = x % kListPad;
         if (r >= nq) continue;
@@ -391,8 +397,9 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
         const int tw = S.theiler;   // rows outside the window
         const uint32_t total = (uint32_t)(n - 1 - min((int)i, tw) - min(n - 1 - (int)i, tw));
         const uint32_t kb = sm.kept_bins[r][w], kr = sm.kept_rows[r][w];
-        const float bound = kr == total ? inf_f() : __uint_as_float(kb << kKeyShift);
-        const float sent = kr == total ? inf_f() : __uint_as_float((kb << kKeyShift) + 1u);
+        const bool whole = kr == total || (kb << kKeyShift) >= __float_as_uint(inf_f());
+        const float bound = whole ? inf_f() : __uint_as_float(kb << kKeyShift);
+        const float sent = whole ? inf_f() : __uint_as_float((kb << kKeyShift) + 1u);
         if (w == 0) S.l1[i * S.s1 + kr + u] = LEnt{sent, (int32_t)i};
         else S.l2[i * S.s2 + kr + u] = LEnt2{sent, inf_f(), (int32_t)i};
         if (u == 0) {
@@ -509,7 +516,14 @@ __global__ __launch_bounds__(kSortThreads) void list_order_kernel(const ListLaun
             hi[q] = __builtin_fmaxf(hi[q], red[1][q][u]);
         }
     }
+    // the steps are cut on halved values: differences of halved finite
+    // floats cannot overflow, so no step of the cell code meets inf / inf
     const float steps = (float)(1 << bpd);
+#pragma unroll
+    for (int q = 0; q < kOrderDims; ++q) {
+        lo[q] *= 0.5f;
+        hi[q] *= 0.5f;
+    }
     uint32_t code[ROWS];                        // each row's cell, computed once
 #pragma unroll
     for (int u = 0; u < ROWS; ++u) {
@@ -521,7 +535,7 @@ __global__ __launch_bounds__(kSortThreads) void list_order_kernel(const ListLaun
         for (int q = 0; q < kOrderDims; ++q) {
             cell[q] = 0;
             if (q < D && hi[q] > lo[q]) {
-                const float t = (S.zy[(int64_t)q * n + x] - lo[q]) / (hi[q] - lo[q]) * steps;
+                const float t = (0.5f * S.zy[(int64_t)q * n + x] - lo[q]) / (hi[q] - lo[q]) * steps;
                 cell[q] = t >= 1.0f ? (t < steps ? (uint32_t)t : (uint32_t)steps - 1u) : 0u;
             }
         }
@@ -559,7 +573,8 @@ __global__ __launch_bounds__(kSortThreads) void list_order_kernel(const ListLaun
 // ------------------------------------------------------------------ scan
 // Each list row is followed by kListPad sentinel entries (row = self, d_yz =
 // +inf) whose key distance lies in the bucket that starts at the row's bound:
-// the bound plus one unit in the last place (+inf when nothing was left out).
+// the bound plus one unit in the last place (+inf for a whole list: nothing
+// left out, or only rows at +inf).
 // A step of kU <= kListPad entries that starts at or before the list's end
 // then needs no bounds checks, and the last step of a list always ends on a
 // sentinel, whose bucket-floor test (floor = bound >= radius) is exactly the

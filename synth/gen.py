@@ -237,9 +237,18 @@ def random_points(n: int, dims, seed: int, kind: str = "normal"):
 
     kind: "normal" (continuous), "grid" (values on a coarse dyadic grid, so many
     exact distance ties), "dup" (normal values with a quarter of the rows
-    duplicated), "tiny" (denormal-range magnitudes), "wide" (mixed magnitudes).
+    duplicated), "tiny" (denormal-range magnitudes), "wide" (mixed magnitudes),
+    "cells" (every value s * 3e38 + u with a random sign s per value and
+    u ~ U(-0.25e38, 0.25e38): two values of one sign differ by at most 0.5e38,
+    two of opposite signs by more than the largest float, so in any subspace a
+    row is at a finite distance only from the rows whose signs all agree with
+    its own, and at +inf from the rest), "split" (the same values with one sign
+    per row, shared by all its coordinates: two clusters of exactly n // 2 and
+    n - n // 2 rows, finite within a cluster and +inf across).
     """
     g = _rng(seed)
+    if kind == "split":
+        sign = np.where(g.permutation(n) < n // 2, -1.0, 1.0)
     out = []
     for d in dims:
         if d == 0:
@@ -255,6 +264,9 @@ def random_points(n: int, dims, seed: int, kind: str = "normal"):
             a = g.standard_normal((d, n)) * 1e-39
         elif kind == "wide":
             a = g.standard_normal((d, n)) * np.exp2(g.integers(-20, 21, size=(d, n)))
+        elif kind in ("cells", "split"):
+            s = np.where(g.random((d, n)) < 0.5, -1.0, 1.0) if kind == "cells" else np.tile(sign, (d, 1))
+            a = s * 3e38 + g.uniform(-0.25e38, 0.25e38, size=(d, n))
         else:
             raise ValueError(kind)
         out.append(a.astype(np.float32))

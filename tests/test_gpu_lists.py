@@ -159,3 +159,40 @@ def test_large_n_unpacked_histograms(monkeypatch):
         re, ra, rb, rc, _ = cksg.eps_and_counts(Xe, Y, Z, 4, queries=rows)
         assert np.array_equal(eps[e, rows], re) and np.array_equal(cx[e, rows], ra)
         assert np.array_equal(cy[e, rows], rb) and np.array_equal(cz[e, rows], rc)
+
+
+def _overflow_points(n, dims, seed, kind):
+    if kind == "mixed":
+        # values whose differences are finite or overflow depending on the pair
+        g = np.random.default_rng(seed)
+        vals = np.array([-3e38, 3e38, 0.0, 1.0, -2.5e38], np.float32)
+        return [None if d == 0 else np.ascontiguousarray(vals[g.integers(0, 5, size=(d, n))]) for d in dims]
+    return synth.random_points(n, dims, seed=seed, kind=kind)
+
+
+@pytest.mark.parametrize("caps", ["default", "16,40", "2,3"])
+@pytest.mark.parametrize("n,dims,kind,some_inf", [(3000, (3, 1, 5), "cells", True), (2000, (1, 1, 5), "split", False),
+                                                  (3000, (1, 2, 3), "cells", False), (200, (1, 1, 2), "mixed", False),
+                                                  (3000, (1, 1, 0), "cells", False)])
+def test_list_path_overflowing_differences(monkeypatch, caps, n, dims, kind, some_inf):
+    # Differences that overflow to +inf.  With the default capacities a row's
+    # rows at a finite (Y,Z) or Z distance fit its lists and the rest are at
+    # +inf, so the first bucket a list leaves out is the +inf bucket; in the
+    # "cells" inputs many rows also have fewer than k rows at a finite joint
+    # distance (512 joint sign cells for 9 columns, ~6 rows each), so their
+    # radius is +inf and their scans run to the sentinels.
+    # Radii and counts bit for bit against the oracle on every estimate.
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    if caps != "default":
+        monkeypatch.setenv("MTE_LIST_CAP", caps)
+    X, Y, Z = _overflow_points(n, dims, 40 + n, kind)
+    if kind != "mixed" and caps == "default" and Z is not None:
+        # every row's finite (Y,Z) neighbours fit the smallest default list,
+        # and some rows lie outside them
+        yz = np.concatenate([Z, Y]) > 0
+        _, inv, size = np.unique(yz.T, axis=0, return_inverse=True, return_counts=True)
+        assert size.max() - 1 <= 1024 and size.min() - 1 < n - 1
+    say("overflow case", n, dims, kind, "caps", caps)
+    cmi, eps, *_ = check_against_oracle(X, Y, Z, 4, 8, seed=5, cand=1)
+    if some_inf:
+        assert np.isinf(eps).any() and np.isfinite(eps).any()
