@@ -131,6 +131,31 @@ int cmi_ksg_surrogates_dev_ex(const float *dX, int dx, const float *dY, int dy, 
                               uint64_t seed, uint32_t cand, double *d_out, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimate and S surrogates of cmi_ksg_surrogates_dev, same arguments and
+ * results (bit for bit), with every scratch word in one static device array
+ * of MTE_NOALLOC_SCRATCH_BYTES that each GPU holds from the library's load
+ * until the process ends.  The call allocates nothing: no hipMalloc, no
+ * host staging, no library allocator; it enqueues a setup kernel and the
+ * all-pairs kernels on `stream` and returns.
+ *   - mte_init must have been called (it builds the harmonic table and binds
+ *     the array's device address); otherwise MTE_EINVAL.
+ *   - N <= 2^20 (the harmonic table of mte_init).
+ *   - The scratch needed, about 4*dx*N*(1+S) bytes of permuted X plus
+ *     8*(1+S)*ceil(N/64) of chunk sums and small tables, must fit
+ *     MTE_NOALLOC_SCRATCH_BYTES; otherwise MTE_EINVAL with the size in the
+ *     message.  (N = 10^4, 1+S = 201, dx = 1 takes 8.3 MB.)
+ *   - All calls on one GPU share the array and keep the last call's
+ *     contents; calls that overlap in time on one GPU (different streams,
+ *     or threads) race and give wrong results.  Serialise them.
+ */
+#define MTE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cmi_ksg_surrogates_dev_noalloc(const float *dX, int dx, const float *dY, int dy,
+                                   const float *dZ, int dz, int64_t N, int64_t ld, int k, int S,
+                                   uint64_t seed, uint32_t cand, double *d_out, void *stream);
+
+/*
  * Autocorrelation decay time of a series x[T] (host), the heuristic the
  * paper uses to size the Theiler window (section on autocorrelation in real
  * data): the shortest lag L >= 1 at which the autocorrelation function has

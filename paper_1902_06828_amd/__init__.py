@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     cmi_ksg_surrogates,
     cmi_ksg_surrogates_rep,
     cmi_ksg_surrogates_dev,
+    cmi_ksg_surrogates_dev_noalloc,
     lib,
     mte_autocorr_decay_time,
     mte_chi2_sf,

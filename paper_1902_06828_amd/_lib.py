@@ -86,6 +86,7 @@ SIGNATURES = {
     "cmi_ksg_dev": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _P, _P],
     "cmi_ksg_surrogates_dev": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _U64, _U32, _P, _P],
     "cmi_ksg_surrogates_dev_ex": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _I, _U64, _U32, _P, _P],
+    "cmi_ksg_surrogates_dev_noalloc": [_P, _I, _P, _I, _P, _I, _I64, _I64, _I, _I, _U64, _U32, _P, _P],
     "mte_autocorr_decay_time": [_P, _I64, _I, _P],
     "mte_fdr_bh": [_P, _I, ctypes.c_double, _P],
     "mte_link_metrics": [_P, _P, _I, _P, _P],
@@ -246,10 +247,8 @@ def cmi_ksg_dev(X, Y, Z, k: int, out, stream=None) -> None:
     cmi_ksg_surrogates_dev(X, Y, Z, k, 0, 0, 0, out, stream)
 
 
-def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, stream=None,
-                           n: int | None = None, theiler: int = 0) -> None:
-    """Device-resident estimate and S surrogates into out[0..S] (float64 CUDA
-    tensor), asynchronous on `stream` (torch's current stream by default)."""
+def _dev_shape(X, Y, Z, S, out, n):
+    """Checks the device-resident arguments; returns (rows, ld)."""
     import torch
 
     def chk(t, name):
@@ -269,10 +268,30 @@ def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, s
         raise ValueError("X, Y and Z must share the leading dimension")
     if any(t is not None and t.shape[1] < rows for t in (X, Y, Z)) or rows > ld:
         raise ValueError("fewer columns than rows requested")
-    _check(lib().cmi_ksg_surrogates_dev_ex(
-        ctypes.c_void_p(X.data_ptr()), X.shape[0], ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
-        None if Z is None else ctypes.c_void_p(Z.data_ptr()), 0 if Z is None else Z.shape[0],
-        rows, ld, k, theiler, S, seed, cand, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return rows, ld
+
+
+def _dev_cols(X, Y, Z):
+    return (ctypes.c_void_p(X.data_ptr()), X.shape[0], ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
+            None if Z is None else ctypes.c_void_p(Z.data_ptr()), 0 if Z is None else Z.shape[0])
+
+
+def cmi_ksg_surrogates_dev(X, Y, Z, k: int, S: int, seed: int, cand: int, out, stream=None,
+                           n: int | None = None, theiler: int = 0) -> None:
+    """Device-resident estimate and S surrogates into out[0..S] (float64 CUDA
+    tensor), asynchronous on `stream` (torch's current stream by default)."""
+    rows, ld = _dev_shape(X, Y, Z, S, out, n)
+    _check(lib().cmi_ksg_surrogates_dev_ex(*_dev_cols(X, Y, Z), rows, ld, k, theiler, S, seed, cand,
+                                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+
+
+def cmi_ksg_surrogates_dev_noalloc(X, Y, Z, k: int, S: int, seed: int, cand: int, out, stream=None,
+                                   n: int | None = None) -> None:
+    """cmi_ksg_surrogates_dev with every scratch word in the library's static
+    device array (no allocation); needs mte_init first."""
+    rows, ld = _dev_shape(X, Y, Z, S, out, n)
+    _check(lib().cmi_ksg_surrogates_dev_noalloc(*_dev_cols(X, Y, Z), rows, ld, k, S, seed, cand,
+                                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
 
 
 def mte_permutation(seed: int, cand: int, s: int, n: int) -> np.ndarray:

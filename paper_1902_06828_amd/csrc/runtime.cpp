@@ -113,6 +113,8 @@ Ctx &ctx() {
     return c;
 }
 
+static int harm_locked(int64_t n);
+
 static int init_locked(int device, size_t budget) {
     Ctx &c = ctx();
     if (c.inited) {
@@ -139,6 +141,11 @@ static int init_locked(int device, size_t budget) {
     c.budget = budget ? budget : (size_t)(0.9 * (double)fr);
     MTE_HIP(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
     MTE_HIP(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
+    // set-up work of the allocation-free call: the harmonic table (2^20
+    // entries) and the address of its static scratch array on this device
+    int rc;
+    if ((rc = harm_locked(int64_t(1) << 20))) return rc;
+    if ((rc = noalloc_bind(device))) return rc;
     c.inited = true;
     return MTE_OK;
 }
@@ -164,9 +171,8 @@ double harmonic_host(int64_t n) {
     return h;
 }
 
-int ensure_harm(int64_t n) {
+static int harm_locked(int64_t n) {
     Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
     if (c.harm && n <= c.harm_n) return MTE_OK;
     int64_t cap = std::max<int64_t>(n, std::max<int64_t>(2 * c.harm_n, int64_t(1) << 20));
     std::vector<double> h((size_t)cap + 1);
@@ -179,6 +185,11 @@ int ensure_harm(int64_t n) {
     c.harm = d;
     c.harm_n = cap;
     return MTE_OK;
+}
+
+int ensure_harm(int64_t n) {
+    std::lock_guard<std::mutex> lk(ctx().mu);
+    return harm_locked(n);
 }
 
 const double *harm_table() { return ctx().harm; }
@@ -417,6 +428,18 @@ static int g_pref_for(const std::vector<JobSpec> &specs) {
     for (const auto &s : specs) e += s.n_est();
     const double avg = (double)e / (double)std::max<size_t>(1, specs.size());
     return avg >= 16 ? 8 : (avg >= 4 ? 4 : 1);
+}
+
+int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out) {
+    Ctx &c = ctx();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.tuned.find(shape_key(specs));
+        if (it != c.tuned.end()) { *out = it->second; return MTE_OK; }
+    }
+    out->variant = variant_for(specs, g_pref_for(specs));
+    out->rs_mult = 1;
+    return out->variant < 0 ? fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions") : MTE_OK;
 }
 
 int choose_tiles(const std::vector<JobSpec> &all_specs, hipStream_t s, bool tune, TileChoice *out) {
@@ -775,18 +798,17 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     return MTE_OK;
 }
 
-int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+int plan_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, PairPlan *plan) {
     Ctx &c = ctx();
     TileCfg cfg;
     if (!kernel_variant(tc.variant, &cfg)) return fail(MTE_EINVAL, "bad tile variant");
-    variant_ = tc.variant;
-    n_jobs_ = (int)specs.size();
+    PairPlan &P = *plan;
+    const int n_jobs = (int)specs.size();
     for (const auto &sp : specs)
         if (sp.k > cfg.kmax || sp.dx > cfg.dxm || sp.dy > cfg.dym || sp.dz > cfg.dzm)
             return fail(MTE_EINVAL, "job does not fit the tile configuration");
-    int rc;
     const int qt = kWaves * 64 * cfg.qp;
-    const int bpc = variant_blocks_per_cu(variant_);
+    const int bpc = variant_blocks_per_cu(tc.variant);
     const int64_t slots = (int64_t)c.n_cu * bpc;
     int64_t base_items = 0;
     for (const auto &sp : specs)
@@ -795,18 +817,17 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
     if (tc.rs_mult > 0 && base_items < 3 * slots) rs_base = (3 * slots + base_items - 1) / base_items;
     if (tc.rs_mult > 1) rs_base *= tc.rs_mult;
 
-    // layout
-    std::vector<Job> jobs(n_jobs_);
-    std::vector<int64_t> a_off(n_jobs_ + 1), b_off(n_jobs_ + 1), blk_off(n_jobs_ + 1);
-    size_t scratch_bytes = 0;
-    int64_t sync_words_total = 2;   // queue head + error flag
-    struct Off { size_t xp, chunk, part, eps, cnt; int64_t sync; };
-    std::vector<Off> offs(n_jobs_);
-    int64_t n_keys = 0;
-    a_off[0] = b_off[0] = blk_off[0] = 0;
-    for (int j = 0; j < n_jobs_; ++j) {
+    P.jobs.assign(n_jobs, Job{});
+    P.a_off.assign(n_jobs + 1, 0);
+    P.b_off.assign(n_jobs + 1, 0);
+    P.blk_off.assign(n_jobs + 1, 0);
+    P.offs.assign(n_jobs, PairPlan::Off{});
+    P.scratch_bytes = 0;
+    P.sync_words = 2;   // queue head + error flag
+    P.n_keys = 0;
+    for (int j = 0; j < n_jobs; ++j) {
         const JobSpec &sp = specs[j];
-        Job &J = jobs[j];
+        Job &J = P.jobs[j];
         std::memset(&J, 0, sizeof J);
         for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
         J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
@@ -824,50 +845,77 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
         J.rs = (int)rs;
         J.split_len = (int)split_len;
         const int64_t items = (int64_t)J.n_groups * J.n_tiles * J.rs;
-        a_off[j + 1] = a_off[j] + items;
-        b_off[j + 1] = b_off[j] + (J.rs > 1 ? items : 0);
-        blk_off[j + 1] = blk_off[j] + (int64_t)J.n_est * permute_blocks(sp.n, sp.reps);
-        J.a_off = a_off[j];
-        J.b_off = b_off[j];
+        P.a_off[j + 1] = P.a_off[j] + items;
+        P.b_off[j + 1] = P.b_off[j] + (J.rs > 1 ? items : 0);
+        P.blk_off[j + 1] = P.blk_off[j] + (int64_t)J.n_est * permute_blocks(sp.n, sp.reps);
+        J.a_off = P.a_off[j];
+        J.b_off = P.b_off[j];
         const int64_t nch = (sp.n + kChunk - 1) / kChunk;
-        Off &o = offs[j];
-        o.xp = scratch_bytes;
-        scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.n_est * sp.dx * sp.n, 256);
-        o.chunk = scratch_bytes;
-        scratch_bytes = align_up(scratch_bytes + sizeof(double) * (size_t)J.n_est * nch, 256);
+        PairPlan::Off &o = P.offs[j];
+        size_t &sb = P.scratch_bytes;
+        o.xp = sb;
+        sb = align_up(sb + sizeof(float) * (size_t)J.n_est * sp.dx * sp.n, 256);
+        o.chunk = sb;
+        sb = align_up(sb + sizeof(double) * (size_t)J.n_est * nch, 256);
         if (J.rs > 1) {
-            o.part = scratch_bytes;
-            scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.rs * J.n_est * sp.n * cfg.kmax, 256);
-            o.eps = scratch_bytes;
-            scratch_bytes = align_up(scratch_bytes + sizeof(float) * (size_t)J.n_est * sp.n, 256);
-            o.cnt = scratch_bytes;
-            scratch_bytes = align_up(scratch_bytes + sizeof(int32_t) * (size_t)J.rs * J.n_est * 3 * sp.n, 256);
+            o.part = sb;
+            sb = align_up(sb + sizeof(float) * (size_t)J.rs * J.n_est * sp.n * cfg.kmax, 256);
+            o.eps = sb;
+            sb = align_up(sb + sizeof(float) * (size_t)J.n_est * sp.n, 256);
+            o.cnt = sb;
+            sb = align_up(sb + sizeof(int32_t) * (size_t)J.rs * J.n_est * 3 * sp.n, 256);
         }
-        o.sync = sync_words_total;
-        sync_words_total += sync_words(J.n_groups, J.n_tiles);
-        sync_words_total = (sync_words_total + 63) / 64 * 64;
+        o.sync = P.sync_words;
+        P.sync_words += sync_words(J.n_groups, J.n_tiles);
+        P.sync_words = (P.sync_words + 63) / 64 * 64;
         J.out = sp.out;
         J.diag_eps = sp.diag_eps;
         J.diag_cnt = sp.diag_cnt;
-        n_keys += J.n_est;
+        P.n_keys += J.n_est;
     }
-    li_.items_a = a_off[n_jobs_];
-    li_.items_b = b_off[n_jobs_];
-    const int64_t total = li_.items_a + li_.items_b;
+    P.li.items_a = P.a_off[n_jobs];
+    P.li.items_b = P.b_off[n_jobs];
+    const int64_t total = P.li.items_a + P.li.items_b;
     if (total >= (int64_t)0x7fffffff) return fail(MTE_EINVAL, "batch too large");
-    li_.grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, slots));
-    permute_blocks_ = blk_off[n_jobs_];
-    sync_total_ = sync_words_total;
+    P.li.grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, slots));
+    P.permute_blocks = P.blk_off[n_jobs];
+    P.tbl_jobs = align_up(sizeof(Job) * n_jobs, 256);
+    P.tbl_keys = align_up(sizeof(EstKey) * (size_t)P.n_keys, 256);
+    P.tbl_offs = align_up(sizeof(int64_t) * 3 * (n_jobs + 1), 256);
+    return MTE_OK;
+}
 
-    if ((rc = scratch_.ensure(std::max<size_t>(scratch_bytes, 256)))) return rc;
+void bind_pairs(PairPlan &P, uint8_t *scratch, uint32_t *sync, EstKey *keys_dev) {
+    int64_t kpos = 0;
+    for (size_t j = 0; j < P.jobs.size(); ++j) {
+        Job &J = P.jobs[j];
+        const PairPlan::Off &o = P.offs[j];
+        J.xp = reinterpret_cast<float *>(scratch + o.xp);
+        J.chunk = reinterpret_cast<double *>(scratch + o.chunk);
+        if (J.rs > 1) {
+            J.part = reinterpret_cast<float *>(scratch + o.part);
+            J.eps = reinterpret_cast<float *>(scratch + o.eps);
+            J.cnt = reinterpret_cast<int32_t *>(scratch + o.cnt);
+        }
+        J.sync = sync + o.sync;
+        J.keys = keys_dev + kpos;
+        kpos += J.n_est;
+    }
+}
+
+int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+    PairPlan P;
+    int rc;
+    if ((rc = plan_pairs(specs, tc, &P))) return rc;
+    variant_ = tc.variant;
+    n_jobs_ = (int)specs.size();
+    li_ = P.li;
+    permute_blocks_ = P.permute_blocks;
+    sync_total_ = P.sync_words;
+    if ((rc = scratch_.ensure(std::max<size_t>(P.scratch_bytes, 256)))) return rc;
     if ((rc = sync_.ensure(sizeof(uint32_t) * (size_t)sync_total_))) return rc;
-    uint8_t *sb = scratch_.as<uint8_t>();
-    uint32_t *sy = sync_.as<uint32_t>();
-    work_ = sy;
-    const size_t tbl_jobs = align_up(sizeof(Job) * n_jobs_, 256);
-    const size_t tbl_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
-    const size_t tbl_offs = align_up(sizeof(int64_t) * 3 * (n_jobs_ + 1), 256);
-    const size_t tbl_bytes = tbl_jobs + tbl_keys + tbl_offs;
+    work_ = sync_.as<uint32_t>();
+    const size_t tbl_bytes = P.tbl_jobs + P.tbl_keys + P.tbl_offs;
     if ((rc = tables_.ensure(tbl_bytes))) return rc;
     // pinned staging, reused by this thread (the copy below completes before
     // prepare returns)
@@ -876,31 +924,20 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
     if ((rc = staging->ensure(tbl_bytes))) return rc;
     uint8_t *tb = tables_.as<uint8_t>();
     uint8_t *hs = static_cast<uint8_t *>(staging->p);
-    EstKey *keys_dev = reinterpret_cast<EstKey *>(tb + tbl_jobs);
-    EstKey *keys_host = reinterpret_cast<EstKey *>(hs + tbl_jobs);
+    bind_pairs(P, scratch_.as<uint8_t>(), work_, reinterpret_cast<EstKey *>(tb + P.tbl_jobs));
+    EstKey *keys_host = reinterpret_cast<EstKey *>(hs + P.tbl_jobs);
     int64_t kpos = 0;
-    for (int j = 0; j < n_jobs_; ++j) {
-        Job &J = jobs[j];
-        const Off &o = offs[j];
-        J.xp = reinterpret_cast<float *>(sb + o.xp);
-        J.chunk = reinterpret_cast<double *>(sb + o.chunk);
-        if (J.rs > 1) {
-            J.part = reinterpret_cast<float *>(sb + o.part);
-            J.eps = reinterpret_cast<float *>(sb + o.eps);
-            J.cnt = reinterpret_cast<int32_t *>(sb + o.cnt);
-        }
-        J.sync = sy + o.sync;
-        J.keys = keys_dev + kpos;
-        std::memcpy(keys_host + kpos, specs[j].keys.data(), sizeof(EstKey) * J.n_est);
-        kpos += J.n_est;
+    for (const JobSpec &sp : specs) {
+        std::memcpy(keys_host + kpos, sp.keys.data(), sizeof(EstKey) * sp.n_est());
+        kpos += sp.n_est();
     }
-    std::memcpy(hs, jobs.data(), sizeof(Job) * n_jobs_);
-    int64_t *offs_host = reinterpret_cast<int64_t *>(hs + tbl_jobs + tbl_keys);
-    std::memcpy(offs_host, a_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
-    std::memcpy(offs_host + (n_jobs_ + 1), b_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
-    std::memcpy(offs_host + 2 * (n_jobs_ + 1), blk_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    std::memcpy(hs, P.jobs.data(), sizeof(Job) * n_jobs_);
+    int64_t *offs_host = reinterpret_cast<int64_t *>(hs + P.tbl_jobs + P.tbl_keys);
+    std::memcpy(offs_host, P.a_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    std::memcpy(offs_host + (n_jobs_ + 1), P.b_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
+    std::memcpy(offs_host + 2 * (n_jobs_ + 1), P.blk_off.data(), sizeof(int64_t) * (n_jobs_ + 1));
     jobs_dev_ = reinterpret_cast<Job *>(tb);
-    a_off_ = reinterpret_cast<int64_t *>(tb + tbl_jobs + tbl_keys);
+    a_off_ = reinterpret_cast<int64_t *>(tb + P.tbl_jobs + P.tbl_keys);
     b_off_ = a_off_ + (n_jobs_ + 1);
     blk_off_ = b_off_ + (n_jobs_ + 1);
     MTE_HIP(hipMemcpyAsync(tb, hs, tbl_bytes, hipMemcpyHostToDevice, s));

@@ -190,6 +190,39 @@ int variant_for(const std::vector<JobSpec> &specs, int g_pref);
 // the first call for a shape when `tune` is set.
 int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, bool tune, TileChoice *out);
 
+// The tile choice for jobs run on the all-pairs kernel whatever path
+// assign_paths would give them: the autotuner's cached choice for the shape
+// when there is one, else the heuristic.  Allocates nothing.
+int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out);
+
+// Layout of the all-pairs part of a launch: the Job records (scratch,
+// counter and key pointers not yet set), the work-item and permute-block
+// offsets, each job's byte offsets within one scratch region and its first
+// counter word, and the sizes of the tables (jobs, keys, three offset
+// arrays, each rounded to 256 bytes).
+struct PairPlan {
+    std::vector<Job> jobs;
+    std::vector<int64_t> a_off, b_off, blk_off;
+    struct Off {
+        size_t xp = 0, chunk = 0, part = 0, eps = 0, cnt = 0;
+        int64_t sync = 0;
+    };
+    std::vector<Off> offs;
+    size_t scratch_bytes = 0;
+    int64_t sync_words = 0;           // including the 2 work words
+    int64_t n_keys = 0;
+    LaunchInfo li{};
+    int64_t permute_blocks = 0;
+    size_t tbl_jobs = 0, tbl_keys = 0, tbl_offs = 0;
+};
+int plan_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, PairPlan *plan);
+// Point every job's scratch, counters and keys into the given regions.
+void bind_pairs(PairPlan &plan, uint8_t *scratch, uint32_t *sync, EstKey *keys_dev);
+
+// Address of the allocation-free call's static scratch array on `device`
+// (bound once per device at initialisation; see noalloc.hip).
+int noalloc_bind(int device);
+
 // Run a batch to completion on an internal stream (used by the host-pointer
 // calls and the greedy driver).  Outputs land in the JobSpec device buffers.
 int run_blocking(const std::vector<JobSpec> &specs, hipStream_t s);
