@@ -123,6 +123,9 @@ struct ListSet {
 };
 
 constexpr int kBuildRows = 2;                // rows per build block when N <= 2^16
+constexpr int kLeanRows = 2;                 // rows per block of the compiled-dimension build
+// Compiled-dimension build: dz <= kBuildFixedDz Z columns and one Y column.
+constexpr int kBuildFixedDz = 12;
 constexpr int kBuildCopies = 1;              // histogram copies per row (spread LDS atomics)
 constexpr int kListStatWord = 16;
 constexpr int kListStatSlots = 64;            // spread so that the atomics do not queue on one address
@@ -141,6 +144,10 @@ struct ListLaunch {
     int64_t build_blocks;
     int build_qb;                 // rows per build block: kBuildRows (N <= 2^16) or 1
     int build_pack;               // 16-bit packed histograms (every set has N <= 2^16)
+    int build_dz;                 // > 0: every set has this many Z columns and one Y column
+                                  // (the build's compiled-dimension forms)
+    int build_kind;               // 0 generic dimensions (list_build_kernel); 1 compiled
+                                  // dimensions (list_build_dz_kernel)
     int stats;                    // non-zero: the scan accumulates its entry counts
     const int64_t *est_off;       // [n_jobs+1] prefix sums of n_est
     int n_jobs, n_sets;

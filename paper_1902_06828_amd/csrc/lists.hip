@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 #include "engine.h"
 #include "ksg_device.h"
@@ -404,6 +405,254 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
         else S.l2[i * S.s2 + kr + u] = LEnt2{sent, inf_f(), (int32_t)i};
         if (u == 0) {
             S.len[2 * i + w] = (int32_t)kr;
+            S.bound[2 * i + w] = bound;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ build, compiled dimensions
+// list_build_kernel for sets with DZ Z columns and one Y column, N < 2^16,
+// QB rows per block: two passes over the pairs as there, with straight-line
+// distance code and a counting pass without branches.  The counting pass
+// counts every row j < N, the query row itself included (its distances are
+// exactly 0, so it adds one to bin 0 of both lists), and sends the lanes past
+// the last row to bin 4095, the bin of NaN encodings, which no distance
+// reaches; afterwards the query row and the rows of its Theiler window are
+// taken out again and bin 4095 is cleared.  The selection takes both lists
+// of every row in one block scan: a bin's word holds both lists' counts, 16
+// bits each, and their sums stay below 2^16, so one packed prefix is both
+// lists' write cursors.  The write pass checks the window per pair.
+constexpr int kLR = 4;                  // reference rows per thread per step
+
+template <int DZ, int QB, int R>
+__device__ __forceinline__ void lean_dists(const float *zy, int n, const float (&q)[QB][DZ + 1],
+                                           const uint32_t (&boff)[R], float (&az)[QB][R], float (&ayz)[QB][R]) {
+    float v[DZ + 1][R];
+#pragma unroll
+    for (int c = 0; c < DZ + 1; ++c)
+#pragma unroll
+        for (int u = 0; u < R; ++u) v[c][u] = gload_b(zy + (size_t)c * n, boff[u]);
+#pragma unroll
+    for (int r = 0; r < QB; ++r)
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            float a = absdiff(q[r][0], v[0][u]);
+#pragma unroll
+            for (int c = 1; c < DZ; ++c) a = fmax_(a, absdiff(q[r][c], v[c][u]));
+            az[r][u] = a;
+            ayz[r][u] = fmax_(a, absdiff(q[r][DZ], v[DZ][u]));
+        }
+}
+
+template <int QB>
+struct LeanSmem {
+    alignas(16) uint32_t h[QB][kKeyBins];   // list 1 count | list 2 count << 16, then cursors
+    float q[QB][kBuildFixedDz + 1];
+    uint32_t wtot[QB][kBW];
+    uint32_t red[2 * QB][kBW];
+    int set;
+};
+
+template <int DZ, int QB>
+__global__ __launch_bounds__(kBT) void list_build_dz_kernel(const ListSet *__restrict__ sets, int n_sets,
+                                                            const int64_t *__restrict__ blk_off) {
+    __shared__ LeanSmem<QB> sm;
+    const int tid = tid_x(), lane = tid & 63, wave = tid >> 6;
+    const int64_t b = bid_x();
+    if (tid == 0) sm.set = find_job(blk_off, n_sets, b);
+    for (int x = tid; x < QB * kKeyBins; x += kBT) (&sm.h[0][0])[x] = 0u;
+    __syncthreads();
+    const ListSet &S = sets[sm.set];
+    const float *zy = S.zy;
+    const int n = S.n, tw = S.theiler;
+    const int i0 = (int)(b - blk_off[sm.set]) * QB;
+    const int nq = min(QB, n - i0);
+    for (int x = tid; x < QB * (DZ + 1); x += kBT) {
+        const int r = x / (DZ + 1), c = x - r * (DZ + 1);
+        sm.q[r][c] = zy[(size_t)c * n + min(i0 + r, n - 1)];
+    }
+    __syncthreads();
+    float q[QB][DZ + 1];
+#pragma unroll
+    for (int r = 0; r < QB; ++r)
+#pragma unroll
+        for (int c = 0; c < DZ + 1; ++c) q[r][c] = sm.q[r][c];
+    constexpr uint32_t kInc1 = 1u, kInc2 = 1u << 16, kSink = (uint32_t)kKeyBins - 1u;
+    const int step = kBT * kLR;
+    const int full = n / step * step;
+
+    // pass 1: counts of every row j < n
+    auto count_step = [&](int j0, bool tail) {
+        uint32_t boff[kLR], sink[kLR];
+#pragma unroll
+        for (int u = 0; u < kLR; ++u) {
+            const int j = j0 + u * kBT;
+            const bool in = !tail || j < n;
+            boff[u] = (uint32_t)(in ? j : i0) * 4u;
+            sink[u] = in ? 0u : kSink;
+        }
+        float az[QB][kLR], ayz[QB][kLR];
+        lean_dists<DZ, QB, kLR>(zy, n, q, boff, az, ayz);
+#pragma unroll
+        for (int r = 0; r < QB; ++r)
+#pragma unroll
+            for (int u = 0; u < kLR; ++u) {
+                const uint32_t k1 = key_of(ayz[r][u]) | sink[u], k2 = key_of(az[r][u]) | sink[u];
+                atomicAdd(&sm.h[r][k1], k1 == k2 ? kInc1 + kInc2 : kInc1);
+                if (k1 != k2) atomicAdd(&sm.h[r][k2], kInc2);
+            }
+    };
+    int j0 = tid;
+    for (; j0 < full; j0 += step) count_step(j0, false);
+    if (j0 < n) count_step(j0, true);
+    __syncthreads();
+    // take out the query rows and their windows (counted above), clear the sink
+    const int wn = 2 * tw + 1;
+    for (int x = tid; x < QB * wn; x += kBT) {
+        const int r = x / wn, j = i0 + r + (x % wn) - tw;
+        if (r >= nq || j < 0 || j >= n) continue;
+        float a = 0.f;
+#pragma unroll
+        for (int c = 0; c < DZ; ++c) a = fmax_(a, absdiff(sm.q[r][c], zy[(size_t)c * n + j]));
+        const float cyz = fmax_(a, absdiff(sm.q[r][DZ], zy[(size_t)DZ * n + j]));
+        atomicSub(&sm.h[r][key_of(cyz)], kInc1);
+        atomicSub(&sm.h[r][key_of(a)], kInc2);
+    }
+    __syncthreads();
+    if (tid < QB) sm.h[tid][kSink] = 0u;
+    __syncthreads();
+
+    // selection: per row, the packed exclusive prefix over the bins (thread t
+    // owns bins t*kPer .. t*kPer+kPer-1) becomes the cursors; a list keeps
+    // the bins whose inclusive count fits its capacity (a prefix, since the
+    // counts only grow)
+    const uint32_t m1 = (uint32_t)S.m1, m2 = (uint32_t)S.m2;
+    uint32_t kb[QB][2], kr[QB][2];
+    {
+        uint32_t loc[QB], run[QB];
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+            loc[r] = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) loc[r] += sm.h[r][tid * kPer + x];
+            run[r] = loc[r];
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+            for (int r = 0; r < QB; ++r) {
+                const uint32_t t = __shfl_up(run[r], off, 64);
+                if (lane >= off) run[r] += t;
+            }
+        if (lane == 63)
+#pragma unroll
+            for (int r = 0; r < QB; ++r) sm.wtot[r][wave] = run[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+            uint32_t before = 0;
+#pragma unroll
+            for (int w = 0; w < kBW; ++w) before += w < wave ? sm.wtot[r][w] : 0u;
+            run[r] += before - loc[r];         // exclusive start of this thread's bins
+            uint32_t nb = 0, nr = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) {
+                uint32_t *wd = &sm.h[r][tid * kPer + x];
+                const uint32_t v = *wd;
+                *wd = run[r];
+                run[r] += v;
+                // bins kept by list 1 (low half) and list 2 (high half)
+                if ((run[r] & 0xffffu) <= m1) { nb += 1u; nr += v & 0xffffu; }
+                if ((run[r] >> 16) <= m2) { nb += 1u << 16; nr += v & 0xffff0000u; }
+            }
+            nb = (uint32_t)wave_sum((int)nb);
+            nr = (uint32_t)wave_sum((int)nr);
+            if (lane == 0) {
+                sm.red[2 * r][wave] = nb;
+                sm.red[2 * r + 1][wave] = nr;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+            uint32_t nb = 0, nr = 0;
+#pragma unroll
+            for (int w = 0; w < kBW; ++w) {
+                nb += sm.red[2 * r][w];
+                nr += sm.red[2 * r + 1][w];
+            }
+            kb[r][0] = nb & 0xffffu;
+            kb[r][1] = nb >> 16;
+            kr[r][0] = nr & 0xffffu;
+            kr[r][1] = nr >> 16;
+        }
+    }
+
+    // pass 2: write the kept rows (bin 4095 never holds a row: kept bins are
+    // taken below it)
+    uint32_t keep1[QB], keep2[QB];
+    LEnt *out1[QB];
+    LEnt2 *out2[QB];
+#pragma unroll
+    for (int r = 0; r < QB; ++r) {
+        keep1[r] = min(kb[r][0], kSink);
+        keep2[r] = min(kb[r][1], kSink);
+        const int64_t i = min(i0 + r, n - 1);
+        out1[r] = S.l1 + i * S.s1;
+        out2[r] = S.l2 + i * S.s2;
+    }
+    const uint32_t w2 = 2u * (uint32_t)tw;
+    auto write_step = [&](int jb, bool tail) {
+        uint32_t boff[kLR];
+        int jj[kLR];
+#pragma unroll
+        for (int u = 0; u < kLR; ++u) {
+            jj[u] = jb + u * kBT;
+            boff[u] = (uint32_t)(!tail || jj[u] < n ? jj[u] : i0) * 4u;
+        }
+        float az[QB][kLR], ayz[QB][kLR];
+        lean_dists<DZ, QB, kLR>(zy, n, q, boff, az, ayz);
+#pragma unroll
+        for (int r = 0; r < QB; ++r)
+#pragma unroll
+            for (int u = 0; u < kLR; ++u) {
+                const int j = jj[u];
+                const bool ok = r < nq && (!tail || j < n) && (uint32_t)(j + (tw - i0 - r)) > w2;
+                const uint32_t k1 = key_of(ayz[r][u]), k2 = key_of(az[r][u]);
+                if (ok && k1 < keep1[r]) {
+                    const uint32_t pos = atomicAdd(&sm.h[r][k1], kInc1) & 0xffffu;
+                    if (pos < m1) gstore(out1[r], pos, LEnt{ayz[r][u], j});
+                }
+                if (ok && k2 < keep2[r]) {
+                    const uint32_t pos = atomicAdd(&sm.h[r][k2], kInc2) >> 16;
+                    if (pos < m2) gstore(out2[r], pos, LEnt2{az[r][u], ayz[r][u], j});
+                }
+            }
+    };
+    j0 = tid;
+    for (; j0 < full; j0 += step) write_step(j0, false);
+    if (j0 < n) write_step(j0, true);
+    // lengths, bounds and the sentinels (as in list_build_kernel; they lie
+    // past the kept entries, so no barrier is needed before them)
+    for (int x = tid; x < QB * 2 * kListPad; x += kBT) {
+        const int r = x / (2 * kListPad), w = (x / kListPad) & 1, u = x % kListPad;
+        if (r >= nq) continue;
+        const int64_t i = i0 + r;
+        const uint32_t total = (uint32_t)(n - 1 - min((int)i, tw) - min(n - 1 - (int)i, tw));
+        uint32_t kbw = 0, krw = 0;
+#pragma unroll
+        for (int rr = 0; rr < QB; ++rr)
+            if (rr == r) {
+                kbw = w == 0 ? kb[rr][0] : kb[rr][1];
+                krw = w == 0 ? kr[rr][0] : kr[rr][1];
+            }
+        const bool whole = krw == total || (kbw << kKeyShift) >= __float_as_uint(inf_f());
+        const float bound = whole ? inf_f() : __uint_as_float(kbw << kKeyShift);
+        const float sent = whole ? inf_f() : __uint_as_float((kbw << kKeyShift) + 1u);
+        if (w == 0) S.l1[i * S.s1 + krw + u] = LEnt{sent, (int32_t)i};
+        else S.l2[i * S.s2 + krw + u] = LEnt2{sent, inf_f(), (int32_t)i};
+        if (u == 0) {
+            S.len[2 * i + w] = (int32_t)krw;
             S.bound[2 * i + w] = bound;
         }
     }
@@ -1239,8 +1488,27 @@ int launch_list_order(const ListLaunch &L, void *stream) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int QB, int... D>
+void *lean_fn(int dz, std::integer_sequence<int, D...>) {
+    void *fns[] = {nullptr, reinterpret_cast<void *>(&list_build_dz_kernel<D + 1, QB>)...};
+    return dz >= 0 && dz <= (int)sizeof...(D) ? fns[dz] : nullptr;
+}
+
 int launch_list_build(const ListLaunch &L, void *stream) {
     if (L.build_blocks <= 0) return 0;
+    if (L.build_kind == 1) {
+        void *fn = L.build_qb == 4 ? lean_fn<4>(L.build_dz, std::make_integer_sequence<int, kBuildFixedDz>{})
+                                   : lean_fn<kBuildRows>(L.build_dz, std::make_integer_sequence<int, kBuildFixedDz>{});
+        if (!fn) return -1;
+        const ListSet *sets = L.sets;
+        int n_sets = L.n_sets;
+        const int64_t *off = L.build_off;
+        void *args[] = {(void *)&sets, (void *)&n_sets, (void *)&off};
+        return hipLaunchKernel(fn, dim3((unsigned)L.build_blocks), dim3(kBT), args, 0, (hipStream_t)stream) ==
+                       hipSuccess
+                   ? 0
+                   : -1;
+    }
     const dim3 grid((unsigned)L.build_blocks), block(kBT);
     if (L.build_pack && L.build_qb == kBuildRows)
         hipLaunchKernelGGL((list_build_kernel<kBuildRows, kBuildCopies, true>), grid, block, 0,

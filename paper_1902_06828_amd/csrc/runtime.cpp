@@ -715,9 +715,28 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
     const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
     // build blocks: kBuildRows rows each with packed 16-bit histograms when
-    // every set has N <= 2^16, one row each with 32-bit histograms otherwise
+    // every set has N <= 2^16, one row each with 32-bit histograms otherwise;
+    // the compiled-dimension form when every set has the same dz <=
+    // kBuildFixedDz, one Y column and N < 2^16 (kLeanRows rows per block)
     const bool pack = nmax_set <= 65536;
-    const int qb = pack ? kBuildRows : 1;
+    int build_dz = 0, build_kind = 0;
+    {
+        const char *bk = std::getenv("MTE_BUILD_KIND");
+        const int want = bk && *bk ? std::atoi(bk) : 1;
+        bool fixed = pack && want == 1;
+        for (int t = 0; t < n_sets; ++t) {
+            const JobSpec &sp = specs[set_rep[t]];
+            fixed = fixed && sp.dz == specs[set_rep[0]].dz && sp.dy == 1 && sp.n < 65536;
+        }
+        const int dz0 = specs[set_rep[0]].dz;
+        if (fixed && dz0 >= 1 && dz0 <= kBuildFixedDz) {
+            build_dz = dz0;
+            build_kind = 1;
+        }
+    }
+    const char *bq = std::getenv("MTE_BUILD_QB");
+    const int lean_qb = bq && *bq ? std::atoi(bq) : kLeanRows;
+    const int qb = build_kind == 1 ? lean_qb : (pack ? kBuildRows : 1);
     for (int t = 0; t < n_sets; ++t) build_off[t + 1] = build_off[t] + (row_off[t + 1] - row_off[t] + qb - 1) / qb;
     const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
     const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
@@ -776,6 +795,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.build_blocks = build_off[n_sets];
     L.build_qb = qb;
     L.build_pack = pack ? 1 : 0;
+    L.build_dz = build_dz;
+    L.build_kind = build_kind;
     L.stats = 0;
     L.n_jobs = n_ljobs_;
     L.n_sets = n_sets;

@@ -196,3 +196,31 @@ def test_list_path_overflowing_differences(monkeypatch, caps, n, dims, kind, som
     cmi, eps, *_ = check_against_oracle(X, Y, Z, 4, 8, seed=5, cand=1)
     if some_inf:
         assert np.isinf(eps).any() and np.isfinite(eps).any()
+
+
+@pytest.mark.parametrize("dims,n,w", [((1, 1, 1), 4500, 0), ((1, 1, 5), 6000, 0), ((2, 1, 7), 5001, 3),
+                                      ((1, 1, 12), 4097, 0), ((1, 1, 4), 9000, 2)])
+def test_build_forms_agree(monkeypatch, dims, n, w):
+    # the neighbour lists come from the generic two-pass build or, for one Y
+    # column and dz <= 12, from the compiled-dimension build with 2 or 4 rows
+    # per block (query rows counted in the first pass and taken out after it,
+    # Theiler windows included); every form must give the oracle's radii and
+    # counts bit for bit
+    X, Y, Z = synth.random_points(n, dims, seed=n + w, kind="normal")
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    out = {}
+    for kind, qb in (("0", "2"), ("1", "2"), ("1", "4")):
+        monkeypatch.setenv("MTE_BUILD_KIND", kind)
+        monkeypatch.setenv("MTE_BUILD_QB", qb)
+        say("build form", kind, qb, dims, n, "window", w)
+        out[(kind, qb)] = mte.cmi_ksg_diag(X, Y, Z, 4, 8, 3, 1, theiler=w)
+    ref = out[("0", "2")]
+    for key, o in out.items():
+        for a, b in zip(ref, o):
+            assert np.array_equal(a, b), key
+    from test_gpu_parity import oracle_estimates
+    rows = np.array([0, 1, n // 2, n - 2, n - 1])
+    for e, (_, re, ra, rb, rc) in enumerate(oracle_estimates(X, Y, Z, 4, 8, 3, 1, queries=rows, theiler=w)):
+        cmi, eps, cx, cy, cz = ref
+        assert np.array_equal(eps[e, rows], re) and np.array_equal(cx[e, rows], ra)
+        assert np.array_equal(cy[e, rows], rb) and np.array_equal(cz[e, rows], rc)

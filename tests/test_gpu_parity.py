@@ -30,13 +30,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_estimates(X, Y, Z, k, S, seed, cand, queries=None):
+def oracle_estimates(X, Y, Z, k, S, seed, cand, queries=None, theiler=0):
     """[(cmi or None, eps, nxz, nyz, nz)] for the estimate and its S surrogates."""
     n = X.shape[1]
     out = []
     for e in range(S + 1):
         Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(seed, cand, e - 1, n))
-        eps, a, b, c, v = cksg.eps_and_counts(Xe, Y, Z, k, queries=queries)
+        eps, a, b, c, v = cksg.eps_and_counts(Xe, Y, Z, k, queries=queries, theiler=theiler)
         out.append((v, eps, a, b, c))
     return out
 
