@@ -66,11 +66,12 @@ def scan_bytes(dx, entries):
     return knn * (8 + 4 * dx) + zl * (12 + 4 * dx)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its factor for a plain
-    copy of known size), or None when the summary covers another kernel or
-    the kernel source has changed since it was taken."""
+def counter_record(kernel):
+    """The committed rocprofv3 counter record of `kernel` (profiles/traffic.json:
+    HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by its
+    factor for a plain copy of known size, and VALU instructions per launch),
+    or None when it covers another kernel or the kernel sources have changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -85,10 +86,37 @@ def measured_traffic(kernel):
             return None
     if rec.get("sha256") != h.hexdigest() or kernel not in rec.get("kernels", {}):
         return None
-    return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+    return rec["kernels"][kernel]
 
 
-def cpu_baseline(X, Y, Z, budget_s=15.0):
+def measured_traffic(kernel):
+    rec = counter_record(kernel)
+    return rec["hbm_bytes_per_launch"] if rec else None
+
+
+def valu_issue_frac(kernel, kernel_ms):
+    """VALU lane slots the kernel's issued instructions occupy (64 per wave
+    instruction, from the counter record) per second, against 78.6 T."""
+    rec = counter_record(kernel)
+    if not rec or "valu_insts_per_launch" not in rec:
+        return None
+    return rec["valu_insts_per_launch"] * 64 / (kernel_ms * 1e-3) / (PEAK_TOPS * 1e12)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X, Y, Z, budget_s=15.0, single_s=6.0):
+    """The C oracle (plain brute force, OpenMP over query rows) on the host:
+    on all the threads OpenMP gives it over a bounded sample of the C2
+    estimates, then on one thread over the first estimates."""
     from oracle import cksg, ksg, perm
     threads = cksg.max_threads()
     t = time.perf_counter()
@@ -100,9 +128,122 @@ def cpu_baseline(X, Y, Z, budget_s=15.0):
         Xe = X if e == 0 else ksg.permute_rows(X, perm.permutation(SEED, 0, e - 1, X.shape[1]))
         cksg.cmi_ksg(Xe, Y, Z, K_NN)
     dt = time.perf_counter() - t
+    n1, t1 = 0, time.perf_counter()
+    while n1 < S + 1 and (n1 == 0 or time.perf_counter() - t1 < single_s):
+        Xe = X if n1 == 0 else ksg.permute_rows(X, perm.permutation(SEED, 0, n1 - 1, X.shape[1]))
+        cksg.cmi_ksg(Xe, Y, Z, K_NN, threads=1)
+        n1 += 1
+    dt1 = time.perf_counter() - t1
     return {"value": count / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} of the 201 C2 estimates (the estimate, then surrogates 0..{count - 2}), "
-                      f"brute-force C oracle, OpenMP over query rows"}
+                      f"brute-force C oracle, OpenMP over query rows",
+            "single_thread_evals_per_s": n1 / dt1, "single_thread_sample": f"the first {n1} C2 estimates",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def c1_leg(mte, torch, dev, reps=200):
+    """C1: one KSG estimate of the Gaussian triple (N = 1000, 1-D X, Y, Z,
+    partial correlation 0.6), latency per call: device-resident (its
+    launch replayed as a graph, results left on the device, stream
+    synchronised per call) and host arrays (copies in and out included)."""
+    import synth
+    X, Y, Z, true = synth.c1_gaussian(1000, 1)
+    d = [torch.from_numpy(a).to(dev) for a in (X, Y, Z)]
+    out = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        mte.cmi_ksg_dev(d[0], d[1], d[2], K_NN, out)
+    stream.synchronize()
+    lat = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        mte.cmi_ksg_dev(d[0], d[1], d[2], K_NN, out)
+        stream.synchronize()
+        lat.append(time.perf_counter() - t)
+    host = []
+    for _ in range(reps // 4):
+        t = time.perf_counter()
+        v = mte.cmi_ksg(X, Y, Z, K_NN)
+        host.append(time.perf_counter() - t)
+    return {"workload": "C1: one estimate, Gaussian triple, N=1000, D=3, k=4",
+            "estimate": v, "closed_form": true,
+            "device_call_p50_s": float(np.percentile(lat, 50)), "device_call_p99_s": float(np.percentile(lat, 99)),
+            "host_call_p50_s": float(np.percentile(host, 50))}
+
+
+def c3_leg(mte):
+    """C3: one target's whole greedy selection on the benchmark's 10-node VAR
+    (N = 10000, lags 1..5, S = 200, alpha = 0.05, k = 4): the target with
+    parents of lowest index, every other node a candidate; direct launches
+    (mte_select_sources) and through the request loop (mte_select_sources_sid)."""
+    import synth
+    series, links = synth.var_network(10, N_ROWS, seed=SEED)
+    target = min(i for (i, _, _, _) in links)
+    cands = [j for j in range(10) if j != target]
+    out = {"workload": "C3: greedy selection for one target, 10-node VAR, N=10000, S=200, lags 1..5",
+           "target": target, "true_parents": sorted({(j, l) for (i, j, l, _) in links if i == target})}
+    t = time.perf_counter()
+    res = mte.mte_select_sources(series, target, cands, max_lag_sources=5, alpha=0.05, S=S, seed=SEED)
+    wall = time.perf_counter() - t
+    out.update(direct_s=wall, estimates=res["n_estimates"], direct_evals_per_s=res["n_estimates"] / wall,
+               sources=[(n, l) for (n, l, _, _) in res["sources"]])
+    sid = mte.mte_series_register(series)
+    t = time.perf_counter()
+    res = mte.mte_select_sources_sid(sid, target, cands, max_lag_sources=5, alpha=0.05, S=S, seed=SEED)
+    wall = time.perf_counter() - t
+    mte.mte_series_release(sid)
+    out.update(served_s=wall, served_evals_per_s=res["n_estimates"] / wall)
+    return out
+
+
+def c5_leg(mte, budget=2 << 30, window=2000, p_nodes=100):
+    """C5: every target of a 100-node VAR (config generator, seed 5, N =
+    10000, S = 200, lags 1..5, alpha = 0.05) searched at once through the
+    request loop, each search in its own thread, under an HBM budget of 2 GiB:
+    evals/s, latency percentiles and admission figures over the first
+    `window` requests; then the series is cancelled and the searches end."""
+    import threading
+    import synth
+    series, _ = synth.var_network(p_nodes, N_ROWS, seed=5)
+    old = mte.mte_serve_get_stats()["budget_bytes"]
+    mte.mte_init(0, budget)
+    sid = mte.mte_series_register(series)
+    errors, done = [], []
+
+    def search(t):
+        try:
+            mte.mte_select_sources_sid(sid, t, [j for j in range(p_nodes) if j != t], max_lag_sources=5,
+                                       alpha=0.05, S=S, seed=SEED + t)
+            done.append(t)
+        except mte.MteError as e:
+            errors.append(e.code)
+
+    mte.mte_serve_get_stats(reset=True)
+    threads = [threading.Thread(target=search, args=(t,)) for t in range(p_nodes)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    while True:
+        st = mte.mte_serve_get_stats()
+        if st["completed"] >= window or not any(th.is_alive() for th in threads):
+            break
+        time.sleep(0.005)
+    wall = time.perf_counter() - t0
+    st = mte.mte_serve_get_stats(reset=True)
+    mte.mte_serve_cancel(sid)
+    for th in threads:
+        th.join()
+    mte.mte_series_release(sid)
+    mte.mte_init(0, old)
+    return {"workload": f"C5: all {p_nodes} targets of a {p_nodes}-node VAR concurrently through the request loop, "
+                        f"N=10000, S=200, HBM budget {budget >> 20} MiB, first {window} requests",
+            "window_s": wall, "requests": st["completed"], "estimates": st["estimates"],
+            "evals_per_s": st["estimates"] / wall, "p50_latency_s": st["p50_latency_s"],
+            "p99_latency_s": st["p99_latency_s"], "batches": st["batches"],
+            "mean_batch_requests": st["mean_batch_requests"], "peak_bytes_in_use": st["peak_bytes_in_use"],
+            "budget_bytes": st["budget_bytes"], "admissions_that_waited": st["waited"],
+            "rejected": st["rejected"], "searches_cancelled": errors.count(mte._lib.MTE_ECANCELED),
+            "searches_completed_in_window": len(done), "other_errors": [c for c in errors if c != mte._lib.MTE_ECANCELED]}
 
 
 def served(mte, torch, n_burst=48, n_poisson=96, load=0.8):
@@ -169,13 +310,12 @@ def network_leg(mte):
     S = 200, alpha = 0.05, FDR over omnibus p-values; wall time, estimates per
     second and the link statistics against the generating graph."""
     import synth
-    from oracle import network
     series, links = synth.var_network(10, N_ROWS, seed=SEED)
     t = time.perf_counter()
     adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, S=S, seed=SEED)
     wall = time.perf_counter() - t
     est = int(sum(s["n_estimates"] for s in summ))
-    m = mte.mte_link_metrics(adj, network.truth_adjacency(10, links))
+    m = mte.mte_link_metrics(adj, synth.truth_adjacency(10, links))
     return {"workload": "10-node VAR (config form), T=10000, all targets, S=200, alpha=0.05, BH-FDR 0.05",
             "wall_s": wall, "estimates": est, "evals_per_s": est / wall,
             "precision": m["precision"], "recall": m["recall"], "specificity": m["specificity"]}
@@ -193,7 +333,6 @@ def gauss_leg(mte, torch, dev):
     the library takes (D = 512, N = 10^6).  Gram flops: one fma (2 flops) per
     upper-triangle entry and row, D (D + 1) N."""
     import synth
-    from oracle import network
     series, links = synth.var_network(10, N_ROWS, seed=SEED)
     mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, estimator="gauss")
     t = time.perf_counter()
@@ -203,7 +342,7 @@ def gauss_leg(mte, torch, dev):
                                           estimator="gauss")
     wall = (time.perf_counter() - t) / reps
     est = int(sum(s["n_estimates"] for s in summ))
-    m = mte.mte_link_metrics(adj, network.truth_adjacency(10, links))
+    m = mte.mte_link_metrics(adj, synth.truth_adjacency(10, links))
     out = {"workload": "10-node VAR, T=10000, all targets, Gaussian estimator, analytic null, alpha=0.05, "
                        "BH-FDR 0.05",
            "wall_s": wall, "estimates": est, "precision": m["precision"], "recall": m["recall"],
@@ -242,6 +381,9 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--no-gauss", action="store_true")
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 1 GiB (256Mi float32 read + written) before the "
                          "timed region, as the reference for HBM byte counters")
@@ -310,18 +452,24 @@ def main():
     def roofline_of(stage):
         k_ms = stage_ms[stage]["ms_per_launch"]
         if stage == "scan":
-            # a gather/stream kernel: list entries and permuted X values it reads
+            # a gather kernel: HBM bytes from the counter record; the bytes
+            # its lanes request (list entries and permuted X values as issued,
+            # most served by L2) are reported beside them, not as the roof
             bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
-            work = scan_bytes(1, entries)
-            achieved = work / (k_ms * 1e-3) / 1e9
+            work = measured_traffic(stage)
+            achieved = work / (k_ms * 1e-3) / 1e9 if work else None
+            gather = scan_bytes(1, entries)
+            extra = {"gather_bytes_per_launch": gather, "gather_gb_per_s": gather / (k_ms * 1e-3) / 1e9}
         else:
             bound, unit, peak = "alu", "TOP/s", PEAK_TOPS
             work = algorithmic_ops(N_ROWS, 1, 1, 5, E) if stage == "all_pairs" else (
                 build_ops(N_ROWS, 1, 5) if stage == "build" else None)
             achieved = work / (k_ms * 1e-3) / 1e12 if work else None
+            extra = {}
         return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak if achieved else None, "traffic": measured_traffic(stage),
-                "kernel": stage, "kernel_ms": k_ms, "work_per_launch": work}
+                "kernel": stage, "kernel_ms": k_ms, "work_per_launch": work,
+                "valu_issue_frac": valu_issue_frac(stage, k_ms), **extra}
 
     # on the list path the permutation runs beside the build (a second stream),
     # so it is not on the step's critical path
@@ -396,11 +544,35 @@ def main():
             f"{gl['recall']:.2f}; gram " + ", ".join(f"D={g['D']} N={g['N']}: {g['kernel_ms']:.3f} ms "
                                                      f"{g['tflops']:.1f} TF/s" for g in gl["gram"]))
 
+    c1 = None
+    if not args.no_c1:
+        log("c1: single-estimate latency, N = 1000")
+        c1 = c1_leg(mte, torch, dev)
+        log(f"c1: device call p50 {c1['device_call_p50_s'] * 1e3:.3f} ms, host call p50 "
+            f"{c1['host_call_p50_s'] * 1e3:.3f} ms, estimate {c1['estimate']:.4f} (closed form "
+            f"{c1['closed_form']:.4f})")
+
+    c3 = None
+    if not args.no_c3:
+        log("c3: one target's greedy selection")
+        c3 = c3_leg(mte)
+        log(f"c3: {c3['direct_s']:.3f} s direct ({c3['direct_evals_per_s']:.0f} evals/s), {c3['served_s']:.3f} s "
+            f"served, {c3['estimates']} estimates, sources {c3['sources']} (true {c3['true_parents']})")
+
+    c5 = None
+    if not args.no_c5:
+        log("c5: 100 concurrent target searches under a 2 GiB budget")
+        c5 = c5_leg(mte)
+        log(f"c5: {c5['evals_per_s']:.0f} evals/s over {c5['requests']} requests, p50 "
+            f"{c5['p50_latency_s'] * 1e3:.1f} ms p99 {c5['p99_latency_s'] * 1e3:.1f} ms, peak "
+            f"{c5['peak_bytes_in_use'] >> 20} MiB, {c5['admissions_that_waited']} admissions waited")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: C oracle on a bounded sample")
         cpu = cpu_baseline(X, Y, Z)
-        log(f"cpu: {cpu['value']:.3f} evals/s on {cpu['cores']} threads")
+        log(f"cpu: {cpu['value']:.3f} evals/s on {cpu['cores']} threads, {cpu['single_thread_evals_per_s']:.3f} on "
+            f"one ({cpu['cpu_model']})")
 
     line = {
         "metric": METRIC,
@@ -432,6 +604,9 @@ def main():
         "served": srv,
         "network": net,
         "gauss": gl,
+        "c1": c1,
+        "c3": c3,
+        "c5": c5,
     }
     print(json.dumps(line), flush=True)
 

@@ -43,7 +43,8 @@ typedef enum {
     MTE_ENOMEM = -2,   /* device memory (or the HBM budget) is exhausted */
     MTE_EDEVICE = -3,  /* no usable GPU, a HIP call failed, or a kernel reported an error */
     MTE_ETIMEOUT = -4, /* mte_wait ran out of time; the request is still pending */
-    MTE_EBUSY = -5     /* the object is in use (e.g. a series with pending requests) */
+    MTE_EBUSY = -5,    /* the object is in use (e.g. a series with pending requests) */
+    MTE_ECANCELED = -6 /* the request's series was cancelled (mte_serve_cancel) */
 } mte_status;
 
 /* Message for the last failing call on this thread (never NULL). */
@@ -433,8 +434,18 @@ typedef struct {
     int theiler;              /* Theiler window (>= 0) */
 } mte_request;
 
-/* Queue a request without blocking; copies nodes and lags. */
+/* Queue a request without blocking; copies nodes and lags.  A request whose
+ * launch alone would exceed the HBM budget finishes with MTE_ENOMEM (reported
+ * by mte_wait); one that needs memory held by batches in flight waits at the
+ * queue front until they retire.  MTE_ECANCELED on a cancelled series. */
 int mte_submit(const mte_request *req, uint64_t *ticket_out);
+
+/* Cancel a series (the paper's run-time section runs one search per target
+ * concurrently; this stops all of them on one series): its queued requests
+ * finish with MTE_ECANCELED, new requests on it and on its z-scored copy are
+ * refused with MTE_ECANCELED, and batches already on the GPU complete.  A
+ * greedy search on it returns MTE_ECANCELED.  mte_series_release frees it. */
+int mte_serve_cancel(int32_t sid);
 
 /* Wait for a request: cmi_out gets the estimate, surr_out (may be NULL) the S
  * surrogates.  timeout_s < 0 waits forever.  MTE_ETIMEOUT leaves the ticket
@@ -448,6 +459,7 @@ typedef struct {
     double p50_latency_s, p99_latency_s, mean_batch_requests;
     int64_t peak_bytes_in_use;
     int64_t budget_bytes;
+    int64_t waited;           /* requests admitted after waiting at the queue front for memory */
 } mte_serve_stats;
 
 /* Statistics since the last reset (reset = 1 clears them after reading). */

@@ -67,11 +67,3 @@ def link_metrics(inferred, truth):
     div = lambda x, y: float(x) / y if y else float("nan")
     return {"tp": tp, "fp": fp, "tn": tn, "fn": fn, "precision": div(tp, tp + fp), "recall": div(tp, tp + fn),
             "specificity": div(tn, tn + fp), "fpr": div(fp, fp + tn)}
-
-
-def truth_adjacency(p_nodes: int, links):
-    """A[s][t] = 1 for every (target t, source s, lag, c) link of a generator."""
-    adj = np.zeros((p_nodes, p_nodes), dtype=np.uint8)
-    for (t, s, _lag, _c) in links:
-        adj[s, t] = 1
-    return adj

@@ -41,6 +41,7 @@ from ._lib import (  # noqa: F401
     mte_permutation_rep,
     mte_select_sources,
     mte_select_sources_sid,
+    mte_serve_cancel,
     mte_serve_get_stats,
     mte_series_register,
     mte_series_release,

@@ -15,9 +15,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmte.so")
 
-MTE_OK, MTE_EINVAL, MTE_ENOMEM, MTE_EDEVICE, MTE_ETIMEOUT, MTE_EBUSY = 0, -1, -2, -3, -4, -5
+MTE_OK, MTE_EINVAL, MTE_ENOMEM, MTE_EDEVICE, MTE_ETIMEOUT, MTE_EBUSY, MTE_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "MTE_OK", -1: "MTE_EINVAL", -2: "MTE_ENOMEM", -3: "MTE_EDEVICE", -4: "MTE_ETIMEOUT",
-          -5: "MTE_EBUSY"}
+          -5: "MTE_EBUSY", -6: "MTE_ECANCELED"}
 
 
 class MteError(RuntimeError):
@@ -63,7 +63,7 @@ class mte_serve_stats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("estimates", ctypes.c_int64),
                 ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("mean_batch_requests", ctypes.c_double), ("peak_bytes_in_use", ctypes.c_int64),
-                ("budget_bytes", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("waited", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -102,6 +102,7 @@ SIGNATURES = {
     "mte_submit": [_P, _P],
     "mte_wait": [_U64, _P, _P, _D],
     "mte_serve_get_stats": [_P, _I],
+    "mte_serve_cancel": [ctypes.c_int32],
     "mte_tile_configs": [_P, _I, _P],
     "mte_kernel_timing": [_I],
     "mte_kernel_timing_read": [_P, _P, _I],
@@ -421,6 +422,12 @@ def mte_wait(ticket: int, S: int = 0, timeout_s: float = -1.0):
     surr = np.empty(max(S, 0), np.float64)
     _check(lib().mte_wait(ticket, ctypes.byref(out), _ptr(surr) if S > 0 else None, timeout_s))
     return out.value, surr
+
+
+def mte_serve_cancel(sid: int) -> None:
+    """Cancel a series: its queued requests and any search on it end with
+    MTE_ECANCELED; batches on the GPU complete."""
+    _check(lib().mte_serve_cancel(sid))
 
 
 def mte_serve_get_stats(reset: bool = False) -> dict:

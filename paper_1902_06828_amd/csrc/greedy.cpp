@@ -218,7 +218,12 @@ public:
             q.cand = tid0 + (uint32_t)j;
             q.theiler = w_;
             int rc = mte_submit(&q, &tickets[(size_t)j]);
-            if (rc) return rc;
+            if (rc) {
+                // retire the requests already queued before returning
+                std::vector<double> junk((size_t)S_ + 1);
+                for (int t = 0; t < j; ++t) (void)mte_wait(tickets[(size_t)t], junk.data(), junk.data() + 1, -1.0);
+                return rc;
+            }
         }
         real->assign((size_t)n, 0.0);
         surr->assign((size_t)n * S_, 0.0);

@@ -545,7 +545,7 @@ static int check_spec(const JobSpec &sp) {
     return MTE_OK;
 }
 
-int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, size_t *measure) {
     if (specs.empty()) return fail(MTE_EINVAL, "empty batch");
     int rc;
     int64_t nmax = 0;
@@ -553,7 +553,8 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
         if ((rc = check_spec(sp))) return rc;
         nmax = std::max<int64_t>(nmax, sp.n);
     }
-    if ((rc = ensure_harm(nmax))) return rc;
+    if (measure) *measure = 0;
+    else if ((rc = ensure_harm(nmax))) return rc;
     std::vector<int> set_of;
     int n_sets = 0;
     assign_paths(specs, &set_of, &n_sets);
@@ -571,9 +572,9 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     for (const auto &sp : specs) n_est_total_ += sp.n_est();
     n_jobs_ = 0;
     variant_ = -1;
-    if (!pairs.empty() && (rc = prepare_pairs(pairs, tc, s))) return rc;
+    if (!pairs.empty() && (rc = prepare_pairs(pairs, tc, s, measure))) return rc;
     n_ljobs_ = 0;
-    if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, s))) return rc;
+    if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, s, measure))) return rc;
     return MTE_OK;
 }
 
@@ -590,16 +591,17 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
 constexpr double kListSetBytes = 4.0 * (1 << 30);
 
 static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
+    const double cap_bytes = kListSetBytes;
     if (dz == 0) {
         // no Z list; list 1 holds every row when it fits (an incomplete list
         // leaves the surrogates whose permuted x is an outlier undecided)
-        *m1 = (int)std::max<double>(1024.0, std::min<double>(n - 1.0, kListSetBytes / ((double)n * sizeof(LEnt))));
+        *m1 = (int)std::max<double>(1024.0, std::min<double>(n - 1.0, cap_bytes / ((double)n * sizeof(LEnt))));
         *m2 = 0;
     } else {
         const int e = dx + dy - dz;
         *m1 = e >= 2 ? 8192 : e == 1 ? 4096 : e == 0 ? 2048 : 1024;
         while (*m1 > 1024 && (double)n * (std::min(n - 1, *m1) * (double)sizeof(LEnt) +
-                                          std::min(n - 1, 2 * *m1) * (double)sizeof(LEnt2)) > kListSetBytes)
+                                          std::min(n - 1, 2 * *m1) * (double)sizeof(LEnt2)) > cap_bytes)
             *m1 /= 2;
         *m2 = 2 * *m1;
     }
@@ -614,7 +616,7 @@ static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
 }
 
 int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
-                         hipStream_t s) {
+                         hipStream_t s, size_t *measure) {
     Ctx &c = ctx();
     n_ljobs_ = (int)specs.size();
     std::vector<Job> jobs(n_ljobs_);
@@ -697,6 +699,16 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     }
     const size_t o_failq = bytes;
     bytes = align_up(bytes + sizeof(uint64_t) * (size_t)lane_off[n_ljobs_], 256);
+    // tables: jobs, sets, keys, offsets
+    const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
+    const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
+    const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
+    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
+    const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
+    if (measure) {
+        *measure += bytes + sizeof(uint32_t) * kListCounterWords + tbytes;
+        return MTE_OK;
+    }
     int rc;
     if ((rc = lscratch_.ensure(bytes))) return rc;
     if ((rc = lcounters_.ensure(sizeof(uint32_t) * kListCounterWords))) return rc;
@@ -710,10 +722,6 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.zy = reinterpret_cast<float *>(sb + o_zy[t]);
         S.order = o_order[t] ? reinterpret_cast<int32_t *>(sb + o_order[t]) : nullptr;
     }
-    // tables: jobs, sets, keys, offsets
-    const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
-    const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
-    const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
     // build blocks: kBuildRows rows each with packed 16-bit histograms when
     // every set has N <= 2^16, one row each with 32-bit histograms otherwise;
     // the compiled-dimension form when every set has the same dz <=
@@ -738,8 +746,6 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     const int lean_qb = bq && *bq ? std::atoi(bq) : kLeanRows;
     const int qb = build_kind == 1 ? lean_qb : (pack ? kBuildRows : 1);
     for (int t = 0; t < n_sets; ++t) build_off[t + 1] = build_off[t] + (row_off[t + 1] - row_off[t] + qb - 1) / qb;
-    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
-    const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
     if ((rc = ltables_.ensure(tbytes))) return rc;
     static thread_local HostBuf *staging = new HostBuf;
     if ((rc = staging->ensure(tbytes))) return rc;
@@ -924,10 +930,15 @@ void bind_pairs(PairPlan &P, uint8_t *scratch, uint32_t *sync, EstKey *keys_dev)
     }
 }
 
-int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s) {
+int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, size_t *measure) {
     PairPlan P;
     int rc;
     if ((rc = plan_pairs(specs, tc, &P))) return rc;
+    if (measure) {
+        *measure += std::max<size_t>(P.scratch_bytes, 256) + sizeof(uint32_t) * (size_t)P.sync_words + P.tbl_jobs +
+                    P.tbl_keys + P.tbl_offs;
+        return MTE_OK;
+    }
     variant_ = tc.variant;
     n_jobs_ = (int)specs.size();
     li_ = P.li;

@@ -106,8 +106,11 @@ class Batch {
 public:
     ~Batch();
     // Lay out and upload everything for `specs` with the given tile choice
-    // (the tile choice only concerns the jobs of the all-pairs kernel).
-    int prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s);
+    // (the tile choice only concerns the jobs of the all-pairs kernel).  With
+    // `measure` set, only compute the device bytes the launch would hold
+    // (device_bytes() after a real prepare) and allocate nothing.
+    int prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s,
+                size_t *measure = nullptr);
     // Enqueue the launch sequence on s (graph replay if captured).
     int enqueue(hipStream_t s, bool use_graph);
     // Non-zero when a kernel reported an error (reads device words; syncs s).
@@ -119,9 +122,9 @@ private:
     int capture();
     int launch_direct(hipStream_t s);
     int launch_all(hipStream_t s, bool timed);
-    int prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s);
+    int prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, size_t *measure);
     int prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
-                      hipStream_t s);
+                      hipStream_t s, size_t *measure);
     // neighbour-list part
     int n_ljobs_ = 0;
     ListLaunch ll_{};

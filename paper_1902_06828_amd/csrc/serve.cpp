@@ -8,8 +8,11 @@
 // briefly.  Requests that arrive while earlier batches are on the GPU are
 // admitted into the next batch as soon as a slot and memory free up; that
 // batch runs on another stream, so its blocks start as the earlier kernel's
-// persistent blocks drain.  Each estimate's result does not depend on the
-// batch it ran in (exact counts, fixed-order sums).
+// persistent blocks drain.  A batch is sized before anything is allocated;
+// the queue front waits for memory (rather than failing) while other batches
+// hold it, and admission is retried only once a batch has retired.  Each
+// estimate's result does not depend on the batch it ran in (exact counts,
+// fixed-order sums).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -33,6 +36,7 @@ struct Series {
     int64_t T = 0;
     int pending = 0;
     int32_t std_sid = -1;   // its per-node z-scored copy, made on first use
+    bool cancelled = false; // mte_serve_cancel: new requests are refused
 };
 
 struct Req {
@@ -41,6 +45,7 @@ struct Req {
     std::vector<int32_t> nodes, lags;
     Clock::time_point t_submit, t_done;
     int state = 0;                 // 0 queued, 1 on the GPU, 2 done
+    bool waited = false;           // held at the queue front for memory
     int status = MTE_OK;
     std::string error;
     std::vector<double> result;    // 1 + S
@@ -73,8 +78,10 @@ public:
     std::thread worker;
     bool running = false, stop = false;
     size_t bytes_in_flight = 0;
+    bool mem_blocked = false;      // the queue front waits for a batch to retire
     // statistics
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, estimates = 0, batch_reqs = 0;
+    int64_t waited = 0;            // requests admitted after waiting for memory
     std::vector<double> latencies;
     size_t peak_bytes = 0;
 
@@ -130,6 +137,7 @@ public:
             bytes_in_flight -= s.bytes;
             s.bytes = 0;
             s.busy = false;
+            mem_blocked = false;
             cv_done.notify_all();
         }
     }
@@ -154,51 +162,91 @@ public:
         return sp;
     }
 
+    // The queue front waits for memory: admission is retried after the
+    // next retirement.
+    void block_front() {
+        mem_blocked = true;
+        if (!queue.empty()) queue.front()->waited = true;
+    }
+
+    // Drop the first n queued requests with a status (mu held).
+    void fail_front(size_t n, int status, const char *msg) {
+        for (size_t i = 0; i < n; ++i) finish_req(queue[i], status, msg);
+        queue.erase(queue.begin(), queue.begin() + (long)n);
+        cv_done.notify_all();
+    }
+
+    // The requests that would share the front request's neighbour-list set
+    // (same series, rows, Y and Z columns and window) are moved up behind it,
+    // keeping their order, so that a batch holds few list sets (mu held).
+    // The front request itself never moves.
+    void group_front() {
+        if (queue.size() < 2) return;
+        const Req &f = *queue.front();
+        auto same_set = [&](const Req &q) {
+            if (q.r.sid != f.r.sid || q.r.N != f.r.N || q.r.t0 != f.r.t0 || q.r.dy != f.r.dy || q.r.dz != f.r.dz ||
+                q.r.theiler != f.r.theiler)
+                return false;
+            for (int c = 0; c < q.r.dy + q.r.dz; ++c)
+                if (q.nodes[q.r.dx + c] != f.nodes[f.r.dx + c] || q.lags[q.r.dx + c] != f.lags[f.r.dx + c])
+                    return false;
+            return true;
+        };
+        const size_t lim = std::min(queue.size(), 4 * kMaxBatchRequests);
+        std::stable_partition(queue.begin() + 1, queue.begin() + (long)lim,
+                              [&](const std::shared_ptr<Req> &q) { return same_set(*q); });
+    }
+
     // Form and launch one batch on slot s from the queue front (mu held).
+    // The batch is sized first (Batch::prepare in measuring mode); it is
+    // halved while it does not fit beside the batches in flight, a single
+    // request that exceeds the whole budget is rejected, and one that only
+    // needs memory held by others waits.  An allocation that fails while other
+    // batches hold memory makes the front wait as well.
     void admit(Slot &s) {
+        if (mem_blocked) return;
         const size_t budget = ctx().budget;
-        std::vector<std::shared_ptr<Req>> take;
-        size_t n_out = 0;
-        for (auto &q : queue) {
-            if (take.size() >= kMaxBatchRequests) break;
-            take.push_back(q);
-            n_out += (size_t)q->r.S + 1;
-        }
-        while (!take.empty()) {
+        group_front();
+        size_t take = std::min(queue.size(), kMaxBatchRequests);
+        while (take > 0) {
+            size_t n_out = 0;
+            for (size_t i = 0; i < take; ++i) n_out += (size_t)queue[i]->r.S + 1;
             int rc = s.out.ensure(sizeof(double) * n_out);
             if (rc == MTE_OK) rc = s.hout.ensure(sizeof(double) * n_out);
+            if (rc != MTE_OK) {
+                if (bytes_in_flight > 0) return block_front();
+                return fail_front(take, rc, "output buffer allocation failed");
+            }
             std::vector<JobSpec> specs;
             size_t pos = 0;
-            for (auto &q : take) {
-                specs.push_back(spec_for(*q, s.out.as<double>() + pos));
-                pos += (size_t)q->r.S + 1;
+            for (size_t i = 0; i < take; ++i) {
+                specs.push_back(spec_for(*queue[i], s.out.as<double>() + pos));
+                pos += (size_t)queue[i]->r.S + 1;
             }
-            auto b = std::make_unique<Batch>();
             TileChoice tc;
-            if (rc == MTE_OK) rc = choose_tiles(specs, s.stream, false, &tc);
-            if (rc == MTE_OK) rc = b->prepare(specs, tc, s.stream);
-            const size_t bytes = rc == MTE_OK ? b->device_bytes() + s.out.bytes : 0;
-            if (rc == MTE_OK && bytes_in_flight + bytes > budget) {
-                if (take.size() == 1) {
-                    if (bytes > budget) {
-                        // can never fit: reject
-                        finish_req(take[0], MTE_ENOMEM, "request exceeds the HBM budget");
-                        queue.pop_front();
-                        cv_done.notify_all();
-                    }
-                    return;   // wait for memory
+            size_t need = 0;
+            auto b = std::make_unique<Batch>();
+            rc = choose_tiles(specs, s.stream, false, &tc);
+            if (rc == MTE_OK) rc = b->prepare(specs, tc, s.stream, &need);
+            if (rc != MTE_OK) return fail_front(take, rc, "batch preparation failed");
+            const size_t bytes = need + sizeof(double) * n_out;
+            if (bytes_in_flight + bytes > budget) {
+                if (take > 1) {
+                    take /= 2;
+                    continue;
                 }
-                n_out = 0;
-                take.resize(take.size() / 2);
-                for (auto &q : take) n_out += (size_t)q->r.S + 1;
-                continue;
+                if (bytes > budget) return fail_front(1, MTE_ENOMEM, "request exceeds the HBM budget");
+                return block_front();
             }
-            if (rc != MTE_OK) {
-                for (auto &q : take) finish_req(q, rc, "batch preparation failed");
-                queue.erase(queue.begin(), queue.begin() + (long)take.size());
-                cv_done.notify_all();
-                return;
+            rc = b->prepare(specs, tc, s.stream);
+            if (rc == MTE_ENOMEM) {
+                if (bytes_in_flight > 0) return block_front();
+                if (take > 1) {
+                    take /= 2;
+                    continue;
+                }
             }
+            if (rc != MTE_OK) return fail_front(take, rc, "batch preparation failed");
             rc = b->enqueue(s.stream, false);
             if (rc == MTE_OK && hipMemcpyAsync(s.hout.p, s.out.p, sizeof(double) * n_out,
                                                hipMemcpyDeviceToHost, s.stream) != hipSuccess)
@@ -206,14 +254,14 @@ public:
             if (rc == MTE_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rc = MTE_EDEVICE;
             if (rc != MTE_OK) {
                 (void)hipStreamSynchronize(s.stream);
-                for (auto &q : take) finish_req(q, MTE_EDEVICE, "launch failed");
-                queue.erase(queue.begin(), queue.begin() + (long)take.size());
-                cv_done.notify_all();
-                return;
+                return fail_front(take, MTE_EDEVICE, "launch failed");
             }
-            for (auto &q : take) q->state = 1;
-            queue.erase(queue.begin(), queue.begin() + (long)take.size());
-            s.reqs = std::move(take);
+            s.reqs.assign(queue.begin(), queue.begin() + (long)take);
+            queue.erase(queue.begin(), queue.begin() + (long)take);
+            for (auto &q : s.reqs) {
+                q->state = 1;
+                if (q->waited) waited++;
+            }
             s.batch = std::move(b);
             s.bytes = bytes;
             s.busy = true;
@@ -223,6 +271,21 @@ public:
             batch_reqs += (int64_t)s.reqs.size();
             return;
         }
+    }
+
+    // Refuse new requests on the series and finish its queued ones with
+    // MTE_ECANCELED (mu held); batches on the GPU complete.
+    void cancel(int32_t sid) {
+        for (auto it = queue.begin(); it != queue.end();) {
+            if ((*it)->r.sid == sid) {
+                finish_req(*it, MTE_ECANCELED, "cancelled");
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if (!queue.empty() && mem_blocked) queue.front()->waited = true;
+        cv_done.notify_all();
     }
 
     void loop(int dev) {
@@ -321,6 +384,7 @@ int series_standardised(int32_t sid, int32_t *std_sid) {
         std::lock_guard<std::mutex> lk(sv.mu);
         auto it = sv.series.find(sid);
         if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+        if (it->second.cancelled) return fail(MTE_ECANCELED, "series %d was cancelled", sid);
         if (it->second.std_sid >= 0) {
             *std_sid = it->second.std_sid;
             return MTE_OK;
@@ -409,6 +473,7 @@ int mte_submit(const mte_request *req, uint64_t *ticket_out) {
     auto it = sv.series.find(req->sid);
     if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", req->sid);
     const Series &se = it->second;
+    if (se.cancelled) return fail(MTE_ECANCELED, "series %d was cancelled", req->sid);
     const int d = req->dx + req->dy + req->dz;
     for (int c = 0; c < d; ++c) {
         if (req->nodes[c] < 0 || req->nodes[c] >= se.P) return fail(MTE_EINVAL, "node out of range");
@@ -465,6 +530,7 @@ int mte_serve_get_stats(mte_serve_stats *out, int reset) {
     out->mean_batch_requests = sv.batches ? (double)sv.batch_reqs / (double)sv.batches : 0.0;
     out->peak_bytes_in_use = (int64_t)sv.peak_bytes;
     out->budget_bytes = (int64_t)ctx().budget;
+    out->waited = sv.waited;
     if (!sv.latencies.empty()) {
         std::vector<double> l = sv.latencies;
         std::sort(l.begin(), l.end());
@@ -476,9 +542,25 @@ int mte_serve_get_stats(mte_serve_stats *out, int reset) {
         out->p99_latency_s = pct(0.99);
     }
     if (reset) {
-        sv.submitted = sv.completed = sv.rejected = sv.batches = sv.estimates = sv.batch_reqs = 0;
+        sv.submitted = sv.completed = sv.rejected = sv.batches = sv.estimates = sv.batch_reqs = sv.waited = 0;
         sv.latencies.clear();
         sv.peak_bytes = sv.bytes_in_flight;
+    }
+    return MTE_OK;
+}
+
+int mte_serve_cancel(int32_t sid) {
+    Server &sv = server();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    auto it = sv.series.find(sid);
+    if (it == sv.series.end()) return fail(MTE_EINVAL, "unknown series %d", sid);
+    it->second.cancelled = true;
+    sv.cancel(sid);
+    const int32_t std_sid = it->second.std_sid;
+    auto st = std_sid >= 0 ? sv.series.find(std_sid) : sv.series.end();
+    if (st != sv.series.end()) {
+        st->second.cancelled = true;
+        sv.cancel(std_sid);
     }
     return MTE_OK;
 }

@@ -14,6 +14,7 @@ from .gen import (  # noqa: F401
     er_digraph,
     paper_var_network,
     random_points,
+    truth_adjacency,
     var_network,
     var_network_trials,
     window,

@@ -207,6 +207,14 @@ def clm_network(p_nodes: int, n_rows: int, seed: int, coupling: float = 0.5,
     return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32)), links
 
 
+def truth_adjacency(p_nodes: int, links):
+    """A[s][t] = 1 for every (target t, source s, lag, c) link of a generator."""
+    adj = np.zeros((p_nodes, p_nodes), dtype=np.uint8)
+    for (t, s, _lag, _c) in links:
+        adj[s, t] = 1
+    return adj
+
+
 # ---------------------------------------------------------------- slicing
 def window(series: np.ndarray, node: int, lag: int, n_rows: int, t0: int = MAX_LAG):
     """Rows t0..t0+n_rows-1 of one node's series delayed by ``lag`` samples

@@ -147,7 +147,7 @@ def test_greedy_analytic_matches_oracle(target):
 
 def test_network_gauss_recovers_var_and_matches_oracle():
     series, links = synth.var_network(10, 3000, seed=0)
-    truth = network.truth_adjacency(10, links)
+    truth = synth.truth_adjacency(10, links)
     say("network gauss, 10 nodes, T=3000")
     adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, estimator="gauss")
     ref_adj, ref_res, ref_keep = network.infer_network(series, alpha=0.05, alpha_fdr=0.05, null="analytic")

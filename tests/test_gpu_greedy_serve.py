@@ -133,3 +133,87 @@ def test_admission_rejects_oversized_request():
     finally:
         mte.mte_init(0, 64 << 30)
     mte.mte_series_release(sid)
+
+
+def _req(S, cand):
+    return dict(nodes=[1, 0, 0, 0, 0], lags=[1, 0, 1, 2, 3], dx=1, dy=1, dz=3, t0=5, n=3000, k=4, S=S, seed=3,
+                cand=cand)
+
+
+def test_admission_waits_for_memory():
+    # two requests that each fit the HBM budget but not together: the second
+    # waits at the queue front until the first retires, and both give the
+    # results they give alone
+    series, _ = synth.var_network(6, 3000, seed=13)
+    sid = mte.mte_series_register(series)
+    S = 60
+    mte.mte_serve_get_stats(reset=True)
+    alone = []
+    for c in (0, 1):
+        say("alone, request", c)
+        alone.append(mte.mte_wait(mte.mte_submit(sid, **_req(S, c)), S))
+    st = mte.mte_serve_get_stats(reset=True)
+    one, old_budget = st["peak_bytes_in_use"], st["budget_bytes"]
+    assert one > 0 and st["waited"] == 0
+    mte.mte_init(0, one + one // 2)
+    try:
+        say("together under a budget of 1.5 requests")
+        tickets = [mte.mte_submit(sid, **_req(S, c)) for c in (0, 1)]
+        mix = [mte.mte_wait(t, S) for t in tickets]
+        st = mte.mte_serve_get_stats(reset=True)
+    finally:
+        mte.mte_init(0, old_budget)
+    assert st["completed"] == 2 and st["rejected"] == 0 and st["waited"] >= 1
+    assert st["peak_bytes_in_use"] <= one + one // 2
+    for (v, s), (v1, s1) in zip(alone, mix):
+        assert v == v1 and np.array_equal(s, s1)
+    mte.mte_series_release(sid)
+
+
+def test_wait_timeout_keeps_the_ticket():
+    # a zero timeout on a 201-estimate request at N = 10^4 returns
+    # MTE_ETIMEOUT (nothing finishes that fast); the ticket stays valid and a
+    # second wait returns the result
+    series, _ = synth.var_network(4, 10000, seed=14)
+    sid = mte.mte_series_register(series)
+    q = dict(nodes=[1, 0, 0, 0], lags=[2, 0, 1, 2], dx=1, dy=1, dz=2, t0=5, n=10000, k=4, S=200, seed=5, cand=2)
+    say("wait with timeout 0")
+    t = mte.mte_submit(sid, **q)
+    with pytest.raises(mte.MteError) as e:
+        mte.mte_wait(t, 200, timeout_s=0.0)
+    assert e.value.code == mte._lib.MTE_ETIMEOUT
+    v, s = mte.mte_wait(t, 200)
+    cols = [series[nd, 5 - lg: 5 - lg + 10000] for nd, lg in zip(q["nodes"], q["lags"])]
+    f = lambda a: np.ascontiguousarray(np.array(a, np.float32))
+    cmi = mte.cmi_ksg_diag(f(cols[:1]), f(cols[1:2]), f(cols[2:]), 4, 200, 5, 2)[0]
+    assert cmi[0] == v and np.array_equal(cmi[1:], s)
+    mte.mte_series_release(sid)
+
+
+def test_cancel_stops_a_running_search():
+    import threading
+    import time
+    series, links = synth.var_network(10, 10000, seed=15)
+    sid = mte.mte_series_register(series)
+    target = min(i for (i, _, _, _) in links)
+    box = {}
+
+    def run():
+        try:
+            box["res"] = mte.mte_select_sources_sid(sid, target, [j for j in range(10) if j != target],
+                                                    max_lag_sources=5, S=200, seed=1)
+        except mte.MteError as err:
+            box["err"] = err
+
+    say("search, then cancel")
+    th = threading.Thread(target=run)
+    th.start()
+    time.sleep(0.02)
+    mte.mte_serve_cancel(sid)
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert "err" in box and box["err"].code == mte._lib.MTE_ECANCELED
+    with pytest.raises(mte.MteError) as e:
+        mte.mte_submit(sid, [1, 0], [1, 0], 1, 1, 0, 5, 300, k=4, S=0)
+    assert e.value.code == mte._lib.MTE_ECANCELED
+    mte.mte_series_release(sid)

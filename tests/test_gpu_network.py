@@ -44,7 +44,7 @@ def test_network_recovers_var_links():
     # S = 100 surrogates detect), with no false link.  The Gaussian estimator
     # finds all of them (tests/test_gpu_gauss.py).
     series, links = synth.var_network(10, 10000, seed=2)
-    truth = network.truth_adjacency(10, links)
+    truth = synth.truth_adjacency(10, links)
     say("network recovery, 10 nodes, links", int(truth.sum()))
     adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, S=100, seed=4)
     m = mte.mte_link_metrics(adj, truth)

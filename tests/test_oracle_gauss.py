@@ -88,5 +88,5 @@ def test_analytic_network_recovers_the_linear_var():
     from synth import gen
     s, links = gen.var_network(10, 3000, seed=0)
     adj, _, _ = network.infer_network(s, null="analytic")
-    m = network.link_metrics(adj, network.truth_adjacency(10, links))
+    m = network.link_metrics(adj, synth.truth_adjacency(10, links))
     assert m["precision"] == 1.0 and m["recall"] == 1.0

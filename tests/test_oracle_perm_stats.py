@@ -7,6 +7,7 @@ import math
 import numpy as np
 import pytest
 
+import synth
 from oracle import perm, stats
 
 
@@ -184,4 +185,4 @@ def test_link_metrics_hand_example():
     m = network.link_metrics(inf, truth)
     assert (m["tp"], m["fp"], m["tn"], m["fn"]) == (1, 1, 3, 1)
     assert m["precision"] == 0.5 and m["recall"] == 0.5 and m["specificity"] == 0.75 and m["fpr"] == 0.25
-    assert np.array_equal(network.truth_adjacency(3, [(1, 0, 2, 0.3), (2, 1, 1, 0.2)]), truth)
+    assert np.array_equal(synth.truth_adjacency(3, [(1, 0, 2, 0.3), (2, 1, 1, 0.2)]), truth)
