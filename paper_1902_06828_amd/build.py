@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmte.so")
 
-SOURCES = ["kernels_k4.hip", "kernels_k8.hip", "kernels_k16.hip", "kernels.hip", "lists.hip", "gauss.hip", "noalloc.hip", "runtime.cpp",
+SOURCES = ["kernels_k4.hip", "kernels_k8.hip", "kernels_k16.hip", "kernels.hip", "lists.hip", "gauss.hip", "noalloc.hip", "solo.hip", "runtime.cpp",
            "api.cpp", "greedy.cpp", "serve.cpp", "network.cpp", "gauss.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -188,6 +188,21 @@ struct LaunchInfo {
     int grid;                     // persistent blocks
 };
 
+// Compiled configurations of the all-pairs kernel for jobs with few estimates
+// (solo.hip): top-k capacity, Z, Y and X column capacities, estimates and
+// query rows per wave.
+struct SoloCfg {
+    int kmax, dzm, dym, dxm, g, qp;
+    int fz;                                  // >= 0: compiled dimensions (dz = fz, dy = dx = 1)
+};
+constexpr int kSoloMaxEstimates = 7;         // jobs with more take the persistent kernel
+int solo_variant_count();
+bool solo_variant(int i, SoloCfg *cfg);
+// One wave per (job, estimate group, query tile); wave_off: [n_jobs+1] prefix
+// sums of each job's waves.  Writes Job::pk (and the diagnostics).
+int launch_solo(int variant, const Job *jobs_dev, int n_jobs, const int64_t *wave_off, int64_t total_waves,
+                void *stream);
+
 // Host-side launch helpers implemented in kernels.hip.
 // jobs_dev: device copy of `n_jobs` Job records; work: 2 device words
 // (queue head, error flag) cleared by `launch_reset`.

@@ -356,13 +356,60 @@ int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, in
     return MTE_OK;
 }
 
+static int solo_kclass(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : 16); }
+
+// The few-estimate variant for a set of jobs: the right top-k class, the
+// smallest column capacities that fit, then the smallest estimate group that
+// holds a job's estimates (else the largest); -1 if none fits.
+static int solo_variant_for(const std::vector<JobSpec> &specs) {
+    int k = 0, dx = 0, dy = 0, dz = 0, e = 0;
+    for (const auto &sp : specs) {
+        k = std::max(k, sp.k);
+        dx = std::max(dx, sp.dx);
+        dy = std::max(dy, sp.dy);
+        dz = std::max(dz, sp.dz);
+        e = std::max(e, sp.n_est());
+    }
+    // compiled dimensions when every job has one estimate, k <= 4, one X and
+    // one Y column and the same dz
+    bool fixed = e == 1 && k <= 4 && dx == 1 && dy == 1;
+    for (const auto &sp : specs) fixed = fixed && sp.dz == dz;
+    int best = -1;
+    SoloCfg bc{};
+    auto score = [&](const SoloCfg &c) {
+        const int gpen = c.g >= e ? c.g - e : 1000 - c.g;
+        return std::make_tuple(c.fz < 0, c.dxm, c.dym, c.dzm, gpen);
+    };
+    for (int v = 0; v < solo_variant_count(); ++v) {
+        SoloCfg c;
+        solo_variant(v, &c);
+        if (c.fz >= 0 ? !(fixed && c.fz == dz) : c.dzm < dz) continue;
+        if (c.kmax != solo_kclass(k) || c.dxm < dx || c.dym < dy) continue;
+        if (best < 0 || score(c) < score(bc)) {
+            best = v;
+            bc = c;
+        }
+    }
+    return best;
+}
+
+bool takes_solo(const JobSpec &sp) {
+    const char *fm = std::getenv("MTE_FORCE_MODE");
+    if (fm && std::strcmp(fm, "brute") == 0) return false;
+    const bool forced = fm && std::strcmp(fm, "solo") == 0;
+    if (!forced && sp.n_est() > kSoloMaxEstimates) return false;
+    if (sp.n > kListMaxN) return false;
+    return solo_variant_for(std::vector<JobSpec>{sp}) >= 0;
+}
+
+// The jobs of the persistent all-pairs kernel (neither list path nor solo).
 static std::vector<JobSpec> pair_specs(const std::vector<JobSpec> &specs) {
     std::vector<int> set_of;
     int ns = 0;
     assign_paths(specs, &set_of, &ns);
     std::vector<JobSpec> out;
     for (size_t j = 0; j < specs.size(); ++j)
-        if (set_of[j] < 0) out.push_back(specs[j]);
+        if (set_of[j] < 0 && !takes_solo(specs[j])) out.push_back(specs[j]);
     return out;
 }
 
@@ -526,7 +573,8 @@ Batch::~Batch() {
 }
 
 size_t Batch::device_bytes() const {
-    return tables_.bytes + scratch_.bytes + sync_.bytes + ltables_.bytes + lscratch_.bytes + lcounters_.bytes;
+    return tables_.bytes + scratch_.bytes + sync_.bytes + ltables_.bytes + lscratch_.bytes + lcounters_.bytes +
+           stables_.bytes + sscratch_.bytes;
 }
 
 static int check_spec(const JobSpec &sp) {
@@ -558,14 +606,16 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     std::vector<int> set_of;
     int n_sets = 0;
     assign_paths(specs, &set_of, &n_sets);
-    std::vector<JobSpec> pairs, lists;
+    std::vector<JobSpec> pairs, lists, solo;
     std::vector<int> lset;
     for (size_t j = 0; j < specs.size(); ++j) {
-        if (set_of[j] < 0) {
-            pairs.push_back(specs[j]);
-        } else {
+        if (set_of[j] >= 0) {
             lists.push_back(specs[j]);
             lset.push_back(set_of[j]);
+        } else if (takes_solo(specs[j])) {
+            solo.push_back(specs[j]);
+        } else {
+            pairs.push_back(specs[j]);
         }
     }
     n_est_total_ = 0;
@@ -575,6 +625,8 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     if (!pairs.empty() && (rc = prepare_pairs(pairs, tc, s, measure))) return rc;
     n_ljobs_ = 0;
     if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, s, measure))) return rc;
+    n_sjobs_ = 0;
+    if (!solo.empty() && (rc = prepare_solo(solo, s, measure))) return rc;
     return MTE_OK;
 }
 
@@ -978,6 +1030,109 @@ int Batch::prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc
     return MTE_OK;
 }
 
+// Few-estimate jobs: per job the permuted X (estimate-major), the packed
+// counts and the chunk sums of the list path's reduction; tables: jobs, keys,
+// and the prefix sums of waves, permute blocks and estimates.
+int Batch::prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t *measure) {
+    const int v = solo_variant_for(specs);
+    if (v < 0) return fail(MTE_EINVAL, "no compiled few-estimate configuration fits these dimensions");
+    SoloCfg cfg;
+    solo_variant(v, &cfg);
+    const int nj = (int)specs.size();
+    std::vector<int64_t> wave_off(nj + 1, 0), blk_off(nj + 1, 0), est_off(nj + 1, 0);
+    struct Off { size_t xp, pk, chunk; };
+    std::vector<Off> offs(nj);
+    size_t bytes = 0;
+    int64_t n_keys = 0;
+    int max_chunks = 0;
+    // a job whose estimates are all the identity (no surrogates) reads its X
+    // columns in place and needs no permutation
+    auto all_ident = [](const JobSpec &sp) {
+        for (const EstKey &kk : sp.keys)
+            if (!kk.ident) return false;
+        return true;
+    };
+    for (int j = 0; j < nj; ++j) {
+        const JobSpec &sp = specs[j];
+        const int E = sp.n_est(), groups = (E + cfg.g - 1) / cfg.g, nch = (sp.n + kChunk - 1) / kChunk;
+        const bool ident = all_ident(sp);
+        wave_off[j + 1] = wave_off[j] + (int64_t)groups * ((sp.n + cfg.qp - 1) / cfg.qp);
+        blk_off[j + 1] = blk_off[j] + (ident ? 0 : (int64_t)E * permute_blocks(sp.n, sp.reps));
+        est_off[j + 1] = est_off[j] + E;
+        offs[j].xp = ident ? SIZE_MAX : bytes;
+        if (!ident) bytes = align_up(bytes + sizeof(float) * (size_t)E * sp.dx * sp.n, 256);
+        offs[j].pk = bytes;
+        bytes = align_up(bytes + sizeof(uint64_t) * (size_t)E * sp.n, 256);
+        offs[j].chunk = bytes;
+        bytes = align_up(bytes + sizeof(double) * (size_t)E * nch, 256);
+        n_keys += E;
+        max_chunks = std::max(max_chunks, nch);
+    }
+    const size_t t_jobs = align_up(sizeof(Job) * nj, 256);
+    const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
+    const size_t t_offs = align_up(sizeof(int64_t) * 3 * (size_t)(nj + 1), 256);
+    const size_t tbytes = t_jobs + t_keys + t_offs;
+    if (measure) {
+        *measure += std::max<size_t>(bytes, 256) + tbytes;
+        return MTE_OK;
+    }
+    int rc;
+    if ((rc = sscratch_.ensure(std::max<size_t>(bytes, 256)))) return rc;
+    if ((rc = stables_.ensure(tbytes))) return rc;
+    static thread_local HostBuf *staging = new HostBuf;
+    if ((rc = staging->ensure(tbytes))) return rc;
+    uint8_t *sb = sscratch_.as<uint8_t>(), *tb = stables_.as<uint8_t>();
+    uint8_t *hs = static_cast<uint8_t *>(staging->p);
+    EstKey *keys_dev = reinterpret_cast<EstKey *>(tb + t_jobs);
+    EstKey *keys_host = reinterpret_cast<EstKey *>(hs + t_jobs);
+    std::vector<Job> jobs(nj);
+    int64_t kpos = 0;
+    for (int j = 0; j < nj; ++j) {
+        const JobSpec &sp = specs[j];
+        Job &J = jobs[j];
+        std::memset(&J, 0, sizeof J);
+        for (int cc = 0; cc < sp.dx + sp.dy + sp.dz; ++cc) J.cols[cc] = sp.cols[cc];
+        J.n = sp.n; J.dx = sp.dx; J.dy = sp.dy; J.dz = sp.dz; J.k = sp.k;
+        J.n_est = sp.n_est();
+        J.rs = 1;
+        J.theiler = sp.theiler;
+        J.reps = sp.reps;
+        J.rep_shuffle = sp.rep_shuffle;
+        J.xp = offs[j].xp == SIZE_MAX ? nullptr : reinterpret_cast<float *>(sb + offs[j].xp);
+        J.pk = reinterpret_cast<uint64_t *>(sb + offs[j].pk);
+        J.chunk = reinterpret_cast<double *>(sb + offs[j].chunk);
+        J.out = sp.out;
+        J.diag_eps = sp.diag_eps;
+        J.diag_cnt = sp.diag_cnt;
+        J.keys = keys_dev + kpos;
+        std::memcpy(keys_host + kpos, sp.keys.data(), sizeof(EstKey) * J.n_est);
+        kpos += J.n_est;
+    }
+    std::memcpy(hs, jobs.data(), sizeof(Job) * nj);
+    int64_t *oh = reinterpret_cast<int64_t *>(hs + t_jobs + t_keys);
+    int64_t *od = reinterpret_cast<int64_t *>(tb + t_jobs + t_keys);
+    const size_t nj1 = (size_t)nj + 1;
+    std::memcpy(oh, wave_off.data(), sizeof(int64_t) * nj1);
+    std::memcpy(oh + nj1, blk_off.data(), sizeof(int64_t) * nj1);
+    std::memcpy(oh + 2 * nj1, est_off.data(), sizeof(int64_t) * nj1);
+    n_sjobs_ = nj;
+    svariant_ = v;
+    sjobs_dev_ = reinterpret_cast<Job *>(tb);
+    s_wave_off_ = od;
+    s_blk_off_ = od + nj1;
+    s_total_waves_ = wave_off[nj];
+    s_permute_blocks_ = blk_off[nj];
+    std::memset(&sl_, 0, sizeof sl_);
+    sl_.jobs = sjobs_dev_;
+    sl_.est_off = od + 2 * nj1;
+    sl_.n_jobs = nj;
+    sl_.ests = est_off[nj];
+    sl_.max_chunks = max_chunks;
+    MTE_HIP(hipMemcpyAsync(tb, hs, tbytes, hipMemcpyHostToDevice, s));
+    MTE_HIP(hipStreamSynchronize(s));
+    return MTE_OK;
+}
+
 // Blocks per CU of the permutation that runs beside the build: a few, so
 // that the build keeps nearly all its waves and the permutation's ALU work
 // fills the build's waits on LDS and L2.
@@ -1013,6 +1168,21 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (launch_main(variant_, jobs_dev_, n_jobs_, a_off_, b_off_, li_, work_, harm_table(), s))
             return hip_fail(hipGetLastError(), "main kernel launch");
         if ((rc = end(kStageAllPairs, s))) return rc;
+    }
+    if (n_sjobs_ > 0) {
+        if (s_permute_blocks_ > 0) {
+            if ((rc = begin(s))) return rc;
+            if (launch_permute(sjobs_dev_, n_sjobs_, s_permute_blocks_, s_blk_off_, s))
+                return hip_fail(hipGetLastError(), "permute launch");
+            if ((rc = end(kStagePermute, s))) return rc;
+        }
+        if ((rc = begin(s))) return rc;
+        if (launch_solo(svariant_, sjobs_dev_, n_sjobs_, s_wave_off_, s_total_waves_, s))
+            return hip_fail(hipGetLastError(), "few-estimate kernel launch");
+        if ((rc = end(kStageAllPairs, s))) return rc;
+        if ((rc = begin(s))) return rc;
+        if (launch_list_reduce(sl_, harm_table(), s)) return hip_fail(hipGetLastError(), "reduce launch");
+        if ((rc = end(kStageReduce, s))) return rc;
     }
     if (n_ljobs_ > 0) {
         const hipStream_t side = ctx().side_stream;

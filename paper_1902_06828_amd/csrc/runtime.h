@@ -96,6 +96,12 @@ struct TileChoice {
 // the same either way).
 constexpr int kListMinEstimates = 8;
 int assign_paths(const std::vector<JobSpec> &specs, std::vector<int> *set_of, int *n_sets);
+// Of the jobs that do not take the list path: those with at most
+// kSoloMaxEstimates estimates and N <= kListMaxN take the few-estimate
+// all-pairs kernel (solo.hip), the others the persistent kernel.
+// MTE_FORCE_MODE=brute sends every such job to the persistent kernel,
+// MTE_FORCE_MODE=solo every one the few-estimate kernel fits.
+bool takes_solo(const JobSpec &sp);
 
 // Timed stages (HIP events around each launch when timing is enabled).
 enum Stage { kStageAllPairs = 0, kStageBuild, kStageScan, kStageFallback, kStageReduce, kStagePermute,
@@ -125,6 +131,14 @@ private:
     int prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, size_t *measure);
     int prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
                       hipStream_t s, size_t *measure);
+    int prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t *measure);
+    // few-estimate part (solo kernel, then the list path's reduction)
+    int n_sjobs_ = 0, svariant_ = -1;
+    Job *sjobs_dev_ = nullptr;
+    int64_t *s_wave_off_ = nullptr, *s_blk_off_ = nullptr;
+    int64_t s_total_waves_ = 0, s_permute_blocks_ = 0;
+    ListLaunch sl_{};
+    DevBuf stables_, sscratch_;
     // neighbour-list part
     int n_ljobs_ = 0;
     ListLaunch ll_{};

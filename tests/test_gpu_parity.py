@@ -247,3 +247,27 @@ def test_full_size_c2_sampled():
     mte.cmi_ksg_surrogates_dev(*(torch.from_numpy(a).to(dev) for a in (X, Y, Z)), k, S, seed, 0, out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), cmi)
+
+
+@pytest.mark.parametrize("n,dims,k,S,w", [(1, (1, 1, 0), 1, 0, 0), (130, (1, 1, 3), 4, 0, 0), (1000, (2, 1, 5), 8, 2, 1),
+                                          (777, (1, 2, 0), 4, 6, 0), (3001, (1, 1, 12), 16, 1, 3),
+                                          (513, (3, 4, 20), 5, 3, 0), (2048, (1, 1, 5), 4, 30, 2)])
+def test_solo_equals_persistent(monkeypatch, n, dims, k, S, w):
+    # jobs with few estimates take the few-estimate kernel (a wave per query
+    # tile, lanes striding over the reference rows); forced onto it or onto
+    # the persistent kernel, every radius, count and estimate must agree, and
+    # agree with the oracle
+    n = max(n, k + 1 + 2 * w)
+    X, Y, Z = synth.random_points(n, dims, seed=n + S, kind="grid" if S == 2 else "normal")
+    out = {}
+    for mode in ("solo", "brute"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("solo vs persistent", n, dims, k, S, w, mode)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, k, S, 4, 2, theiler=w)
+    for a, b in zip(out["solo"], out["brute"]):
+        assert np.array_equal(a, b)
+    cmi, eps, cx, cy, cz = out["solo"]
+    for e, (v, re, ra, rb, rc) in enumerate(oracle_estimates(X, Y, Z, k, min(S, 3), 4, 2, theiler=w)):
+        assert np.array_equal(eps[e], re) and np.array_equal(cx[e], ra)
+        assert np.array_equal(cy[e], rb) and np.array_equal(cz[e], rc)
+        assert abs(cmi[e] - v) <= TOL
