@@ -10,16 +10,33 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ksg_oracle.c")
-LIB = os.path.join(HERE, "libksg_oracle.so")
+# ORACLE_LIBRARY selects the sanitizer build (libksg_oracle_san.so)
+LIB = os.environ.get("ORACLE_LIBRARY") or os.path.join(HERE, "libksg_oracle.so")
+LIB_SAN = os.path.join(HERE, "libksg_oracle_san.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
 
 
 def build() -> str:
     """Compile the C oracle (plain gcc, no fast-math, no FP contraction)."""
-    tmp = LIB + ".tmp"
+    out = os.path.join(HERE, "libksg_oracle.so")
+    tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                            "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build_sanitized() -> str:
+    """The same oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (clang, whose runtime the sanitized library build also uses)."""
+    omp = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(CLANG))), "lib")
+    tmp = LIB_SAN + ".tmp"
+    subprocess.check_call([CLANG, "-O1", "-g", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-shared", "-fPIC", "-o", tmp, SRC, "-lm",
+                           "-L" + omp, "-Wl,-rpath," + omp])
+    os.replace(tmp, LIB_SAN)
+    return LIB_SAN
 
 
 _lib = None
@@ -28,7 +45,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if LIB == os.path.join(HERE, "libksg_oracle.so") and (
+                not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
         L = ctypes.CDLL(LIB)
         f = L.oracle_ksg

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmte.so")
+# MTE_LIBRARY selects another build of the same library (the host-code
+# sanitizer build, libmte_san.so, whose runtime must be preloaded)
+LIB_PATH = os.environ.get("MTE_LIBRARY") or os.path.join(HERE, "libmte.so")
 
 MTE_OK, MTE_EINVAL, MTE_ENOMEM, MTE_EDEVICE, MTE_ETIMEOUT, MTE_EBUSY, MTE_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "MTE_OK", -1: "MTE_EINVAL", -2: "MTE_ENOMEM", -3: "MTE_EDEVICE", -4: "MTE_ETIMEOUT",

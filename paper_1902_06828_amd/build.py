@@ -62,6 +62,67 @@ def hip_runtime() -> str:
     return "/opt/rocm/lib/libamdhip64.so"
 
 
+# Host-code sanitizer build: the host C++ sources (and the host side of the
+# allocation-free entry point) with AddressSanitizer and UndefinedBehavior-
+# Sanitizer, linked with the same device objects into libmte_san.so.  It is
+# loaded through MTE_LIBRARY with the sanitizer runtime preloaded
+# (sanitizer_env()); device code is never instrumented.
+LIB_SAN = os.path.join(PKG, "libmte_san.so")
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+SAN_SOURCES = [s for s in SOURCES if s.endswith(".cpp")] + ["noalloc.hip"]
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime to preload into a process that
+    loads a sanitized library."""
+    r = subprocess.run([CLANGXX, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
+def sanitizer_env(env=None) -> dict:
+    """Environment for a Python process that loads libmte_san.so."""
+    e = dict(os.environ if env is None else env)
+    e["MTE_LIBRARY"] = LIB_SAN
+    # the sanitizer runtime must come first; anything already preloaded stays
+    e["LD_PRELOAD"] = ":".join(x for x in (asan_runtime(), e.get("LD_PRELOAD", "")) if x)
+    e["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1:abort_on_error=0"
+    e["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    return e
+
+
+def _compile_san(src: str) -> str:
+    d = os.path.join(BUILD, "san")
+    obj = os.path.join(d, os.path.basename(src) + ".o")
+    if src.endswith(".hip"):
+        flags = DEVICE + [x for f in SAN for x in ("-Xarch_host", f)]
+    else:
+        flags = HOST + SAN
+    cmd = [HIPCC] + COMMON + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libmte_san.so (after build(): the device objects come from it)."""
+    os.makedirs(os.path.join(BUILD, "san"), exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SAN_SOURCES))) as ex:
+        san = dict(zip(SAN_SOURCES, ex.map(_compile_san, SAN_SOURCES)))
+    objs = [san.get(s, os.path.join(BUILD, os.path.basename(s) + ".o")) for s in SOURCES]
+    tmp = LIB_SAN + ".tmp"
+    rt = hip_runtime()
+    cmd = [CLANGXX, "-shared", "-fPIC", "-fsanitize=address,undefined", "-o", tmp] + objs + [
+        rt, "-Wl,-rpath," + os.path.dirname(rt), "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB_SAN)
+    if verbose:
+        print("built", LIB_SAN)
+    return LIB_SAN
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
@@ -82,4 +143,6 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
     sys.exit(0)
