@@ -412,6 +412,10 @@ int mte_link_metrics(const uint8_t *inferred, const uint8_t *truth, int P, int64
  * I(X;Y|Z) over lag-shifted windows of a resident series); requests are
  * admitted while the in-flight limit and the HBM budget allow, batched with
  * whatever else is pending, and run concurrently with earlier batches.
+ * At most three batches are in flight, each on its own stream; the
+ * environment variable MTE_SERVE_SLOTS=1|2|3, read when the loop starts,
+ * lowers that limit (1 runs the batches one after another, for attributing
+ * time to kernels); results do not depend on it.
  * ------------------------------------------------------------------------ */
 
 /* Upload data [P][T] (host, row-major) and keep it resident.  *sid_out >= 0. */

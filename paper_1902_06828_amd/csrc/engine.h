@@ -75,6 +75,14 @@ struct Job {
     // list path: each (row, estimate)'s counts in one word,
     // n_xz | n_yz << kPackBits | n_z << 2 kPackBits ([n_est][n])
     uint64_t *pk;
+    // list path with one Z column (rank counts, see ListSet::zs): the set's
+    // rank of each row, the permuted X in rank order, estimate-major
+    // (xr[e][c][r] = X_c[pi_e(zord[r])], [n_est][dx][n]), and each pair's
+    // radius from the k-NN scan (er[e][i], -1 for a pair left to the
+    // all-rows redo); null otherwise
+    const int32_t *zrank;
+    float *xr;
+    float *er;
 };
 
 // Counts of the list path are packed kPackBits to a field: N <= kListMaxN.
@@ -120,7 +128,20 @@ struct ListSet {
     LEnt2 *l2;                    // [n][s2]  Z list
     int32_t *len;                 // [n][2]
     float *bound;                 // [n][2]
+    // One Z column and n <= kRankMaxN: the rows sorted by z, so that the rows
+    // within a radius of a row's z are one range of ranks (float subtraction
+    // is monotone in its first operand).  zs[r] the r-th smallest z, zord[r]
+    // its row, zrank the inverse, yr[c][r] = Y_c[zord[r]].  The counts of
+    // such a set's jobs come from these ranges, not from the Z list (whose
+    // capacity is then kRankListCap).  Null otherwise.
+    float *zs;
+    int32_t *zord;
+    int32_t *zrank;
+    float *yr;
 };
+
+constexpr int kRankMaxN = 32768;              // rank counts: rows ranked by O(n^2) compares
+constexpr int kRankListCap = 8;               // Z-list capacity of a set counted by ranks
 
 constexpr int kBuildRows = 2;                // rows per build block when N <= 2^16
 constexpr int kLeanRows = 2;                 // rows per block of the compiled-dimension build
@@ -162,6 +183,11 @@ struct ListLaunch {
     int fb_grid;                  // blocks of the fallback kernel
     int max_chunks;               // largest ceil(n / kChunk) of the jobs (reduction grid)
     int sortx;                    // some job has no Z: sort the X columns (Job::xs)
+    int rank_sets;                // sets counted by ranks (ListSet::zs)
+    int64_t rank_waves;           // rank-count waves: sum over those sets' jobs of
+                                  // n_est * ceil(n / 64)
+    const int64_t *rank_off;      // [n_jobs+1] prefix sums of each job's rank-count waves
+    int max_rank_n;               // largest n of a set counted by ranks
 };
 
 // Counter words of one job (all zero before a launch):
@@ -224,6 +250,8 @@ int launch_list_order(const ListLaunch &L, void *stream);  // the scan's row ord
 int launch_list_build(const ListLaunch &L, void *stream);
 int launch_list_sortx(const ListLaunch &L, void *stream);
 int launch_list_scan(const ListLaunch &L, void *stream);
+int launch_list_rank_sort(const ListLaunch &L, void *stream);   // ranks of the one-Z-column sets
+int launch_list_rank_count(const ListLaunch &L, void *stream);  // their jobs' counts
 int launch_list_fallback(const ListLaunch &L, void *stream);
 int launch_list_reduce(const ListLaunch &L, const double *harm, void *stream);
 

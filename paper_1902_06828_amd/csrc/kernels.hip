@@ -107,10 +107,12 @@ __global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jo
             x = (int64_t)s_src_rep * nr + t;
         else
             x = base + swap_or_not((uint32_t)t, dn, rounds, s_rk, s_k);
+        const int64_t ri = J.xr ? (int64_t)min(max(J.zrank[i], 0), J.n - 1) : 0;
         for (int c = 0; c < J.dx; ++c) {
             const float v = J.cols[c][x];
             if (J.xt) J.xt[((int64_t)c * J.n + i) * J.n_est + e] = v;
             J.xp[((int64_t)e * J.dx + c) * J.n + i] = v;
+            if (J.xr) J.xr[((int64_t)e * J.dx + c) * J.n + ri] = v;
         }
     }
     __syncthreads();   // the next item rewrites the key schedule

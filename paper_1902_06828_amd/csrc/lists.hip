@@ -1081,8 +1081,11 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     const int len2 = S.len[2 * (int64_t)i + 1];
     const bool noz = J.dz == 0;
     const bool knn_decided = decided;
-    act = live && decided && !noz;
-    decided = false;
+    // a job of a set counted by ranks takes its counts from the rank-count
+    // kernel: this kernel hands it the radius (or the pair to the redo)
+    const bool ranked = J.er != nullptr;
+    act = live && decided && !noz && !ranked;
+    decided = ranked && knn_decided;
     int m2 = 0;
     {
         LEnt2 cur[kU];
@@ -1192,10 +1195,13 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
         decided = true;
     }
     if (live) {
+        if (ranked) {
+            J.er[(int64_t)e * n + i] = decided ? eps : -1.0f;
+        }
         if (!decided) {
             const uint32_t pos = atomicAdd(&L.counters[0], 1u);
             L.failq[pos] = ((uint64_t)jb << 40) | ((uint64_t)i * J.n_est + e);
-        } else {
+        } else if (!ranked) {
             J.pk[(int64_t)e * n + i] = pack_counts(cxz, cyz, cz);
             if (J.eps) J.eps[(int64_t)e * n + i] = eps;
             if (J.cnt) {
@@ -1211,6 +1217,167 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
             atomicAdd(&st[0], (unsigned long long)seen1);
             atomicAdd(&st[1], (unsigned long long)seen2);
         }
+    }
+}
+
+// ------------------------------------------------------------------ ranks
+// Sets with one Z column: the rows ranked by z (ties by row index).  A block
+// takes 64 rows; its four waves count, for those rows, the rows before them
+// in a quarter of the set each (z staged in LDS), and the four partial
+// ranks are added.
+constexpr int kRankThreads = 256;
+constexpr int kRankRows = 64;
+
+__global__ __launch_bounds__(kRankThreads) void list_rank_sort_kernel(const ListLaunch L) {
+    const ListSet &S = L.sets[__builtin_amdgcn_workgroup_id_y()];
+    if (!S.zs) return;
+    const int n = S.n;
+    const int i0 = (int)bid_x() * kRankRows;
+    if (i0 >= n) return;
+    const int tid = tid_x(), lane = tid & 63, part = tid >> 6;
+    const float *z = S.cols[S.dy];
+    __shared__ float t[kRankThreads];
+    __shared__ int partial[kRankThreads / 64][kRankRows];
+    const int i = i0 + lane;
+    const float zi = i < n ? z[i] : 0.f;
+    const int span = (n + 3) / 4;
+    const int j_lo = part * span, j_hi = min(n, j_lo + span);
+    int r = 0;
+    // every thread takes part in the staging, so the loop bounds are
+    // those of the longest part
+    for (int j0 = 0; j0 < span; j0 += 64) {
+        __syncthreads();
+        const int jj = j_lo + j0 + lane;
+        t[tid] = jj < j_hi ? z[jj] : 0.f;
+        __syncthreads();
+        const int m = min(64, j_hi - (j_lo + j0));
+        for (int u = 0; u < m; ++u) {
+            const float v = t[part * 64 + u];
+            const int j = j_lo + j0 + u;
+            r += (v < zi) | ((v == zi) & (j < i));
+        }
+    }
+    partial[part][lane] = r;
+    __syncthreads();
+    if (part == 0 && i < n) {
+        const int rank = partial[0][lane] + partial[1][lane] + partial[2][lane] + partial[3][lane];
+        S.zrank[i] = rank;
+        S.zord[rank] = i;
+        S.zs[rank] = zi;
+        S.yr[rank] = S.cols[0][i];
+    }
+}
+
+// Counts of the pairs of a set with one Z column.  The rows within the
+// radius of row i in z are the ranks [lo, hi) with fl(zs[r] - z_i) > -eps
+// and fl(zs[r] - z_i) < eps (two binary searches), so n_z = hi - lo, and
+// n_yz, n_xz are the rows of that range within eps in y, in x: a wave takes
+// 64 pairs (64 ranks, one estimate), finds their ranges lane by lane, then
+// counts each pair in turn with all lanes, 64 ranks per step (coalesced
+// loads of y and of the estimate's permuted x in rank order, ballot counts).
+// The pair's own row and the rows of its Theiler window are taken out
+// afterwards.  Same tests as the definition, so the same counts, and every
+// pair is decided.
+template <int DXM>
+__global__ __launch_bounds__(kRankThreads) void list_rank_count_kernel(const ListLaunch L) {
+    const int lane = tid_x() & 63;
+    const int64_t w = (int64_t)bid_x() * (kRankThreads / 64) +
+                      (int)__builtin_amdgcn_readfirstlane((uint32_t)tid_x() >> 6);
+    if (w >= L.rank_waves) return;
+    const int jb = find_job(L.rank_off, L.n_jobs, w);
+    const Job &J = L.jobs[jb];
+    const ListSet &S = L.sets[J.set];
+    const int n = J.n, dx = J.dx;
+    const int nt = (n + 63) / 64;
+    const int64_t loc = w - L.rank_off[jb];
+    const int e = (int)(loc / nt);
+    const int r = (int)(loc - (int64_t)e * nt) * 64 + lane;
+    const int rr = min(r, n - 1);
+    // (ranks and rows are clamped to the set: inputs that are not finite,
+    // which device calls do not check, leave a wrong result, never a fault)
+    const int i = min(max(S.zord[rr], 0), n - 1);
+    const float eps = J.er[(int64_t)e * n + i];
+    const bool ok = r < n && eps >= 0.f;      // -1: the pair is in the redo queue
+    const float *zs = S.zs, *yr = S.yr;
+    const float *xr = J.xr + (int64_t)e * dx * n;
+    const float zq = zs[rr], yq = yr[rr];
+    float xq[DXM];
+#pragma unroll
+    for (int c = 0; c < DXM; ++c) xq[c] = c < dx ? xr[(int64_t)c * n + rr] : 0.f;
+    int lo = 0, hi = n;
+    {
+        int a = 0, b = n;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (zs[m] - zq > -eps) b = m; else a = m + 1;
+        }
+        lo = a;
+        b = n;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (zs[m] - zq >= eps) b = m; else a = m + 1;
+        }
+        hi = a;
+    }
+    int mx = 0, my = 0, mz = 0;
+    int64_t ent = 0;
+    for (uint64_t todo = ballot(ok); todo; todo &= todo - 1) {
+        const int o = lowest(todo);
+        const int plo = bcast(lo, o), phi = bcast(hi, o), pi = bcast(i, o);
+        const float pe = bcast(eps, o), py = bcast(yq, o);
+        float px[DXM];
+#pragma unroll
+        for (int c = 0; c < DXM; ++c) px[c] = bcast(xq[c], o);
+        int cx = 0, cy = 0;
+        for (int q = plo; q < phi; q += 64) {
+            const int m = q + lane;
+            const bool in = m < phi;
+            const int mm = in ? m : phi - 1;
+            const float y = yr[mm];
+            float d = absdiff(xr[mm], px[0]);
+            Unroll<1, DXM>::upto(dx, [&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                d = fmax_(d, absdiff(xr[(int64_t)c * n + mm], px[c]));
+            });
+            cy += __builtin_popcountll(ballot(in && absdiff(y, py) < pe));
+            cx += __builtin_popcountll(ballot(in && d < pe));
+        }
+        int cz = phi - plo;
+        const int w0 = max(0, pi - J.theiler), w1 = min(n - 1, pi + J.theiler);
+        for (int j = w0 + lane; j - lane <= w1; j += 64) {
+            const bool inw = j <= w1;
+            const int rj = min(max(S.zrank[inw ? j : w1], 0), n - 1);
+            const bool inr = inw && rj >= plo && rj < phi;
+            float d = absdiff(xr[rj], px[0]);
+            Unroll<1, DXM>::upto(dx, [&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                d = fmax_(d, absdiff(xr[(int64_t)c * n + rj], px[c]));
+            });
+            cz -= __builtin_popcountll(ballot(inr));
+            cy -= __builtin_popcountll(ballot(inr && absdiff(yr[rj], py) < pe));
+            cx -= __builtin_popcountll(ballot(inr && d < pe));
+        }
+        ent += phi - plo;
+        if (lane == o) {
+            mx = cx;
+            my = cy;
+            mz = cz;
+        }
+    }
+    if (ok) {
+        J.pk[(int64_t)e * n + i] = pack_counts(mx, my, mz);
+        if (J.eps) J.eps[(int64_t)e * n + i] = eps;
+        if (J.cnt) {
+            J.cnt[((int64_t)e * 3 + 0) * n + i] = mx;
+            J.cnt[((int64_t)e * 3 + 1) * n + i] = my;
+            J.cnt[((int64_t)e * 3 + 2) * n + i] = mz;
+        }
+    }
+    if (L.stats && lane == 0) {
+        const int slot = (int)(w & (kListStatSlots - 1));
+        unsigned long long *st =
+            reinterpret_cast<unsigned long long *>(L.counters + kListStatWord + slot * kListStatStride);
+        atomicAdd(&st[1], (unsigned long long)ent);
     }
 }
 
@@ -1535,6 +1702,25 @@ int launch_list_scan(const ListLaunch &L, void *stream) {
     return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kBlock), args, 0, (hipStream_t)stream) == hipSuccess
                ? 0
                : -1;
+}
+
+int launch_list_rank_sort(const ListLaunch &L, void *stream) {
+    if (L.rank_sets <= 0) return 0;
+    const dim3 grid((unsigned)((L.max_rank_n + kRankRows - 1) / kRankRows), (unsigned)L.n_sets);
+    hipLaunchKernelGGL(list_rank_sort_kernel, grid, dim3(kRankThreads), 0, (hipStream_t)stream, L);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_rank_count(const ListLaunch &L, void *stream) {
+    if (L.rank_waves <= 0) return 0;
+    const int64_t blocks = (L.rank_waves + kRankThreads / 64 - 1) / (kRankThreads / 64);
+    if (L.dxm > 1)
+        hipLaunchKernelGGL(list_rank_count_kernel<kMaxDx>, dim3((unsigned)blocks), dim3(kRankThreads), 0,
+                           (hipStream_t)stream, L);
+    else
+        hipLaunchKernelGGL(list_rank_count_kernel<1>, dim3((unsigned)blocks), dim3(kRankThreads), 0,
+                           (hipStream_t)stream, L);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_list_fallback(const ListLaunch &L, void *stream) {

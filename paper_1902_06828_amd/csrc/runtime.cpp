@@ -40,37 +40,46 @@ static size_t round_size(size_t b) {
 void *DeviceAllocator::alloc(size_t bytes) {
     bytes = round_size(bytes ? bytes : 1);
     std::lock_guard<std::mutex> lk(mu_);
-    auto it = free_.find(bytes);
+    auto it = free_.lower_bound(bytes);
     void *p = nullptr;
-    if (it != free_.end()) {
+    size_t got = bytes;
+    if (it != free_.end() && it->first <= bytes + bytes / 4 + (size_t(64) << 20)) {
         p = it->second;
+        got = it->first;
+        cached_ -= got;
         free_.erase(it);
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         for (auto &kv : free_) (void)hipFree(kv.second);
         free_.clear();
+        cached_ = 0;
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
     }
-    in_use_ += bytes;
+    live_[p] = got;
+    in_use_ += got;
     peak_ = std::max(peak_, in_use_);
     return p;
 }
 
 void DeviceAllocator::release(void *p, size_t bytes) {
     if (!p) return;
-    bytes = round_size(bytes ? bytes : 1);
     std::lock_guard<std::mutex> lk(mu_);
-    in_use_ -= bytes;
-    free_.emplace(bytes, p);
+    auto it = live_.find(p);
+    const size_t got = it != live_.end() ? it->second : round_size(bytes ? bytes : 1);
+    if (it != live_.end()) live_.erase(it);
+    in_use_ -= got;
+    cached_ += got;
+    free_.emplace(got, p);
 }
 
 void DeviceAllocator::trim() {
     std::lock_guard<std::mutex> lk(mu_);
     for (auto &kv : free_) (void)hipFree(kv.second);
     free_.clear();
+    cached_ = 0;
 }
 
 DevBuf::~DevBuf() { reset(); }
@@ -693,15 +702,30 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     size_t bytes = 0;
     int nmax_set = 0;
     std::vector<size_t> o_l1(n_sets), o_l2(n_sets), o_len(n_sets), o_bound(n_sets), o_zy(n_sets),
-        o_order(n_sets, 0);
+        o_order(n_sets, 0), o_rank(n_sets, 0);
     std::vector<int> set_dx(n_sets, 0);
     for (int j = 0; j < n_ljobs_; ++j) set_dx[set_of[j]] = std::max(set_dx[set_of[j]], specs[j].dx);
+    // sets with one Z column and one Y column are counted by ranks of z
+    // (MTE_RANK_COUNTS=0 keeps them on the Z list, for comparison)
+    const char *rk_env = std::getenv("MTE_RANK_COUNTS");
+    const bool rank_on = !(rk_env && *rk_env == '0');
+    std::vector<char> ranked(n_sets, 0);
+    int rank_sets = 0, max_rank_n = 0;
+    for (int t = 0; t < n_sets; ++t) {
+        const JobSpec &sp = specs[set_rep[t]];
+        ranked[t] = rank_on && sp.dz == 1 && sp.dy == 1 && sp.n <= kRankMaxN;
+        if (ranked[t]) {
+            ++rank_sets;
+            max_rank_n = std::max(max_rank_n, sp.n);
+        }
+    }
     for (int t = 0; t < n_sets; ++t) {
         const JobSpec &sp = specs[set_rep[t]];
         ListSet &S = sets[t];
         std::memset(&S, 0, sizeof S);
         int cap1 = 0, cap2 = 0;
         list_caps(set_dx[t], sp.dy, sp.dz, sp.n, &cap1, &cap2);
+        if (ranked[t]) cap2 = kRankListCap;
         for (int cc = 0; cc < sp.dy + sp.dz; ++cc) S.cols[cc] = sp.cols[sp.dx + cc];
         S.n = sp.n;
         S.dy = sp.dy;
@@ -732,9 +756,15 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
             o_order[t] = bytes;
             bytes = align_up(bytes + sizeof(int32_t) * (size_t)sp.n, 256);
         }
+        // rank arrays: zs, zord, zrank, yr (n words each)
+        if (ranked[t]) {
+            o_rank[t] = bytes;
+            bytes = align_up(bytes + 4 * sizeof(float) * (size_t)sp.n, 256);
+        }
     }
-    struct Off { size_t xt, xp, pk, xs, chunk; };
+    struct Off { size_t xt, xp, pk, xs, chunk, xr, er; };
     std::vector<Off> offs(n_ljobs_);
+    std::vector<int64_t> rank_off(n_ljobs_ + 1, 0);
     for (int j = 0; j < n_ljobs_; ++j) {
         const JobSpec &sp = specs[j];
         const size_t pairs = (size_t)sp.n * sp.n_est();
@@ -742,6 +772,14 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
         offs[j].xp = bytes;
         bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
+        rank_off[j + 1] = rank_off[j];
+        if (ranked[set_of[j]]) {
+            offs[j].xr = bytes;
+            bytes = align_up(bytes + sizeof(float) * pairs * sp.dx, 256);
+            offs[j].er = bytes;
+            bytes = align_up(bytes + sizeof(float) * pairs, 256);
+            rank_off[j + 1] += (int64_t)sp.n_est() * ((sp.n + 63) / 64);
+        }
         offs[j].xs = bytes;
         if (sp.dz == 0) bytes = align_up(bytes + sizeof(float) * (size_t)sp.n, 256);
         offs[j].pk = bytes;
@@ -755,7 +793,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
     const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
     const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
-    const size_t t_offs = align_up(sizeof(int64_t) * (4 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
+    const size_t t_offs = align_up(sizeof(int64_t) * (5 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
     const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
     if (measure) {
         *measure += bytes + sizeof(uint32_t) * kListCounterWords + tbytes;
@@ -773,6 +811,13 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         S.bound = reinterpret_cast<float *>(sb + o_bound[t]);
         S.zy = reinterpret_cast<float *>(sb + o_zy[t]);
         S.order = o_order[t] ? reinterpret_cast<int32_t *>(sb + o_order[t]) : nullptr;
+        if (ranked[t]) {
+            const size_t nb = sizeof(float) * (size_t)S.n;
+            S.zs = reinterpret_cast<float *>(sb + o_rank[t]);
+            S.zord = reinterpret_cast<int32_t *>(sb + o_rank[t] + nb);
+            S.zrank = reinterpret_cast<int32_t *>(sb + o_rank[t] + 2 * nb);
+            S.yr = reinterpret_cast<float *>(sb + o_rank[t] + 3 * nb);
+        }
     }
     // build blocks: kBuildRows rows each with packed 16-bit histograms when
     // every set has N <= 2^16, one row each with 32-bit histograms otherwise;
@@ -824,6 +869,11 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         J.eps = sp.diag_eps;
         J.cnt = sp.diag_cnt;
         J.pk = reinterpret_cast<uint64_t *>(sb + offs[j].pk);
+        if (ranked[set_of[j]]) {
+            J.zrank = sets[set_of[j]].zrank;
+            J.xr = reinterpret_cast<float *>(sb + offs[j].xr);
+            J.er = reinterpret_cast<float *>(sb + offs[j].er);
+        }
         J.chunk = reinterpret_cast<double *>(sb + offs[j].chunk);
         J.out = sp.out;
         J.keys = keys_dev + kpos;
@@ -840,6 +890,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     std::memcpy(oh + 2 * nj1, blk_off.data(), sizeof(int64_t) * nj1);
     std::memcpy(oh + 3 * nj1, row_off.data(), sizeof(int64_t) * (n_sets + 1));
     std::memcpy(oh + 3 * nj1 + (n_sets + 1), build_off.data(), sizeof(int64_t) * (n_sets + 1));
+    std::memcpy(oh + 3 * nj1 + 2 * (n_sets + 1), rank_off.data(), sizeof(int64_t) * nj1);
     ljobs_dev_ = reinterpret_cast<Job *>(tb);
     lblk_off_ = od + 2 * nj1;
     lpermute_blocks_ = blk_off[n_ljobs_];
@@ -870,6 +921,10 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     for (const JobSpec &sp : specs) L.max_chunks = std::max(L.max_chunks, (sp.n + kChunk - 1) / kChunk);
     L.sortx = 0;
     for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
+    L.rank_sets = rank_sets;
+    L.max_rank_n = max_rank_n;
+    L.rank_off = od + 3 * nj1 + 2 * (n_sets + 1);
+    L.rank_waves = rank_off[n_ljobs_];
     if (L.lanes >= ((int64_t)1 << 40) || n_ljobs_ >= (1 << 23)) return fail(MTE_EINVAL, "batch too large");
     n_est_pairs_ = L.lanes;
     MTE_HIP(hipMemcpyAsync(tb, hs, tbytes, hipMemcpyHostToDevice, s));
@@ -1193,6 +1248,9 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (launch_list_zy(ll_, s)) return hip_fail(hipGetLastError(), "Y,Z copy launch");
         MTE_HIP(hipEventRecord(fork_, s));
         MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
+        // the ranks of the one-Z-column sets come first: the permutation
+        // writes those sets' jobs' X in rank order
+        if (launch_list_rank_sort(ll_, side)) return hip_fail(hipGetLastError(), "rank launch");
         if ((rc = begin(side))) return rc;
         // capped only while the permutation is the smaller part: a launch of
         // many estimates over few list sets has more permutation than build
@@ -1212,6 +1270,7 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         MTE_HIP(hipStreamWaitEvent(s, join_, 0));
         if ((rc = begin(s))) return rc;
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
+        if (launch_list_rank_count(ll_, s)) return hip_fail(hipGetLastError(), "rank count launch");
         if ((rc = end(kStageScan, s))) return rc;
         if ((rc = begin(s))) return rc;
         if (launch_list_fallback(ll_, s)) return hip_fail(hipGetLastError(), "list fallback launch");

@@ -26,7 +26,13 @@ int hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // ---------------------------------------------------------------- memory
-// Caching device allocator: freed blocks are kept by exact size and reused.
+// Caching device allocator.  Freed blocks are kept and a request takes the
+// smallest cached block that holds it, if that block is at most a quarter
+// (plus 64 MiB) larger; otherwise a new block.  Batches of the request loop
+// differ in size from one to the next, so reuse by exact size alone would
+// allocate nearly every batch anew and fill the device with cached blocks
+// until a failed allocation freed them all (hipFree waits for the device).
+// in_use counts the blocks' real sizes.
 class DeviceAllocator {
 public:
     void *alloc(size_t bytes);          // nullptr on failure
@@ -34,11 +40,13 @@ public:
     void trim();                        // free every cached block
     size_t in_use() const { return in_use_; }
     size_t peak() const { return peak_; }
+    size_t cached() const { return cached_; }
     void reset_peak() { peak_ = in_use_; }
 private:
     std::mutex mu_;
     std::multimap<size_t, void *> free_;
-    size_t in_use_ = 0, peak_ = 0;
+    std::map<void *, size_t> live_;     // block sizes of the blocks handed out
+    size_t in_use_ = 0, peak_ = 0, cached_ = 0;
 };
 
 // RAII device buffer from the context allocator.

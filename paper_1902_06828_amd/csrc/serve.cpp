@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <thread>
@@ -75,6 +76,7 @@ public:
     std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
     Slot slots[kSlots];
+    int active_slots = kSlots;     // MTE_SERVE_SLOTS (1..3) limits the batches in flight
     std::thread worker;
     bool running = false, stop = false;
     size_t bytes_in_flight = 0;
@@ -92,6 +94,11 @@ public:
         for (auto &s : slots) {
             if (!s.stream) MTE_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             if (!s.done) MTE_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        }
+        active_slots = kSlots;
+        if (const char *v = std::getenv("MTE_SERVE_SLOTS")) {
+            const int n = std::atoi(v);
+            if (n >= 1 && n <= kSlots) active_slots = n;
         }
         stop = false;
         running = true;
@@ -294,7 +301,8 @@ public:
         for (;;) {
             retire();
             bool any_busy = false;
-            for (auto &s : slots) {
+            for (int i = 0; i < active_slots; ++i) {
+                Slot &s = slots[i];
                 if (!s.busy && !queue.empty()) admit(s);
                 any_busy |= s.busy;
             }

@@ -12,6 +12,7 @@ from .gen import (  # noqa: F401
     clm_network,
     empty_network,
     er_digraph,
+    paper_clm_network,
     paper_var_network,
     random_points,
     truth_adjacency,

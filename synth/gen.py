@@ -15,6 +15,8 @@ Workloads (paper, Validation tasks section, and the configurations measured here
   normalised to sum 0.4 per target, noise s.d. 0.1).
 * ``empty_network``: independent AR(1) processes (no links).
 * ``clm_network``: coupled logistic maps, coupling applied after the map.
+* ``paper_clm_network``: the paper's CLM variant (the map applied to the weighted
+  input: self-coupling 0.5, couplings normalised to sum 0.4, noise s.d. 0.1).
 * ``random_points``: sample matrices with ties and duplicate rows for parity tests.
 """
 
@@ -204,6 +206,42 @@ def clm_network(p_nodes: int, n_rows: int, seed: int, coupling: float = 0.5,
         v[v >= 1.0] = 0.0
         x[t] = v
         fx[t] = f(v)
+    return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32)), links
+
+
+def paper_clm_network(p_nodes: int, n_rows: int, seed: int):
+    """The paper's coupled-logistic-map variant (CLM section): the map acts on
+    the weighted input, a_i(t) = 0.5 x_i(t-1) + sum_j alpha x_j(t-l_ij) with the
+    couplings uniform and normalised to sum 0.4 per target (the VAR section's
+    conditions), then x_i(t) = [f(a_i(t)) + eta] mod 1, f(a) = 4a(1-a),
+    eta ~ N(0, 0.1^2).  A node without sources keeps the self term alone.
+
+    Returns (series [P][n_rows+MAX_LAG] float32, links (target, source, lag, alpha)).
+    """
+    parents = er_digraph(p_nodes, seed)
+    g = _rng(seed * 7919 + 1)
+    links = []
+    for i in range(p_nodes):
+        if parents[i]:
+            c = 0.4 / len(parents[i])
+            for j in parents[i]:
+                links.append((i, j, int(g.integers(1, MAX_LAG + 1)), c))
+    h = _rng(seed * 104729 + 3)
+    total = BURN_IN + n_rows + MAX_LAG
+    w = np.zeros((MAX_LAG, p_nodes, p_nodes))
+    w[0][np.arange(p_nodes), np.arange(p_nodes)] = 0.5
+    for (i, j, lag, c) in links:
+        w[lag - 1][i, j] += c
+    x = np.zeros((total, p_nodes))
+    x[:MAX_LAG] = h.random((MAX_LAG, p_nodes))
+    noise = h.standard_normal((total, p_nodes)) * 0.1
+    for t in range(MAX_LAG, total):
+        a = np.zeros(p_nodes)
+        for lag in range(1, MAX_LAG + 1):
+            a = a + w[lag - 1] @ x[t - lag]
+        v = np.mod(4.0 * a * (1.0 - a) + noise[t], 1.0)
+        v[v >= 1.0] = 0.0
+        x[t] = v
     return np.ascontiguousarray(x[BURN_IN:].T.astype(np.float32)), links
 
 

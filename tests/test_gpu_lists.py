@@ -224,3 +224,60 @@ def test_build_forms_agree(monkeypatch, dims, n, w):
         cmi, eps, cx, cy, cz = ref
         assert np.array_equal(eps[e, rows], re) and np.array_equal(cx[e, rows], ra)
         assert np.array_equal(cy[e, rows], rb) and np.array_equal(cz[e, rows], rc)
+
+
+# One Z column and one Y column: the counts come from ranges of ranks of z
+# (rows sorted by z, two binary searches per pair) instead of the Z list.
+RANK_CASES = [
+    # (n, dx, k, kind, S)
+    (3, 1, 1, "normal", 7),
+    (9, 1, 4, "grid", 9),
+    (65, 2, 3, "dup", 9),
+    (1000, 1, 4, "grid", 15),
+    (3001, 3, 8, "normal", 9),
+    (4097, 1, 4, "wide", 9),
+    (2000, 1, 4, "tiny", 9),
+    (1500, 1, 16, "dup", 9),
+]
+
+
+@pytest.mark.parametrize("n,dx,k,kind,S", RANK_CASES)
+def test_rank_counts_parity(monkeypatch, n, dx, k, kind, S):
+    # radii and counts bit for bit against the oracle, and the whole output
+    # equal to that of the same launch counted on the Z list
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    X, Y, Z = synth.random_points(n, (dx, 1, 1), seed=n + 31 * k, kind=kind)
+    say("rank counts", n, dx, k, kind, S)
+    mte.mte_list_stats(reset=True)
+    ranked = check_against_oracle(X, Y, Z, k, S)
+    pairs, _ = mte.mte_list_stats(reset=True)
+    assert pairs == n * (S + 1)
+    monkeypatch.setenv("MTE_RANK_COUNTS", "0")
+    say("  the same launch on the Z list")
+    zlist = mte.cmi_ksg_diag(X, Y, Z, k, S, 11, 3)
+    for a, b in zip(ranked, zlist):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,dx,kind", [(2000, 1, "split"), (200, 1, "mixed"), (3000, 2, "cells")])
+def test_rank_counts_overflowing_differences(monkeypatch, n, dx, kind):
+    # z differences that overflow to +inf fall outside every range (the range
+    # test is strict on both sides, like the distance test)
+    monkeypatch.setenv("MTE_FORCE_MODE", "list")
+    X, Y, Z = _overflow_points(n, (dx, 1, 1), 60 + n, kind)
+    say("rank counts, overflowing differences", n, dx, kind)
+    check_against_oracle(X, Y, Z, 4, 8, seed=5, cand=1)
+
+
+@pytest.mark.parametrize("n", [32768, 32769])
+def test_rank_size_limit(monkeypatch, n):
+    # sets of up to 32768 rows are ranked, larger ones keep the Z list; both
+    # sides of the limit against the all-pairs kernel
+    X, Y, Z = synth.random_points(n, (1, 1, 1), seed=n)
+    out = {}
+    for mode in ("brute", "list"):
+        monkeypatch.setenv("MTE_FORCE_MODE", mode)
+        say("rank size limit, N", n, "mode", mode)
+        out[mode] = mte.cmi_ksg_diag(X, Y, Z, 4, 8, 5, 1)
+    for a, b in zip(out["brute"], out["list"]):
+        assert np.array_equal(a, b)

@@ -39,6 +39,10 @@ CASES = [
     (300, (2, 1, 3), 3, "dup", 2),
     (130, (1, 2, 1), 1, "wide", 10),
     (1000, (1, 2, 0), 4, "grid", 5),
+    # one Z and one Y column: counts from ranks of z, window rows taken out
+    (400, (1, 1, 1), 4, "grid", 4),
+    (700, (2, 1, 1), 4, "dup", 2),
+    (513, (1, 1, 1), 3, "normal", 70),
 ]
 
 

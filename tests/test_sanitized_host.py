@@ -3,7 +3,7 @@
 The library's host C++ (validation, layouts, the request loop, the greedy
 search, the tests, network statistics) and the C oracle are rebuilt with both
 sanitizers (libmte_san.so, libksg_oracle_san.so; device code is not
-instrumented) and the CPU tests of the C ABI and of the oracle run in a
+instrumented) and the whole CPU suite (this file aside) runs in a
 subprocess that loads them, with the sanitizer runtime preloaded.  Any report
 aborts that process."""
 
@@ -26,7 +26,7 @@ def test_host_code_under_sanitizers():
     env = B.sanitizer_env()
     env["ORACLE_LIBRARY"] = cksg.LIB_SAN
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
-                        "tests/test_abi_cpu.py", "tests/test_oracle_ksg.py", "tests/test_oracle_perm_stats.py"],
+                        "tests", "--deselect", "tests/test_sanitized_host.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     tail = (r.stdout + r.stderr)[-3000:]
     assert r.returncode == 0, tail
