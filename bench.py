@@ -304,21 +304,59 @@ def served(mte, torch, n_burst=48, n_poisson=96, load=0.8):
     }
 
 
-def network_leg(mte):
+def network_leg(mte, stages=False, clm=True):
     """Network inference on the benchmark's 10-node VAR (T = 10000): every
     target's greedy selection through the request loop (targets concurrent),
     S = 200, alpha = 0.05, FDR over omnibus p-values; wall time, estimates per
-    second and the link statistics against the generating graph."""
+    second and the link statistics against the generating graph.  With
+    `stages`, the kernels' HIP-event times per stage over the run (launches
+    are then made directly, not from graphs; with MTE_SERVE_SLOTS=1 the
+    batches run one at a time, so the stage times add up to the GPU time).
+    With `clm`, also the paper's CLM network at its significance level."""
     import synth
     series, links = synth.var_network(10, N_ROWS, seed=SEED)
+    stage_names = list(mte._lib.STAGES)
+    if stages:
+        mte.mte_kernel_timing(True)
+        for st in stage_names:
+            mte.mte_kernel_timing_stage(st, reset=True)
+    mte.mte_serve_get_stats(reset=True)
     t = time.perf_counter()
     adj, summ = mte.mte_infer_network(series, max_lag_sources=5, alpha=0.05, alpha_fdr=0.05, S=S, seed=SEED)
     wall = time.perf_counter() - t
+    sst = mte.mte_serve_get_stats(reset=True)
+    stage_ms = {}
+    if stages:
+        for st in stage_names:
+            n, ms = mte.mte_kernel_timing_stage(st, reset=True)
+            if n:
+                stage_ms[st] = {"launches": n, "ms": ms}
+        mte.mte_kernel_timing(False)
     est = int(sum(s["n_estimates"] for s in summ))
     m = mte.mte_link_metrics(adj, synth.truth_adjacency(10, links))
-    return {"workload": "10-node VAR (config form), T=10000, all targets, S=200, alpha=0.05, BH-FDR 0.05",
-            "wall_s": wall, "estimates": est, "evals_per_s": est / wall,
-            "precision": m["precision"], "recall": m["recall"], "specificity": m["specificity"]}
+    out = {"workload": "10-node VAR (config form), T=10000, all targets, S=200, alpha=0.05, BH-FDR 0.05",
+           "wall_s": wall, "estimates": est, "evals_per_s": est / wall,
+           "precision": m["precision"], "recall": m["recall"], "specificity": m["specificity"],
+           "batches": sst["batches"], "mean_batch_requests": sst["mean_batch_requests"],
+           "serve_slots": int(os.environ.get("MTE_SERVE_SLOTS") or 3)}
+    if stages:
+        out["stages_ms"] = stage_ms
+    if not clm:
+        return out
+    # the paper's KSG workload: its coupled-logistic-map variant at its
+    # significance level (S = 1001 > 1/alpha surrogates)
+    cs, clinks = synth.paper_clm_network(10, N_ROWS, seed=1)
+    t = time.perf_counter()
+    cadj, csumm = mte.mte_infer_network(cs, max_lag_sources=5, alpha=0.001, alpha_fdr=0.001, S=1001, seed=1)
+    cwall = time.perf_counter() - t
+    cest = int(sum(s["n_estimates"] for s in csumm))
+    cm = mte.mte_link_metrics(cadj, synth.truth_adjacency(10, clinks))
+    clm = {"workload": "10-node CLM (paper's form), T=10000, all targets, S=1001, alpha=0.001, BH-FDR 0.001",
+           "wall_s": cwall, "estimates": cest, "evals_per_s": cest / cwall, "links": int(len(clinks)),
+           "precision": cm["precision"], "recall": cm["recall"], "specificity": cm["specificity"],
+           "paper_accuracy": "precision, recall and specificity above 0.98 on average at T=10000"}
+    out["clm"] = clm
+    return out
 
 
 PEAK_F64_TFLOPS = 78.6                 # MI355X fp64 (vector and matrix rates are equal)
@@ -381,6 +419,9 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--no-gauss", action="store_true")
+    ap.add_argument("--no-clm", action="store_true", help="network leg without the paper's CLM network")
+    ap.add_argument("--network-stages", action="store_true",
+                    help="per-stage kernel times over the network leg (direct launches)")
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
@@ -532,9 +573,17 @@ def main():
     net = None
     if not args.no_network:
         log("network: all targets of the 10-node VAR")
-        net = network_leg(mte)
+        net = network_leg(mte, stages=args.network_stages, clm=not args.no_clm)
         log(f"network: {net['wall_s']:.2f} s, {net['evals_per_s']:.1f} evals/s, precision {net['precision']:.2f} "
             f"recall {net['recall']:.2f}")
+        if "stages_ms" in net:
+            tot = sum(v["ms"] for k, v in net["stages_ms"].items() if k != "permute")
+            log("network: stage ms " + ", ".join(f"{k} {v['ms']:.1f}" for k, v in net["stages_ms"].items()) +
+                f" (all but the permutation, which runs beside the build: {tot:.1f})")
+        if "clm" in net:
+            c = net["clm"]
+            log(f"network: paper's CLM, {c['wall_s']:.2f} s, {c['evals_per_s']:.1f} evals/s, precision "
+                f"{c['precision']:.3f} recall {c['recall']:.3f} specificity {c['specificity']:.3f}")
 
     gl = None
     if not args.no_gauss:
