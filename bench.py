@@ -182,6 +182,10 @@ def c3_leg(mte):
     cands = [j for j in range(10) if j != target]
     out = {"workload": "C3: greedy selection for one target, 10-node VAR, N=10000, S=200, lags 1..5",
            "target": target, "true_parents": sorted({(j, l) for (i, j, l, _) in links if i == target})}
+    # an untimed first search: the autotuner's first calls for these shapes
+    t = time.perf_counter()
+    mte.mte_select_sources(series, target, cands, max_lag_sources=5, alpha=0.05, S=S, seed=SEED)
+    out["first_search_s"] = time.perf_counter() - t
     t = time.perf_counter()
     res = mte.mte_select_sources(series, target, cands, max_lag_sources=5, alpha=0.05, S=S, seed=SEED)
     wall = time.perf_counter() - t
@@ -563,6 +567,17 @@ def main():
                  "identical_to_batched": bool(same)}
         log(f"plain: {plain['evals_per_s']:.1f} evals/s (identical results: {same})")
 
+    # the autotuner's choices, by the leg whose calls made or read them
+    seen_tuning = set()
+    tuning = {}
+
+    def note_tuning(leg):
+        new = [r for r in mte.mte_tune_report() if (r["key"], r["from"]) not in seen_tuning]
+        seen_tuning.update((r["key"], r["from"]) for r in new)
+        tuning[leg] = new
+
+    note_tuning("batched_and_plain")
+
     srv = None
     if not args.no_served:
         log("served: burst + Poisson arrivals")
@@ -570,6 +585,15 @@ def main():
         log(f"served: {srv['saturation_evals_per_s']:.1f} evals/s saturated; Poisson p50 "
             f"{srv['p50_latency_s'] * 1e3:.1f} ms p99 {srv['p99_latency_s'] * 1e3:.1f} ms")
 
+    note_tuning("served")
+    c3 = None
+    if not args.no_c3:
+        log("c3: one target's greedy selection")
+        c3 = c3_leg(mte)
+        log(f"c3: {c3['direct_s']:.3f} s direct ({c3['direct_evals_per_s']:.0f} evals/s), {c3['served_s']:.3f} s "
+            f"served, {c3['estimates']} estimates, sources {c3['sources']} (true {c3['true_parents']})")
+
+    note_tuning("c3")
     net = None
     if not args.no_network:
         log("network: all targets of the 10-node VAR")
@@ -585,6 +609,7 @@ def main():
             log(f"network: paper's CLM, {c['wall_s']:.2f} s, {c['evals_per_s']:.1f} evals/s, precision "
                 f"{c['precision']:.3f} recall {c['recall']:.3f} specificity {c['specificity']:.3f}")
 
+    note_tuning("network")
     gl = None
     if not args.no_gauss:
         log("gauss: network inference with the Gaussian estimator, Gram kernel")
@@ -593,6 +618,7 @@ def main():
             f"{gl['recall']:.2f}; gram " + ", ".join(f"D={g['D']} N={g['N']}: {g['kernel_ms']:.3f} ms "
                                                      f"{g['tflops']:.1f} TF/s" for g in gl["gram"]))
 
+    note_tuning("gauss")
     c1 = None
     if not args.no_c1:
         log("c1: single-estimate latency, N = 1000")
@@ -601,13 +627,7 @@ def main():
             f"{c1['host_call_p50_s'] * 1e3:.3f} ms, estimate {c1['estimate']:.4f} (closed form "
             f"{c1['closed_form']:.4f})")
 
-    c3 = None
-    if not args.no_c3:
-        log("c3: one target's greedy selection")
-        c3 = c3_leg(mte)
-        log(f"c3: {c3['direct_s']:.3f} s direct ({c3['direct_evals_per_s']:.0f} evals/s), {c3['served_s']:.3f} s "
-            f"served, {c3['estimates']} estimates, sources {c3['sources']} (true {c3['true_parents']})")
-
+    note_tuning("c1")
     c5 = None
     if not args.no_c5:
         log("c5: 100 concurrent target searches under a 2 GiB budget")
@@ -616,6 +636,7 @@ def main():
             f"{c5['p50_latency_s'] * 1e3:.1f} ms p99 {c5['p99_latency_s'] * 1e3:.1f} ms, peak "
             f"{c5['peak_bytes_in_use'] >> 20} MiB, {c5['admissions_that_waited']} admissions waited")
 
+    note_tuning("c5")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: C oracle on a bounded sample")
@@ -656,6 +677,9 @@ def main():
         "c1": c1,
         "c3": c3,
         "c5": c5,
+        "tuned_choices": tuning,
+        "tile_configs": [list(r) for r in mte.mte_tile_configs()],
+        "tile_config_fields": ["kmax", "g", "qp", "dzm", "dym", "dxm"],
     }
     print(json.dumps(line), flush=True)
 

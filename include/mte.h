@@ -480,6 +480,32 @@ int mte_serve_get_stats(mte_serve_stats *out, int reset);
 int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
 
 /* --------------------------------------------------------------------------
+ * Tuned launch choices.  The autotuner times candidate launch choices on a
+ * shape's first call and keeps the fastest; none of them changes a result.
+ *   all-pairs kernel: tile configuration (a row of mte_tile_configs) and
+ *     reference-split multiplier, per batch shape ("P:" keys), tuned by the
+ *     device calls (cmi_ksg_surrogates_dev);
+ *   list path: rows per block of the compiled-dimension build (2, 4), the
+ *     scan's cooperative-finish threshold (2, 4, 8 lanes) and, for launches
+ *     of one job, the estimate-group lane order, per job shape ("L:" keys:
+ *     N, dims, k, estimates, Theiler window, replications, one job or
+ *     several), tuned by the device calls on the batch itself and by the host
+ *     calls and greedy rounds on one job of the shape when the batch holds at
+ *     least 2^20 (row, estimate) pairs; the request loop only looks them up.
+ * Choices persist in a text file, MTE_TUNE_FILE or else
+ * $XDG_CACHE_HOME/mte/tune.txt or $HOME/.cache/mte/tune.txt ("off": none),
+ * keyed by the GPU architecture and the library build; MTE_TUNE=0 turns
+ * tuning off.
+ * mte_tune_report writes the choices made or read in this process, one per
+ * line: "<key> variant=<v> split=<m> build_rows=<q> coop_lanes=<c>
+ * grouped=<g> ms=<t> from=<tuned|file>" (0 / -1: the default).  It writes at
+ * most cap - 1 bytes and a NUL to buf (buf may be NULL when cap is 0) and
+ * the full length to *len_out, so a second call with a larger buffer gets
+ * everything.
+ * ------------------------------------------------------------------------ */
+int mte_tune_report(char *buf, size_t cap, size_t *len_out);
+
+/* --------------------------------------------------------------------------
  * Kernel timing: when enabled, launches are made directly (no graph replay)
  * and HIP events are recorded around every kernel launch of the stages
  * below, on the stream the kernel runs on (the list path's permutation runs

@@ -50,5 +50,6 @@ from ._lib import (  # noqa: F401
     mte_shutdown,
     mte_submit,
     mte_tile_configs,
+    mte_tune_report,
     mte_wait,
 )

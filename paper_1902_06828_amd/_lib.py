@@ -106,6 +106,7 @@ SIGNATURES = {
     "mte_serve_get_stats": [_P, _I],
     "mte_serve_cancel": [ctypes.c_int32],
     "mte_tile_configs": [_P, _I, _P],
+    "mte_tune_report": [_P, _SZ, _P],
     "mte_kernel_timing": [_I],
     "mte_kernel_timing_read": [_P, _P, _I],
     "mte_kernel_timing_stage": [_I, _P, _P, _I],
@@ -445,6 +446,25 @@ def mte_tile_configs():
     buf = np.empty((n.value, 6), np.int32)
     _check(lib().mte_tile_configs(_ptr(buf), n.value, ctypes.byref(n)))
     return [tuple(int(v) for v in row) for row in buf]
+
+
+def mte_tune_report():
+    """The autotuner's choices made or read from the tuning file in this
+    process: a list of dicts (key, variant, split, build_rows, coop_lanes,
+    grouped, ms, from)."""
+    n = ctypes.c_size_t()
+    _check(lib().mte_tune_report(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().mte_tune_report(buf, n.value + 1, ctypes.byref(n)))
+    out = []
+    for line in buf.value.decode().splitlines():
+        key, *fields = line.split()
+        rec = {"key": key}
+        for f in fields:
+            name, val = f.split("=", 1)
+            rec[name] = val if name == "from" else (float(val) if name == "ms" else int(val))
+        out.append(rec)
+    return out
 
 
 # ---------------------------------------------------------------- timing

@@ -219,7 +219,7 @@ static int dev_estimate(const float *dX, int dx, const float *dY, int dy, const 
     sp.out = d_out;
     std::vector<JobSpec> specs{sp};
     TileChoice tc;
-    if ((rc = choose_tiles(specs, s, true, &tc))) return rc;
+    if ((rc = choose_tiles(specs, s, kTuneBatch, &tc))) return rc;
     auto b = std::make_unique<Batch>();
     if ((rc = b->prepare(specs, tc, s))) return rc;
     g_dev_bytes += b->device_bytes();
@@ -249,7 +249,7 @@ extern "C" {
 
 const char *mte_last_error(void) { return mte::last_error(); }
 
-int mte_abi_version(void) { return 5; }
+int mte_abi_version(void) { return 6; }
 
 int mte_init(int device, size_t hbm_budget_bytes) { return init_device(device, hbm_budget_bytes); }
 
@@ -377,6 +377,29 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out) {
         std::memcpy(cfg_out + 6 * i, v, sizeof v);
     }
     *count_out = n;
+    return MTE_OK;
+}
+
+int mte_tune_report(char *buf, size_t cap, size_t *len_out) {
+    if (!len_out || (cap && !buf)) return fail(MTE_EINVAL, "null pointer argument");
+    std::string text;
+    {
+        Ctx &c = ctx();
+        std::lock_guard<std::mutex> lk(c.mu);
+        char line[512];
+        for (const auto &t : c.tune_log) {
+            snprintf(line, sizeof line, "%s variant=%d split=%d build_rows=%d coop_lanes=%d grouped=%d ms=%.4f from=%s\n",
+                     t.key.c_str(), t.tc.variant, t.tc.rs_mult, t.tc.build_qb, t.tc.coop_lanes, t.tc.grouped, t.ms,
+                     t.from_disk ? "file" : "tuned");
+            text += line;
+        }
+    }
+    *len_out = text.size();
+    if (cap) {
+        const size_t m = std::min(cap - 1, text.size());
+        std::memcpy(buf, text.data(), m);
+        buf[m] = '\0';
+    }
     return MTE_OK;
 }
 

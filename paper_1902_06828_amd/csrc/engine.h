@@ -140,6 +140,7 @@ struct ListSet {
     float *yr;
 };
 
+constexpr int kCoopLanes = 4;                 // default cooperative-finish threshold of the scan
 constexpr int kRankMaxN = 32768;              // rank counts: rows ranked by O(n^2) compares
 constexpr int kRankListCap = 8;               // Z-list capacity of a set counted by ranks
 
@@ -183,6 +184,8 @@ struct ListLaunch {
     int fb_grid;                  // blocks of the fallback kernel
     int max_chunks;               // largest ceil(n / kChunk) of the jobs (reduction grid)
     int sortx;                    // some job has no Z: sort the X columns (Job::xs)
+    int coop_lanes;               // the scan finishes cooperatively once this many lanes remain
+    int grouped;                  // one job: lanes over 64-estimate groups, XCD-contiguous blocks
     int rank_sets;                // sets counted by ranks (ListSet::zs)
     int64_t rank_waves;           // rank-count waves: sum over those sets' jobs of
                                   // n_est * ceil(n / 64)

@@ -915,7 +915,8 @@ __device__ __forceinline__ T *bcast(T *v, int o) {
 // 0.335 ms with 4, 0.350 ms with 6, 0.372 ms with 8.  2 or 4 entries per lane
 // per cooperative step were slower still (more scattered gathers past the
 // stop position).
-constexpr int kCoopLanes = 4;
+// The threshold (kCoopLanes by default) and the grouped lane order are launch
+// parameters, chosen by the tuner; neither changes a result.
 constexpr int kCoopU = 1;      // list entries per lane per cooperative step
 
 template <int KMAX, int DXM>
@@ -934,7 +935,8 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     // XCDs, the waves of a row are neighbours, sharing its list entries, and
     // rows that run together are near in (Y,Z), so that many of the X values
     // they gather are the same.
-    const bool grouped = L.n_jobs == 1;
+    const bool grouped = L.grouped != 0;          // set by the host for launches of one job only
+    const int coop = L.coop_lanes;
     int64_t b = bid_x();
     if (grouped) {
         const int64_t nb = (int64_t)__builtin_amdgcn_grid_size_x() / kBlock, hb = b;
@@ -994,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     {
         LEnt cur[kU];
         load_step(l1, cur);
-        while (__builtin_popcountll(ballot(act)) > kCoopLanes) {
+        while (__builtin_popcountll(ballot(act)) > coop) {
             if (!act) continue;
             if (m1 > len1) {          // list exhausted: undecided
                 act = false;
@@ -1090,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     {
         LEnt2 cur[kU];
         load_step(l2, cur);
-        while (__builtin_popcountll(ballot(act)) > kCoopLanes) {
+        while (__builtin_popcountll(ballot(act)) > coop) {
             if (!act) continue;
             if (m2 > len2) {
                 act = false;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <sys/stat.h>
 
 namespace mte {
 
@@ -123,6 +124,8 @@ Ctx &ctx() {
 }
 
 static int harm_locked(int64_t n);
+static std::string default_tune_file();
+static void load_tune_file_locked();
 
 static int init_locked(int device, size_t budget) {
     Ctx &c = ctx();
@@ -145,6 +148,10 @@ static int init_locked(int device, size_t budget) {
         return fail(MTE_EDEVICE, "libmte is built for gfx950, device is %s", prop.gcnArchName);
     c.device = device;
     c.n_cu = prop.multiProcessorCount;
+    c.arch = prop.gcnArchName;
+    if (size_t colon = c.arch.find(':'); colon != std::string::npos) c.arch.resize(colon);
+    c.tune_file = default_tune_file();
+    load_tune_file_locked();
     size_t fr = 0, tot = 0;
     MTE_HIP(hipMemGetInfo(&fr, &tot));
     c.budget = budget ? budget : (size_t)(0.9 * (double)fr);
@@ -226,6 +233,7 @@ int shutdown_all() {
     if (c.side_stream) (void)hipStreamDestroy(c.side_stream);
     c.side_stream = nullptr;
     c.tuned.clear();
+    c.tune_log.clear();
     c.inited = false;
     c.device = -1;
     return MTE_OK;
@@ -490,7 +498,7 @@ int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out) {
     Ctx &c = ctx();
     {
         std::lock_guard<std::mutex> lk(c.mu);
-        auto it = c.tuned.find(shape_key(specs));
+        auto it = c.tuned.find("P:" + shape_key(specs));
         if (it != c.tuned.end()) { *out = it->second; return MTE_OK; }
     }
     out->variant = variant_for(specs, g_pref_for(specs));
@@ -498,39 +506,127 @@ int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out) {
     return out->variant < 0 ? fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions") : MTE_OK;
 }
 
-int choose_tiles(const std::vector<JobSpec> &all_specs, hipStream_t s, bool tune, TileChoice *out) {
+// ---------------------------------------------------------------- tuning file
+// One choice per line: "mte-tune 1 <arch> <build> <key> <variant> <rs_mult>
+// <build_qb> <coop_lanes> <grouped> <ms>".  Lines of another architecture or
+// another build of the library are skipped, so a rebuilt library tunes anew.
+static const char *build_id() {
+    static std::string id = [] {
+        std::string v = __DATE__ "_" __TIME__;
+        for (char &ch : v)
+            if (ch == ' ' || ch == ':') ch = '-';
+        return v;
+    }();
+    return id.c_str();
+}
+
+static std::string default_tune_file() {
+    const char *f = std::getenv("MTE_TUNE_FILE");
+    if (f) return std::string(f) == "off" ? std::string() : std::string(f);
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) dir = x;
+    else if (const char *h = std::getenv("HOME"); h && *h) dir = std::string(h) + "/.cache";
+    else return std::string();
+    return dir + "/mte/tune.txt";
+}
+
+static void load_tune_file_locked() {
     Ctx &c = ctx();
-    // only the jobs of the all-pairs kernel have a tile choice
-    const std::vector<JobSpec> specs = pair_specs(all_specs);
-    if (specs.empty()) {
-        *out = TileChoice{-1, 1};
-        return MTE_OK;
+    if (c.tune_file.empty()) return;
+    FILE *f = std::fopen(c.tune_file.c_str(), "r");
+    if (!f) return;
+    char line[512], arch[128], bid[128], key[256];
+    while (std::fgets(line, sizeof line, f)) {
+        TileChoice tc;
+        double ms = 0.0;
+        int ver = 0;
+        if (std::sscanf(line, "mte-tune %d %127s %127s %255s %d %d %d %d %d %lf", &ver, arch, bid, key, &tc.variant,
+                        &tc.rs_mult, &tc.build_qb, &tc.coop_lanes, &tc.grouped, &ms) != 10)
+            continue;
+        if (ver != 1 || c.arch != arch || std::strcmp(bid, build_id()) != 0) continue;
+        c.tuned[key] = tc;
+        c.tune_log.push_back(Ctx::TuneNote{key, tc, ms, 1});
     }
+    std::fclose(f);
+}
+
+static void save_tune_locked(const std::string &key, const TileChoice &tc, double ms) {
+    Ctx &c = ctx();
+    c.tuned[key] = tc;
+    c.tune_log.push_back(Ctx::TuneNote{key, tc, ms, 0});
+    if (c.tune_file.empty()) return;
+    // create the directories of the path, then append one line
+    for (size_t pos = c.tune_file.find('/', 1); pos != std::string::npos; pos = c.tune_file.find('/', pos + 1))
+        (void)mkdir(c.tune_file.substr(0, pos).c_str(), 0755);
+    FILE *f = std::fopen(c.tune_file.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "mte-tune 1 %s %s %s %d %d %d %d %d %.4f\n", c.arch.c_str(), build_id(), key.c_str(), tc.variant,
+                 tc.rs_mult, tc.build_qb, tc.coop_lanes, tc.grouped, ms);
+    std::fclose(f);
+}
+
+// ---------------------------------------------------------------- tuning
+static bool tuning_on() {
+    const char *v = std::getenv("MTE_TUNE");
+    return !(v && *v == '0');
+}
+
+// Time one launch of `specs` with choice `tc` (after a warm-up launch);
+// negative when the launch cannot be made.
+static double time_launch(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
+    Batch b;
+    if (b.prepare(specs, tc, s) != MTE_OK) return -1.0;
+    if (b.enqueue_quiet(s) != MTE_OK) return -1.0;
+    (void)hipEventRecord(e0, s);
+    if (b.enqueue_quiet(s) != MTE_OK) return -1.0;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+    if (b.check_error(s) != MTE_OK) return -1.0;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+}
+
+// The list knobs a job shape is tuned for: launches of one job or of several.
+static std::string list_key(const JobSpec &sp, bool several) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "L:n%d:dx%d:dy%d:dz%d:k%d:e%d:w%d:r%d:%s", sp.n, sp.dx, sp.dy, sp.dz, sp.k, sp.n_est(),
+             sp.theiler, sp.reps, several ? "many" : "one");
+    return buf;
+}
+
+static int tune_pairs(const std::vector<JobSpec> &specs, hipStream_t s, int mode, TileChoice *out) {
+    Ctx &c = ctx();
     // test hooks: MTE_FORCE_VARIANT (tile configuration index, used when it
     // fits) and MTE_FORCE_SPLIT (0 = one reference split, m = m times the
     // heuristic split count)
     const int fv = env_int("MTE_FORCE_VARIANT", -1), fs = env_int("MTE_FORCE_SPLIT", -1);
     if (fv >= 0 || fs >= 0) {
-        TileChoice tc;
-        tc.variant = variant_for(specs, g_pref_for(specs));
-        tc.rs_mult = fs >= 0 ? fs : 1;
+        out->variant = variant_for(specs, g_pref_for(specs));
+        out->rs_mult = fs >= 0 ? fs : 1;
         TileCfg fc;
-        if (fv >= 0 && kernel_variant(fv, &fc) && fits(fc, need_of(specs))) tc.variant = fv;
-        if (tc.variant < 0) return fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions");
-        *out = tc;
+        if (fv >= 0 && kernel_variant(fv, &fc) && fits(fc, need_of(specs))) out->variant = fv;
+        if (out->variant < 0) return fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions");
         return MTE_OK;
     }
-    const std::string key = shape_key(specs);
+    const std::string key = "P:" + shape_key(specs);
     {
         std::lock_guard<std::mutex> lk(c.mu);
         auto it = c.tuned.find(key);
-        if (it != c.tuned.end()) { *out = it->second; return MTE_OK; }
+        if (it != c.tuned.end()) {
+            out->variant = it->second.variant;
+            out->rs_mult = it->second.rs_mult;
+            return MTE_OK;
+        }
     }
     TileChoice heur;
     heur.variant = variant_for(specs, g_pref_for(specs));
     heur.rs_mult = 1;
     if (heur.variant < 0) return fail(MTE_EINVAL, "no compiled tile configuration fits these dimensions");
-    if (!tune) { *out = heur; return MTE_OK; }
+    out->variant = heur.variant;
+    out->rs_mult = 1;
+    if (mode != kTuneBatch || !tuning_on()) return MTE_OK;
     // candidate set: every fitting variant with the exact k class, and split
     // multipliers 0 (one split), 1, 2
     std::vector<TileChoice> cand;
@@ -541,33 +637,113 @@ int choose_tiles(const std::vector<JobSpec> &all_specs, hipStream_t s, bool tune
         TileCfg t;
         kernel_variant(v, &t);
         if (!fits(t, nd) || t.dxm != hc.dxm || t.dym != hc.dym || t.dzm > hc.dzm) continue;
-        for (int m : {0, 1, 2}) cand.push_back(TileChoice{v, m});
+        for (int m : {0, 1, 2}) {
+            TileChoice tc;
+            tc.variant = v;
+            tc.rs_mult = m;
+            cand.push_back(tc);
+        }
     }
     hipEvent_t e0, e1;
     MTE_HIP(hipEventCreate(&e0));
     MTE_HIP(hipEventCreate(&e1));
-    float best_ms = 1e30f;
+    double best_ms = 1e30;
     TileChoice best = heur;
     for (const auto &tc : cand) {
-        Batch b;
-        if (b.prepare(specs, tc, s) != MTE_OK) continue;
-        if (b.enqueue(s, false) != MTE_OK) continue;      // warm-up
-        (void)hipEventRecord(e0, s);
-        if (b.enqueue(s, false) != MTE_OK) continue;
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) continue;
-        if (b.check_error(s) != MTE_OK) continue;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) { best_ms = ms; best = tc; }
+        const double ms = time_launch(specs, tc, s, e0, e1);
+        if (ms >= 0.0 && ms < best_ms) {
+            best_ms = ms;
+            best = tc;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lk(c.mu);
-        c.tuned[key] = best;
+        save_tune_locked(key, best, best_ms);
     }
-    *out = best;
+    out->variant = best.variant;
+    out->rs_mult = best.rs_mult;
+    return MTE_OK;
+}
+
+// List knobs: the compiled-dimension build's rows per block (2, 4), the
+// scan's cooperative-finish threshold (2, 4, 8) and, for launches of one
+// job, the estimate-group lane order (on, off).
+static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode, TileChoice *out) {
+    Ctx &c = ctx();
+    const bool several = lists.size() > 1;
+    const JobSpec &rep = lists.front();
+    const std::string key = list_key(rep, several);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.tuned.find(key);
+        if (it != c.tuned.end()) {
+            out->build_qb = it->second.build_qb;
+            out->coop_lanes = it->second.coop_lanes;
+            out->grouped = it->second.grouped;
+            return MTE_OK;
+        }
+    }
+    if (mode == kTuneNone || !tuning_on()) return MTE_OK;
+    int64_t pairs = 0;
+    for (const auto &sp : lists) pairs += (int64_t)sp.n * sp.n_est();
+    if (mode == kTuneShape && pairs < kTuneMinPairs) return MTE_OK;
+    // the launch timed: the batch itself, or one job of its first shape
+    const std::vector<JobSpec> probe = mode == kTuneBatch ? lists : std::vector<JobSpec>{rep};
+    const bool lean = rep.dy == 1 && rep.dz >= 1 && rep.dz <= kBuildFixedDz && rep.n < 65536;
+    std::vector<TileChoice> cand;
+    for (int qb : lean ? std::vector<int>{2, 4} : std::vector<int>{0})
+        for (int coop : {4, 2, 8})
+            for (int grp : several ? std::vector<int>{0} : std::vector<int>{1, 0}) {
+                TileChoice tc = *out;
+                tc.build_qb = qb;
+                tc.coop_lanes = coop;
+                tc.grouped = grp;
+                cand.push_back(tc);
+            }
+    hipEvent_t e0, e1;
+    MTE_HIP(hipEventCreate(&e0));
+    MTE_HIP(hipEventCreate(&e1));
+    double best_ms = 1e30;
+    TileChoice best = cand.front();
+    for (const auto &tc : cand) {
+        const double ms = time_launch(probe, tc, s, e0, e1);
+        if (ms >= 0.0 && ms < best_ms) {
+            best_ms = ms;
+            best = tc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TileChoice rec;
+    rec.build_qb = best.build_qb;
+    rec.coop_lanes = best.coop_lanes;
+    rec.grouped = best.grouped;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        save_tune_locked(key, rec, best_ms);
+    }
+    out->build_qb = rec.build_qb;
+    out->coop_lanes = rec.coop_lanes;
+    out->grouped = rec.grouped;
+    return MTE_OK;
+}
+
+int choose_tiles(const std::vector<JobSpec> &all_specs, hipStream_t s, int mode, TileChoice *out) {
+    *out = TileChoice{};
+    int rc;
+    // the jobs of the all-pairs kernel have a tile choice
+    const std::vector<JobSpec> specs = pair_specs(all_specs);
+    if (!specs.empty() && (rc = tune_pairs(specs, s, mode, out))) return rc;
+    // the list path's jobs have the list knobs
+    std::vector<int> set_of;
+    int n_sets = 0;
+    assign_paths(all_specs, &set_of, &n_sets);
+    std::vector<JobSpec> lists;
+    for (size_t j = 0; j < all_specs.size(); ++j)
+        if (set_of[j] >= 0) lists.push_back(all_specs[j]);
+    if (!lists.empty() && (rc = tune_lists(lists, s, mode, out))) return rc;
     return MTE_OK;
 }
 
@@ -633,7 +809,7 @@ int Batch::prepare(const std::vector<JobSpec> &specs, const TileChoice &tc, hipS
     variant_ = -1;
     if (!pairs.empty() && (rc = prepare_pairs(pairs, tc, s, measure))) return rc;
     n_ljobs_ = 0;
-    if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, s, measure))) return rc;
+    if (!lists.empty() && (rc = prepare_lists(lists, lset, n_sets, tc, s, measure))) return rc;
     n_sjobs_ = 0;
     if (!solo.empty() && (rc = prepare_solo(solo, s, measure))) return rc;
     return MTE_OK;
@@ -677,7 +853,7 @@ static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
 }
 
 int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
-                         hipStream_t s, size_t *measure) {
+                         const TileChoice &tc, hipStream_t s, size_t *measure) {
     Ctx &c = ctx();
     n_ljobs_ = (int)specs.size();
     std::vector<Job> jobs(n_ljobs_);
@@ -840,7 +1016,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         }
     }
     const char *bq = std::getenv("MTE_BUILD_QB");
-    const int lean_qb = bq && *bq ? std::atoi(bq) : kLeanRows;
+    const int lean_qb = bq && *bq ? std::atoi(bq) : (tc.build_qb == 4 ? 4 : kLeanRows);
     const int qb = build_kind == 1 ? lean_qb : (pack ? kBuildRows : 1);
     for (int t = 0; t < n_sets; ++t) build_off[t + 1] = build_off[t] + (row_off[t + 1] - row_off[t] + qb - 1) / qb;
     if ((rc = ltables_.ensure(tbytes))) return rc;
@@ -921,6 +1097,8 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     for (const JobSpec &sp : specs) L.max_chunks = std::max(L.max_chunks, (sp.n + kChunk - 1) / kChunk);
     L.sortx = 0;
     for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
+    L.coop_lanes = env_int("MTE_COOP_LANES", tc.coop_lanes > 0 ? tc.coop_lanes : kCoopLanes);
+    L.grouped = n_ljobs_ == 1 && env_int("MTE_GROUPED", tc.grouped != 0 ? 1 : 0) != 0 ? 1 : 0;
     L.rank_sets = rank_sets;
     L.max_rank_n = max_rank_n;
     L.rank_off = od + 3 * nj1 + 2 * (n_sets + 1);
@@ -1327,6 +1505,11 @@ int Batch::enqueue(hipStream_t s, bool use_graph) {
     return launch_direct(s);
 }
 
+int Batch::enqueue_quiet(hipStream_t s) {
+    quiet_ = true;
+    return launch_all(s, false);
+}
+
 int Batch::check_error(hipStream_t s) {
     uint32_t flag = 0;
     static thread_local std::vector<uint32_t> words(kListCounterWords);
@@ -1335,7 +1518,7 @@ int Batch::check_error(hipStream_t s) {
         MTE_HIP(hipMemcpyAsync(words.data(), lcounters_.as<uint32_t>(), sizeof(uint32_t) * kListCounterWords,
                                hipMemcpyDeviceToHost, s));
     MTE_HIP(hipStreamSynchronize(s));
-    if (n_ljobs_ > 0) {
+    if (n_ljobs_ > 0 && !quiet_) {
         uint64_t seen[2] = {0, 0};
         for (int slot = 0; slot < kListStatSlots; ++slot) {
             uint64_t v[2];
@@ -1355,7 +1538,7 @@ int Batch::check_error(hipStream_t s) {
 
 int run_blocking(const std::vector<JobSpec> &specs, hipStream_t s) {
     TileChoice tc;
-    int rc = choose_tiles(specs, s, false, &tc);
+    int rc = choose_tiles(specs, s, kTuneShape, &tc);
     if (rc) return rc;
     Batch b;
     if ((rc = b.prepare(specs, tc, s))) return rc;

@@ -89,9 +89,14 @@ struct JobSpec {
     int n_est() const { return (int)keys.size(); }
 };
 
+// Launch choices that change no result: the all-pairs kernel's tile
+// configuration and split count, and the list path's knobs (0 = default).
 struct TileChoice {
     int variant = -1;
     int rs_mult = 1;                   // multiplier on the heuristic split count
+    int build_qb = 0;                  // rows per block of the compiled-dimension build (2 or 4)
+    int coop_lanes = 0;                // the scan's cooperative-finish threshold
+    int grouped = -1;                  // one-job launches: estimate-group lane order (1) or not (0)
 };
 
 // Which path runs each job of a batch: -1 = all-pairs kernel, otherwise the
@@ -129,6 +134,8 @@ public:
     int enqueue(hipStream_t s, bool use_graph);
     // Non-zero when a kernel reported an error (reads device words; syncs s).
     int check_error(hipStream_t s);
+    // Launches of the autotuner: direct, no stage timing, no list statistics.
+    int enqueue_quiet(hipStream_t s);
     size_t device_bytes() const;
     int variant() const { return variant_; }
     int64_t estimates() const { return n_est_total_; }
@@ -138,7 +145,7 @@ private:
     int launch_all(hipStream_t s, bool timed);
     int prepare_pairs(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, size_t *measure);
     int prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
-                      hipStream_t s, size_t *measure);
+                      const TileChoice &tc, hipStream_t s, size_t *measure);
     int prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t *measure);
     // few-estimate part (solo kernel, then the list path's reduction)
     int n_sjobs_ = 0, svariant_ = -1;
@@ -169,6 +176,7 @@ private:
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
     bool graph_failed_ = false;
+    bool quiet_ = false;                // a tuning launch: leaves the statistics alone
     // fork/join of the list part's permutation onto the side stream
     hipEvent_t fork_ = nullptr, join_ = nullptr;
 };
@@ -187,8 +195,19 @@ struct Ctx {
     double *harm = nullptr;
     int64_t harm_n = 0;
     std::vector<double *> retired;
-    // autotuner: shape key -> choice
+    // autotuner: shape key -> choice ("P..." keys: all-pairs tiles of a
+    // batch; "L..." keys: list-path knobs of a job shape), the choices made
+    // or loaded (for mte_tune_report), the device's architecture and the
+    // file the choices persist in ("" = none)
     std::map<std::string, TileChoice> tuned;
+    struct TuneNote {
+        std::string key;
+        TileChoice tc;
+        double ms;
+        int from_disk;
+    };
+    std::vector<TuneNote> tune_log;
+    std::string arch, tune_file;
     // kernel timing per stage
     bool timing = false;
     struct Pending { int stage; hipEvent_t a, b; };
@@ -211,9 +230,19 @@ const double *harm_table();
 
 // Pick the tile variant classes for a set of jobs; -1 if nothing fits.
 int variant_for(const std::vector<JobSpec> &specs, int g_pref);
-// Choose (variant, split multiplier) for a batch, running the autotuner on
-// the first call for a shape when `tune` is set.
-int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, bool tune, TileChoice *out);
+// Choose the launch choices of a batch: a choice tuned before for its shape
+// (in this process or read from the tuning file) or, on a shape's first
+// call, by the autotuner as `mode` allows:
+//   kTuneNone   look up only (the request loop: tuning launches would hold
+//               memory outside its budget)
+//   kTuneBatch  time the candidates on the batch itself (device calls)
+//   kTuneShape  time the list knobs on a one-job launch of the batch's first
+//               list job (host calls, greedy rounds); only for batches of at
+//               least kTuneMinPairs (row, estimate) pairs
+// MTE_TUNE=0 turns tuning off (heuristic choices).
+enum { kTuneNone = 0, kTuneBatch = 1, kTuneShape = 2 };
+constexpr int64_t kTuneMinPairs = int64_t(1) << 20;
+int choose_tiles(const std::vector<JobSpec> &specs, hipStream_t s, int mode, TileChoice *out);
 
 // The tile choice for jobs run on the all-pairs kernel whatever path
 // assign_paths would give them: the autotuner's cached choice for the shape

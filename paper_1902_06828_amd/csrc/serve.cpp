@@ -233,7 +233,7 @@ public:
             TileChoice tc;
             size_t need = 0;
             auto b = std::make_unique<Batch>();
-            rc = choose_tiles(specs, s.stream, false, &tc);
+            rc = choose_tiles(specs, s.stream, kTuneNone, &tc);
             if (rc == MTE_OK) rc = b->prepare(specs, tc, s.stream, &need);
             if (rc != MTE_OK) return fail_front(take, rc, "batch preparation failed");
             const size_t bytes = need + sizeof(double) * n_out;

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert mte.lib().mte_abi_version() == 5
+    assert mte.lib().mte_abi_version() == 6
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 100, 1000, 4097, 10000])
@@ -225,3 +225,13 @@ def test_standardise_matches_oracle():
     assert np.array_equal(mte.mte_standardise(s).view(np.uint32), greedy.standardise(s).view(np.uint32))
     r = (g.standard_normal((3, 4, 700)) * 0.01).astype(np.float32)
     assert np.array_equal(mte.mte_standardise(r).view(np.uint32), greedy.standardise(r).view(np.uint32))
+
+
+def test_tune_report_without_a_device():
+    # no call has run on a device, so the report holds no choice; the length
+    # is returned without a buffer, and a buffer size without a buffer is refused
+    assert mte.mte_tune_report() == []
+    import ctypes
+    n = ctypes.c_size_t(99)
+    assert mte.lib().mte_tune_report(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert mte.lib().mte_tune_report(None, 4, ctypes.byref(n)) == mte._lib.MTE_EINVAL
