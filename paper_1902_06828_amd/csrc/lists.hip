@@ -1331,18 +1331,34 @@ __global__ __launch_bounds__(kRankThreads) void list_rank_count_kernel(const Lis
 #pragma unroll
         for (int c = 0; c < DXM; ++c) px[c] = bcast(xq[c], o);
         int cx = 0, cy = 0;
-        for (int q = plo; q < phi; q += 64) {
-            const int m = q + lane;
-            const bool in = m < phi;
-            const int mm = in ? m : phi - 1;
-            const float y = yr[mm];
-            float d = absdiff(xr[mm], px[0]);
-            Unroll<1, DXM>::upto(dx, [&](auto cc) {
-                constexpr int c = decltype(cc)::value;
-                d = fmax_(d, absdiff(xr[(int64_t)c * n + mm], px[c]));
-            });
-            cy += __builtin_popcountll(ballot(in && absdiff(y, py) < pe));
-            cx += __builtin_popcountll(ballot(in && d < pe));
+        // kRankU steps per iteration, their loads issued together (a pair's
+        // steps would otherwise wait for their loads one after another): the
+        // network-inference workload ran 3% faster than with one step per
+        // iteration; buffer loads over the range (no clamp, a lane mask
+        // instead) were 6% slower than either
+        constexpr int kRankU = DXM == 1 ? 4 : 1;
+        for (int q = plo; q < phi; q += 64 * kRankU) {
+            bool in[kRankU];
+            int mm[kRankU];
+            float y[kRankU], x0[kRankU];
+#pragma unroll
+            for (int u = 0; u < kRankU; ++u) {
+                const int m = q + 64 * u + lane;
+                in[u] = m < phi;
+                mm[u] = in[u] ? m : phi - 1;
+                y[u] = yr[mm[u]];
+                x0[u] = xr[mm[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kRankU; ++u) {
+                float d = absdiff(x0[u], px[0]);
+                Unroll<1, DXM>::upto(dx, [&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    d = fmax_(d, absdiff(xr[(int64_t)c * n + mm[u]], px[c]));
+                });
+                cy += __builtin_popcountll(ballot(in[u] && absdiff(y[u], py) < pe));
+                cx += __builtin_popcountll(ballot(in[u] && d < pe));
+            }
         }
         int cz = phi - plo;
         const int w0 = max(0, pi - J.theiler), w1 = min(n - 1, pi + J.theiler);
