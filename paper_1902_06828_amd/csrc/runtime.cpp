@@ -566,6 +566,8 @@ static void save_tune_locked(const std::string &key, const TileChoice &tc, doubl
 }
 
 // ---------------------------------------------------------------- tuning
+constexpr double kTuneMargin = 0.97;   // a candidate must be 3% faster to replace the best
+
 static bool tuning_on() {
     const char *v = std::getenv("MTE_TUNE");
     return !(v && *v == '0');
@@ -647,11 +649,14 @@ static int tune_pairs(const std::vector<JobSpec> &specs, hipStream_t s, int mode
     hipEvent_t e0, e1;
     MTE_HIP(hipEventCreate(&e0));
     MTE_HIP(hipEventCreate(&e1));
-    double best_ms = 1e30;
+    // the heuristic choice stands unless a candidate is kTuneMargin faster,
+    // so that near ties resolve the same way from one run to the next
     TileChoice best = heur;
+    double best_ms = time_launch(specs, heur, s, e0, e1);
+    if (best_ms < 0.0) best_ms = 1e30;
     for (const auto &tc : cand) {
         const double ms = time_launch(specs, tc, s, e0, e1);
-        if (ms >= 0.0 && ms < best_ms) {
+        if (ms >= 0.0 && ms < best_ms * kTuneMargin) {
             best_ms = ms;
             best = tc;
         }
@@ -705,11 +710,14 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     hipEvent_t e0, e1;
     MTE_HIP(hipEventCreate(&e0));
     MTE_HIP(hipEventCreate(&e1));
+    // the first candidate is the default (2 build rows, 4 lanes, the grouped
+    // order for one job); another replaces the best so far only when it is
+    // kTuneMargin faster
     double best_ms = 1e30;
     TileChoice best = cand.front();
     for (const auto &tc : cand) {
         const double ms = time_launch(probe, tc, s, e0, e1);
-        if (ms >= 0.0 && ms < best_ms) {
+        if (ms >= 0.0 && ms < best_ms * (best_ms < 1e30 ? kTuneMargin : 1.0)) {
             best_ms = ms;
             best = tc;
         }
