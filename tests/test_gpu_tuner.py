@@ -92,3 +92,35 @@ def test_greedy_rounds_tuned_or_not(tmp_path, monkeypatch):
     for key in ("target_past", "sources", "sources_before_omnibus", "omnibus_te", "omnibus_p", "n_estimates"):
         assert tuned[key] == plain[key]
     mte.mte_shutdown()
+
+
+def test_tuning_file_skips_foreign_and_broken_lines(tmp_path, monkeypatch):
+    # a choice written by this build on this device is read back; lines of
+    # another architecture or another build of the library, and lines that
+    # do not parse, are skipped
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MTE_TUNE_FILE", str(path))
+    mte.mte_shutdown()
+    X, Y, Z = synth.random_points(4000, (1, 1, 2), seed=3)
+    dev = torch.device("cuda:0")
+    dX, dY, dZ = (torch.from_numpy(a).to(dev) for a in (X, Y, Z))
+    out = torch.zeros(301, dtype=torch.float64, device=dev)
+    mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, 300, 1, 0, out)
+    torch.cuda.synchronize()
+    good = path.read_text().splitlines()
+    assert len(good) == 1
+    f = good[0].split()            # mte-tune 1 <arch> <build> <key> <7 numbers>
+    foreign = [" ".join(f[:2] + ["gfx000"] + f[3:4] + ["L:foreign-arch"] + f[5:]),
+               " ".join(f[:3] + ["another-build"] + ["L:foreign-build"] + f[5:]),
+               " ".join(f[:4] + ["L:short-line"] + f[5:8]),
+               "mte-tune 2 " + " ".join(f[2:]),
+               "not a tuning line", ""]
+    path.write_text("\n".join(foreign + good) + "\n")
+    mte.mte_shutdown()
+    out.zero_()
+    mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, 300, 1, 0, out)
+    torch.cuda.synchronize()
+    rep = mte.mte_tune_report()
+    say("report after restart", rep)
+    assert [r["key"] for r in rep] == [f[4]] and rep[0]["from"] == "file"
+    mte.mte_shutdown()
