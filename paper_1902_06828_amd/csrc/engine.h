@@ -186,6 +186,7 @@ struct ListLaunch {
     int sortx;                    // some job has no Z: sort the X columns (Job::xs)
     int coop_lanes;               // the scan finishes cooperatively once this many lanes remain
     int grouped;                  // one job: lanes over 64-estimate groups, XCD-contiguous blocks
+    int scan_step;                // list entries per step of the scan's lane-by-lane loops (4, 8)
     int rank_sets;                // sets counted by ranks (ListSet::zs)
     int64_t rank_waves;           // rank-count waves: sum over those sets' jobs of
                                   // n_est * ceil(n / 64)

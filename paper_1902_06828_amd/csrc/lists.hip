@@ -830,8 +830,12 @@ __global__ __launch_bounds__(kSortThreads) void list_order_kernel(const ListLaun
 // condition under which the list decides the pair.  A sentinel that enters
 // the k-NN list (bound + 1 ulp < k-th distance) leaves a radius above the
 // bound, i.e. an undecided pair, as it should.
-constexpr int kU = 8;   // list entries per step; the next step's are loaded ahead
-
+// Entries per step (KU, the next step's loaded ahead): 8 or 4, a launch
+// parameter.  One-job launches take 8 (C2's scan: 0.33 ms against 0.38-0.40
+// with 4); launches of several jobs take 4, whose scan kernel holds 55
+// instead of 79 registers and runs 8 waves per SIMD instead of 6 (network
+// inference 1.08-1.09 s against 1.13-1.14 s with 8).
+constexpr int kU = 8;   // the largest step
 static_assert(kU <= kListPad, "a step must stay within the sentinels");
 
 template <int KMAX, int DXM>
@@ -855,31 +859,31 @@ struct Lane {
 
     // max-norm over the X columns between this lane's row and the rows of a
     // step (under the estimate's permutation); all loads issued before use
-    template <class Ent>
-    __device__ __forceinline__ void xdist(const Ent (&en)[kU], float (&d)[kU]) const {
-        uint32_t o[kU];
-        float v[kU];
+    template <class Ent, int NU>
+    __device__ __forceinline__ void xdist(const Ent (&en)[NU], float (&d)[NU]) const {
+        uint32_t o[NU];
+        float v[NU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < NU; ++u) {
             o[u] = (uint32_t)en[u].j * E + e;
             v[u] = gload(xt, o[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) d[u] = absdiff(xq[0], v[u]);
+        for (int u = 0; u < NU; ++u) d[u] = absdiff(xq[0], v[u]);
         Unroll<1, DXM>::upto(dx, [&](auto cc) {
             constexpr int c = decltype(cc)::value;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = gload(xt, c * cs + o[u]);
+            for (int u = 0; u < NU; ++u) v[u] = gload(xt, c * cs + o[u]);
 #pragma unroll
-            for (int u = 0; u < kU; ++u) d[u] = fmax_(d[u], absdiff(xq[c], v[u]));
+            for (int u = 0; u < NU; ++u) d[u] = fmax_(d[u], absdiff(xq[c], v[u]));
         });
     }
 };
 
-template <class Ent>
-__device__ __forceinline__ void load_step(const Ent *l, Ent (&en)[kU]) {
+template <class Ent, int NU>
+__device__ __forceinline__ void load_step(const Ent *l, Ent (&en)[NU]) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) en[u] = l[u];
+    for (int u = 0; u < NU; ++u) en[u] = l[u];
 }
 
 // Wave-uniform helpers of the cooperative finish.
@@ -919,8 +923,9 @@ __device__ __forceinline__ T *bcast(T *v, int o) {
 // parameters, chosen by the tuner; neither changes a result.
 constexpr int kCoopU = 1;      // list entries per lane per cooperative step
 
-template <int KMAX, int DXM>
+template <int KMAX, int DXM, int KU>
 __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
+    static_assert(KU <= kU, "a step must stay within the sentinels");
     const int lane = tid_x() & 63;
     // Lane order.  A launch of one job runs its lanes over estimate groups:
     // group c holds rows x estimates 64c .. 64c + E_c - 1, row-major, with
@@ -994,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     int seen1 = 0, seen2 = 0;     // list entries read (statistics)
     int m1 = 0;
     {
-        LEnt cur[kU];
+        LEnt cur[KU];
         load_step(l1, cur);
         while (__builtin_popcountll(ballot(act)) > coop) {
             if (!act) continue;
@@ -1002,29 +1007,29 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
                 act = false;
                 continue;
             }
-            seen1 = m1 + kU;
-            LEnt nxt[kU];
-            load_step(l1 + m1 + kU, nxt);
-            float d[kU];
+            seen1 = m1 + KU;
+            LEnt nxt[KU];
+            load_step(l1 + m1 + KU, nxt);
+            float d[KU];
             ln.xdist(cur, d);
             float lo = inf_f();
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < KU; ++u) {
                 d[u] = fmax_(d[u], cur[u].d);
                 lo = __builtin_fminf(lo, d[u]);
             }
             if (lo < top[KMAX - 1]) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) topk_insert<KMAX>(top, d[u]);
+                for (int u = 0; u < KU; ++u) topk_insert<KMAX>(top, d[u]);
             }
-            if (bucket_floor(cur[kU - 1].d) >= top[KMAX - 1]) {
+            if (bucket_floor(cur[KU - 1].d) >= top[KMAX - 1]) {
                 decided = true;
                 act = false;
                 continue;
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
-            m1 += kU;
+            for (int u = 0; u < KU; ++u) cur[u] = nxt[u];
+            m1 += KU;
         }
     }
     for (uint64_t rest = ballot(act); rest; rest &= rest - 1) {
@@ -1090,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     decided = ranked && knn_decided;
     int m2 = 0;
     {
-        LEnt2 cur[kU];
+        LEnt2 cur[KU];
         load_step(l2, cur);
         while (__builtin_popcountll(ballot(act)) > coop) {
             if (!act) continue;
@@ -1098,25 +1103,25 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
                 act = false;
                 continue;
             }
-            seen2 = m2 + kU;
-            LEnt2 nxt[kU];
-            load_step(l2 + m2 + kU, nxt);
-            float dx[kU];
+            seen2 = m2 + KU;
+            LEnt2 nxt[KU];
+            load_step(l2 + m2 + KU, nxt);
+            float dx[KU];
             ln.xdist(cur, dx);
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < KU; ++u) {
                 cz += cur[u].dz < eps;
                 cyz += cur[u].dyz < eps;
                 cxz += fmax_(dx[u], cur[u].dz) < eps;
             }
-            if (bucket_floor(cur[kU - 1].dz) >= eps) {
+            if (bucket_floor(cur[KU - 1].dz) >= eps) {
                 decided = true;
                 act = false;
                 continue;
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
-            m2 += kU;
+            for (int u = 0; u < KU; ++u) cur[u] = nxt[u];
+            m2 += KU;
         }
     }
     for (uint64_t rest = ballot(act); rest; rest &= rest - 1) {
@@ -1654,8 +1659,9 @@ __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L,
 }
 
 template <int KMAX, int DXM>
-void *scan_fn() {
-    return reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM>);
+void *scan_fn(int step) {
+    return step == 4 ? reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 4>)
+                     : reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 8>);
 }
 
 }  // namespace
@@ -1711,9 +1717,10 @@ int launch_list_scan(const ListLaunch &L, void *stream) {
     const int64_t blocks = (L.lanes + kBlock - 1) / kBlock;
     void *fn = nullptr;
     const bool wide = L.dxm > 1;
-    if (L.kmax == 4) fn = wide ? scan_fn<4, kMaxDx>() : scan_fn<4, 1>();
-    else if (L.kmax == 8) fn = wide ? scan_fn<8, kMaxDx>() : scan_fn<8, 1>();
-    else if (L.kmax == 16) fn = wide ? scan_fn<16, kMaxDx>() : scan_fn<16, 1>();
+    const int st = L.scan_step;
+    if (L.kmax == 4) fn = wide ? scan_fn<4, kMaxDx>(st) : scan_fn<4, 1>(st);
+    else if (L.kmax == 8) fn = wide ? scan_fn<8, kMaxDx>(st) : scan_fn<8, 1>(st);
+    else if (L.kmax == 16) fn = wide ? scan_fn<16, kMaxDx>(st) : scan_fn<16, 1>(st);
     else return -1;
     ListLaunch arg = L;
     void *args[] = {(void *)&arg};

@@ -513,8 +513,8 @@ int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out) {
 }
 
 // ---------------------------------------------------------------- tuning file
-// One choice per line: "mte-tune 1 <arch> <build> <key> <variant> <rs_mult>
-// <build_qb> <coop_lanes> <grouped> <ms>".  Lines of another architecture or
+// One choice per line: "mte-tune 2 <arch> <build> <key> <variant> <rs_mult>
+// <build_qb> <coop_lanes> <grouped> <scan_step> <ms>".  Lines of another architecture or
 // another build of the library are skipped, so a rebuilt library tunes anew.
 static const char *build_id() {
     static std::string id = [] {
@@ -546,10 +546,10 @@ static void load_tune_file_locked() {
         TileChoice tc;
         double ms = 0.0;
         int ver = 0;
-        if (std::sscanf(line, "mte-tune %d %127s %127s %255s %d %d %d %d %d %lf", &ver, arch, bid, key, &tc.variant,
-                        &tc.rs_mult, &tc.build_qb, &tc.coop_lanes, &tc.grouped, &ms) != 10)
+        if (std::sscanf(line, "mte-tune %d %127s %127s %255s %d %d %d %d %d %d %lf", &ver, arch, bid, key, &tc.variant,
+                        &tc.rs_mult, &tc.build_qb, &tc.coop_lanes, &tc.grouped, &tc.scan_step, &ms) != 11)
             continue;
-        if (ver != 1 || c.arch != arch || std::strcmp(bid, build_id()) != 0) continue;
+        if (ver != 2 || c.arch != arch || std::strcmp(bid, build_id()) != 0) continue;
         c.tuned[key] = tc;
         c.tune_log.push_back(Ctx::TuneNote{key, tc, ms, 1});
     }
@@ -566,8 +566,8 @@ static void save_tune_locked(const std::string &key, const TileChoice &tc, doubl
         (void)mkdir(c.tune_file.substr(0, pos).c_str(), 0755);
     FILE *f = std::fopen(c.tune_file.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "mte-tune 1 %s %s %s %d %d %d %d %d %.4f\n", c.arch.c_str(), build_id(), key.c_str(), tc.variant,
-                 tc.rs_mult, tc.build_qb, tc.coop_lanes, tc.grouped, ms);
+    std::fprintf(f, "mte-tune 2 %s %s %s %d %d %d %d %d %d %.4f\n", c.arch.c_str(), build_id(), key.c_str(), tc.variant,
+                 tc.rs_mult, tc.build_qb, tc.coop_lanes, tc.grouped, tc.scan_step, ms);
     std::fclose(f);
 }
 
@@ -579,22 +579,26 @@ static bool tuning_on() {
     return !(v && *v == '0');
 }
 
-// The shortest of three launches of `specs` with choice `tc` (after a
-// warm-up launch); negative when the launch cannot be made.
+// Time per launch of `specs` with choice `tc`: after a warm-up launch, two
+// rounds of four launches back to back (so that the gaps of one launch's
+// submission count as little as in a stream of calls), the faster round;
+// negative when the launch cannot be made.
 static double time_launch(const std::vector<JobSpec> &specs, const TileChoice &tc, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1) {
+    constexpr int kBack = 4;
     Batch b;
     if (b.prepare(specs, tc, s) != MTE_OK) return -1.0;
     if (b.enqueue_quiet(s) != MTE_OK) return -1.0;
     double best = 1e30;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 2; ++rep) {
         (void)hipEventRecord(e0, s);
-        if (b.enqueue_quiet(s) != MTE_OK) return -1.0;
+        for (int q = 0; q < kBack; ++q)
+            if (b.enqueue_quiet(s) != MTE_OK) return -1.0;
         (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        best = std::min(best, (double)ms);
+        best = std::min(best, (double)ms / kBack);
     }
     if (b.check_error(s) != MTE_OK) return -1.0;
     return best;
@@ -683,8 +687,8 @@ static int tune_pairs(const std::vector<JobSpec> &specs, hipStream_t s, int mode
 }
 
 // List knobs: the compiled-dimension build's rows per block (2, 4), the
-// scan's cooperative-finish threshold (2, 4, 8) and, for launches of one
-// job, the estimate-group lane order (on, off).
+// scan's cooperative-finish threshold (2, 4, 8), its entries per step (8, 4)
+// and, for launches of one job, the estimate-group lane order (on, off).
 static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode, TileChoice *out) {
     Ctx &c = ctx();
     const bool several = lists.size() > 1;
@@ -697,6 +701,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
             out->build_qb = it->second.build_qb;
             out->coop_lanes = it->second.coop_lanes;
             out->grouped = it->second.grouped;
+            out->scan_step = it->second.scan_step;
             return MTE_OK;
         }
     }
@@ -708,21 +713,24 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     const std::vector<JobSpec> probe = mode == kTuneBatch ? lists : std::vector<JobSpec>{rep};
     const bool lean = rep.dy == 1 && rep.dz >= 1 && rep.dz <= kBuildFixedDz && rep.n < 65536;
     std::vector<TileChoice> cand;
+    const int step0 = several ? 4 : 8;
     for (int qb : lean ? std::vector<int>{2, 4} : std::vector<int>{0})
         for (int coop : {4, 2, 8})
-            for (int grp : several ? std::vector<int>{0} : std::vector<int>{1, 0}) {
-                TileChoice tc = *out;
-                tc.build_qb = qb;
-                tc.coop_lanes = coop;
-                tc.grouped = grp;
-                cand.push_back(tc);
-            }
+            for (int grp : several ? std::vector<int>{0} : std::vector<int>{1, 0})
+                for (int step : {step0, 12 - step0}) {
+                    TileChoice tc = *out;
+                    tc.build_qb = qb;
+                    tc.coop_lanes = coop;
+                    tc.grouped = grp;
+                    tc.scan_step = step;
+                    cand.push_back(tc);
+                }
     hipEvent_t e0, e1;
     MTE_HIP(hipEventCreate(&e0));
     MTE_HIP(hipEventCreate(&e1));
     // the first candidate is the default (2 build rows, 4 lanes, the grouped
-    // order for one job); another replaces the best so far only when it is
-    // kTuneMargin faster
+    // order and 8-entry steps for one job, 4-entry steps for several);
+    // another replaces the best so far only when it is kTuneMargin faster
     double best_ms = 1e30;
     TileChoice best = cand.front();
     for (const auto &tc : cand) {
@@ -738,6 +746,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     rec.build_qb = best.build_qb;
     rec.coop_lanes = best.coop_lanes;
     rec.grouped = best.grouped;
+    rec.scan_step = best.scan_step;
     {
         std::lock_guard<std::mutex> lk(c.mu);
         save_tune_locked(key, rec, best_ms);
@@ -745,6 +754,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     out->build_qb = rec.build_qb;
     out->coop_lanes = rec.coop_lanes;
     out->grouped = rec.grouped;
+    out->scan_step = rec.scan_step;
     return MTE_OK;
 }
 
@@ -1117,6 +1127,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
     L.coop_lanes = env_int("MTE_COOP_LANES", tc.coop_lanes > 0 ? tc.coop_lanes : kCoopLanes);
     L.grouped = n_ljobs_ == 1 && env_int("MTE_GROUPED", tc.grouped != 0 ? 1 : 0) != 0 ? 1 : 0;
+    L.scan_step = env_int("MTE_SCAN_STEP", tc.scan_step > 0 ? tc.scan_step : (n_ljobs_ == 1 ? 8 : 4)) == 4 ? 4 : 8;
     L.rank_sets = rank_sets;
     L.max_rank_n = max_rank_n;
     L.rank_off = od + 3 * nj1 + 2 * (n_sets + 1);

@@ -97,6 +97,7 @@ struct TileChoice {
     int build_qb = 0;                  // rows per block of the compiled-dimension build (2 or 4)
     int coop_lanes = 0;                // the scan's cooperative-finish threshold
     int grouped = -1;                  // one-job launches: estimate-group lane order (1) or not (0)
+    int scan_step = 0;                 // the scan's entries per step (4, 8)
 };
 
 // Which path runs each job of a batch: -1 = all-pairs kernel, otherwise the
