@@ -35,87 +35,132 @@ __device__ __forceinline__ int n_rounds_dev(int64_t n) {
 // xp[e][c][i] = X_c[src_e(i)] (and, for the list path, also xt[c][i][e]) for
 // every job, estimate and row.  Rows are R = J.reps replications of nr = n/R rows
 // (R = 1: one block of all rows).  One thread block per (job, estimate,
-// replication, 1024-row chunk of the replication); the block derives one
-// swap-or-not key schedule in LDS:
+// replication, 1024-row chunk of the replication), keyed by the estimate's
+// swap-or-not schedule:
 //   replication shuffle (rep_shuffle): row (r, t) takes (sigma(r), t), sigma
 //     the permutation of {0..R-1} keyed by the estimate's hash h;
 //   within-replication shuffle: row (r, t) takes (r, pi_r(t)), pi_r the
 //     permutation of {0..nr-1} keyed by h for R = 1 and by
 //     mix64(h ^ (r+1) G) for R > 1.
-__device__ __forceinline__ uint32_t swap_or_not(uint32_t x, uint32_t n, int rounds, const uint64_t *rk,
-                                                const uint32_t *kk) {
-    for (int r = 0; r < rounds; ++r) {
-        const uint32_t k = kk[r];
-        const uint32_t xp = (x <= k) ? (k - x) : (k - x + n);
-        const uint32_t hi = x > xp ? x : xp;
-        if (dmix64((uint64_t)hi ^ rk[r]) >> 63) x = xp;
-    }
+//
+// A round r of the schedule for domain n: round key rk = mix64(hh + (r+1) G),
+// K = ((rk >> 32) n) >> 32; x pairs with x' = (K - x) mod n and takes x' when
+// the top bit of mix64(max(x, x') ^ rk) is set.  The schedule is the same for
+// every row of a block, so the round keys are computed in scalar registers once
+// per round and applied to four rows per thread.  max(x, x') < 2^32, so the
+// high word of max(x, x') ^ rk is rk's, and the first xor-shift and the high
+// half of the first product's cross terms are scalar too; of the last
+// product only the top bit is needed (the final xor-shift keeps it).
+constexpr uint32_t kMixC1Lo = 0x1CE4E5B9u, kMixC1Hi = 0xBF58476Du;
+constexpr uint32_t kMixC2Lo = 0x133111EBu, kMixC2Hi = 0x94D049BBu;
+
+struct SonRound {
+    uint32_t k, rk_lo, rk_hi, cross;   // cross = (rk_hi ^ rk_hi >> 30) * C1 low word
+};
+
+__device__ __forceinline__ SonRound son_round_key(uint64_t hh, int r, uint32_t n) {
+    const uint64_t rk = dmix64(hh + (uint64_t)(r + 1) * kGolden);
+    SonRound s;
+    s.k = (uint32_t)(((rk >> 32) * (uint64_t)n) >> 32);
+    s.rk_lo = (uint32_t)rk;
+    s.rk_hi = (uint32_t)(rk >> 32);
+    s.cross = (s.rk_hi ^ (s.rk_hi >> 30)) * kMixC1Lo;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t son_step(uint32_t x, uint32_t n, const SonRound &s) {
+    const uint32_t xp = (x <= s.k) ? (s.k - x) : (s.k - x + n);
+    const uint32_t m = x > xp ? x : xp;
+    // z = (rk_hi : m ^ rk_lo);  z ^= z >> 30
+    uint32_t lo = m ^ s.rk_lo;
+    lo ^= __builtin_amdgcn_alignbit(s.rk_hi, lo, 30);
+    // z *= C1 (mod 2^64)
+    const uint64_t p = (uint64_t)lo * kMixC1Lo;
+    uint32_t nl = (uint32_t)p;
+    uint32_t nh = (uint32_t)(p >> 32) + lo * kMixC1Hi + s.cross;
+    // z ^= z >> 27
+    nl ^= __builtin_amdgcn_alignbit(nh, nl, 27);
+    nh ^= nh >> 27;
+    // top bit of z * C2
+    const uint32_t top = (uint32_t)(((uint64_t)nl * kMixC2Lo) >> 32) + nl * kMixC2Hi + nh * kMixC2Lo;
+    return (int32_t)top < 0 ? xp : x;
+}
+
+// The whole permutation of one index (wave-uniform arguments: scalar code).
+__device__ __forceinline__ uint32_t swap_or_not(uint32_t x, uint32_t n, int rounds, uint64_t hh) {
+    for (int r = 0; r < rounds; ++r) x = son_step(x, n, son_round_key(hh, r, n));
     return x;
 }
 
-__global__ __launch_bounds__(256) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
-                                                     const int64_t *__restrict__ blk_off, int64_t total) {
-    __shared__ uint64_t s_rk[192];
-    __shared__ uint32_t s_k[192];
-    __shared__ int s_job;
-    __shared__ uint32_t s_src_rep;
-    // a grid smaller than the work takes the blocks' items in turn
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    if (threadIdx.x == 0) {
+constexpr int kPermRows = 1024;                        // rows per block
+constexpr int kPermThreads = 256;
+constexpr int kPermPer = kPermRows / kPermThreads;     // rows per thread
+
+__global__ __launch_bounds__(kPermThreads) void permute_kernel(const Job *__restrict__ jobs, int n_jobs,
+                                                              const int64_t *__restrict__ blk_off, int64_t total,
+                                                              int64_t grid) {
+    // a grid smaller than the work takes the blocks' items in turn; the
+    // indices come straight from the hardware registers (the group index is
+    // a scalar value, so everything derived from it stays wave-uniform)
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    for (int64_t b = (int64_t)__builtin_amdgcn_workgroup_id_x(); b < total; b += grid) {
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
+            const int mid = (lo + hi + 1) >> 1;
             if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
         }
-        s_job = lo;
-    }
-    __syncthreads();
-    const Job &J = jobs[s_job];
-    const int64_t local = b - blk_off[s_job];
-    const int reps = J.reps;
-    const int nr = J.n / reps;
-    const int cpr = (nr + 1023) / 1024;
-    const int e = (int)(local / ((int64_t)reps * cpr));
-    const int rem = (int)(local % ((int64_t)reps * cpr));
-    const int rep = rem / cpr;
-    const int c0 = (rem % cpr) * 1024;
-    const EstKey key = J.keys[e];
-    // key schedule: domain dn, hash hh
-    const uint32_t dn = J.rep_shuffle ? (uint32_t)reps : (uint32_t)nr;
-    const uint64_t hh = (J.rep_shuffle || reps == 1) ? key.h : dmix64(key.h ^ ((uint64_t)(rep + 1) * kGolden));
-    const int rounds = n_rounds_dev(dn);
-    if (!key.ident) {
-        for (int r = threadIdx.x; r < rounds; r += blockDim.x) {
-            uint64_t rk = dmix64(hh + (uint64_t)(r + 1) * kGolden);
-            s_rk[r] = rk;
-            s_k[r] = (uint32_t)(((rk >> 32) * (uint64_t)dn) >> 32);
+        const int job = __builtin_amdgcn_readfirstlane(lo);
+        const Job &J = jobs[job];
+        const int64_t local = b - blk_off[job];
+        const int reps = J.reps;
+        const int nr = J.n / reps;
+        const int cpr = (nr + kPermRows - 1) / kPermRows;
+        const int e = (int)(local / ((int64_t)reps * cpr));
+        const int rem = (int)(local % ((int64_t)reps * cpr));
+        const int rep = rem / cpr;
+        const int c0 = (rem % cpr) * kPermRows;
+        const EstKey key = J.keys[e];
+        // key schedule: domain dn, hash hh
+        const uint32_t dn = J.rep_shuffle ? (uint32_t)reps : (uint32_t)nr;
+        const uint64_t hh = (J.rep_shuffle || reps == 1) ? key.h : dmix64(key.h ^ ((uint64_t)(rep + 1) * kGolden));
+        const int rounds = n_rounds_dev(dn);
+        // the divisions above leave these uniform values in vector registers;
+        // read back into scalar ones, the round keys are computed by the
+        // scalar unit
+        const uint64_t hs = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(hh >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)hh);
+        const uint32_t dns = (uint32_t)__builtin_amdgcn_readfirstlane((int)dn);
+        const int rs = __builtin_amdgcn_readfirstlane(rounds);
+        const int64_t base = (int64_t)rep * nr;
+        uint32_t src[kPermPer];
+#pragma unroll
+        for (int q = 0; q < kPermPer; ++q) src[q] = (uint32_t)min(c0 + tid + q * kPermThreads, nr - 1);
+        // source row of row base + t: xbase + src
+        int64_t xbase = base;
+        if (key.ident) {
+        } else if (J.rep_shuffle) {
+            xbase = (int64_t)swap_or_not((uint32_t)rep, dns, rs, hs) * nr;
+        } else {
+            for (int r = 0; r < rs; ++r) {
+                const SonRound s = son_round_key(hs, r, dns);
+#pragma unroll
+                for (int q = 0; q < kPermPer; ++q) src[q] = son_step(src[q], dns, s);
+            }
         }
-    }
-    __syncthreads();
-    if (J.rep_shuffle && threadIdx.x == 0)
-        s_src_rep = key.ident ? (uint32_t)rep : swap_or_not((uint32_t)rep, dn, rounds, s_rk, s_k);
-    __syncthreads();
-    const int64_t base = (int64_t)rep * nr;
-    for (int ii = threadIdx.x; ii < 1024; ii += blockDim.x) {
-        const int t = c0 + ii;
-        if (t >= nr) break;
-        const int64_t i = base + t;
-        int64_t x;
-        if (key.ident)
-            x = i;
-        else if (J.rep_shuffle)
-            x = (int64_t)s_src_rep * nr + t;
-        else
-            x = base + swap_or_not((uint32_t)t, dn, rounds, s_rk, s_k);
-        const int64_t ri = J.xr ? (int64_t)min(max(J.zrank[i], 0), J.n - 1) : 0;
-        for (int c = 0; c < J.dx; ++c) {
-            const float v = J.cols[c][x];
-            if (J.xt) J.xt[((int64_t)c * J.n + i) * J.n_est + e] = v;
-            J.xp[((int64_t)e * J.dx + c) * J.n + i] = v;
-            if (J.xr) J.xr[((int64_t)e * J.dx + c) * J.n + ri] = v;
+#pragma unroll
+        for (int q = 0; q < kPermPer; ++q) {
+            const int t = c0 + tid + q * kPermThreads;
+            if (t >= nr) break;
+            const int64_t i = base + t;
+            const int64_t x = xbase + (int64_t)src[q];
+            const int64_t ri = J.xr ? (int64_t)min(max(J.zrank[i], 0), J.n - 1) : 0;
+            for (int c = 0; c < J.dx; ++c) {
+                const float v = J.cols[c][x];
+                if (J.xt) J.xt[((int64_t)c * J.n + i) * J.n_est + e] = v;
+                J.xp[((int64_t)e * J.dx + c) * J.n + i] = v;
+                if (J.xr) J.xr[((int64_t)e * J.dx + c) * J.n + ri] = v;
+            }
         }
-    }
-    __syncthreads();   // the next item rewrites the key schedule
     }
 }
 
@@ -181,8 +226,8 @@ int launch_permute(const Job *jobs_dev, int n_jobs, int64_t total_blocks, const 
                    void *stream, int64_t max_grid) {
     if (total_blocks <= 0) return 0;
     const int64_t grid = max_grid > 0 && max_grid < total_blocks ? max_grid : total_blocks;
-    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, jobs_dev,
-                       n_jobs, blk_off, total_blocks);
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)grid), dim3(kPermThreads), 0, (hipStream_t)stream, jobs_dev,
+                       n_jobs, blk_off, total_blocks, grid);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -117,6 +117,14 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
+// The build shares the CUs with the surrogate permutation (a second stream),
+// and both are bound by instruction issue; the scan needs both.  The build's
+// waves take the issue arbiter's highest priority, so that the permutation,
+// held to a few blocks per CU, runs in the build's idle issue cycles instead
+// of stretching it: at N = 10^4 with 201 estimates the pair finishes
+// together in 0.25 ms instead of 0.28.
+constexpr int kBuildPrio = 3;
+
 // Threads per build block: 8 waves, so that the 4 blocks whose histograms fit
 // in LDS keep 8 waves on every SIMD (the kernel waits mostly on LDS atomics
 // and L2 loads, and needs the waves to hide them).
@@ -282,6 +290,7 @@ __global__ __launch_bounds__(kBT) void list_build_kernel(const ListSet *__restri
                                                            const int64_t *__restrict__ blk_off) {
     using Sm = BuildSmem<QB, C, PACK>;
     __shared__ Sm sm;
+    __builtin_amdgcn_s_setprio(kBuildPrio);
     const int tid = tid_x();
     const int copy = tid & (C - 1);
     const int64_t b = bid_x();
@@ -457,6 +466,7 @@ template <int DZ, int QB>
 __global__ __launch_bounds__(kBT) void list_build_dz_kernel(const ListSet *__restrict__ sets, int n_sets,
                                                             const int64_t *__restrict__ blk_off) {
     __shared__ LeanSmem<QB> sm;
+    __builtin_amdgcn_s_setprio(kBuildPrio);
     const int tid = tid_x(), lane = tid & 63, wave = tid >> 6;
     const int64_t b = bid_x();
     if (tid == 0) sm.set = find_job(blk_off, n_sets, b);

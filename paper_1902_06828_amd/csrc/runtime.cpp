@@ -573,6 +573,18 @@ static void save_tune_locked(const std::string &key, const TileChoice &tc, doubl
 
 // ---------------------------------------------------------------- tuning
 constexpr double kTuneMargin = 0.97;   // a candidate must be 3% faster to replace the best
+// Wall time one shape's tuning may take (MTE_TUNE_BUDGET_MS overrides): the
+// candidates are timed in order of how far they are from the default, and
+// the search stops when the budget is spent.  A shape whose launch takes
+// tens of milliseconds then keeps the default or a choice one knob away,
+// instead of spending seconds on the full candidate set.
+constexpr int kTuneBudgetMs = 400;
+
+static double tune_budget_s() { return env_int("MTE_TUNE_BUDGET_MS", kTuneBudgetMs) * 1e-3; }
+
+static double wall_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 static bool tuning_on() {
     const char *v = std::getenv("MTE_TUNE");
@@ -666,9 +678,11 @@ static int tune_pairs(const std::vector<JobSpec> &specs, hipStream_t s, int mode
     // the heuristic choice stands unless a candidate is kTuneMargin faster,
     // so that near ties resolve the same way from one run to the next
     TileChoice best = heur;
+    const double t_end = wall_s() + tune_budget_s();
     double best_ms = time_launch(specs, heur, s, e0, e1);
     if (best_ms < 0.0) best_ms = 1e30;
     for (const auto &tc : cand) {
+        if (wall_s() > t_end) break;
         const double ms = time_launch(specs, tc, s, e0, e1);
         if (ms >= 0.0 && ms < best_ms * kTuneMargin) {
             best_ms = ms;
@@ -713,7 +727,8 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     const std::vector<JobSpec> probe = mode == kTuneBatch ? lists : std::vector<JobSpec>{rep};
     const bool lean = rep.dy == 1 && rep.dz >= 1 && rep.dz <= kBuildFixedDz && rep.n < 65536;
     std::vector<TileChoice> cand;
-    const int step0 = several ? 4 : 8;
+    std::vector<int> away;   // knobs that differ from the default
+    const int step0 = several ? 4 : 8, qb0 = lean ? 2 : 0, grp0 = several ? 0 : 1;
     for (int qb : lean ? std::vector<int>{2, 4} : std::vector<int>{0})
         for (int coop : {4, 2, 8})
             for (int grp : several ? std::vector<int>{0} : std::vector<int>{1, 0})
@@ -724,7 +739,12 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
                     tc.grouped = grp;
                     tc.scan_step = step;
                     cand.push_back(tc);
+                    away.push_back((qb != qb0) + (coop != 4) + (grp != grp0) + (step != step0));
                 }
+    // the default first, then one knob away, two, ... (stable within a distance)
+    std::vector<size_t> order(cand.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return away[a] < away[b]; });
     hipEvent_t e0, e1;
     MTE_HIP(hipEventCreate(&e0));
     MTE_HIP(hipEventCreate(&e1));
@@ -732,8 +752,11 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     // order and 8-entry steps for one job, 4-entry steps for several);
     // another replaces the best so far only when it is kTuneMargin faster
     double best_ms = 1e30;
-    TileChoice best = cand.front();
-    for (const auto &tc : cand) {
+    TileChoice best = cand[order.front()];
+    const double t_end = wall_s() + tune_budget_s();
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        if (oi > 0 && wall_s() > t_end) break;
+        const TileChoice &tc = cand[order[oi]];
         const double ms = time_launch(probe, tc, s, e0, e1);
         if (ms >= 0.0 && ms < best_ms * (best_ms < 1e30 ? kTuneMargin : 1.0)) {
             best_ms = ms;
@@ -1395,10 +1418,14 @@ int Batch::prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t
     return MTE_OK;
 }
 
-// Blocks per CU of the permutation that runs beside the build: a few, so
-// that the build keeps nearly all its waves and the permutation's ALU work
-// fills the build's waits on LDS and L2.
-constexpr int kPermuteBlocksPerCu = 2;
+// Blocks per CU (4 waves each) of the permutation that runs beside the build
+// (MTE_PERMUTE_BLOCKS_PER_CU overrides; 0 = uncapped).  The build's waves
+// have the higher issue priority, so the cap only sets how many wave slots
+// the permutation holds: at N = 10^4 with 201 estimates, 2 per CU left the
+// permutation last (0.27 ms beside a 0.23 ms build), 5 or more took wave
+// slots from the build (0.27-0.28 ms), 3-4 let both end at 0.24-0.25 ms
+// (3 was the faster in a stream of synchronised test calls).
+constexpr int kPermuteBlocksPerCu = 3;
 
 // Launch sequence: the all-pairs part (reset, permute, main kernel), then
 // the list part (reset, Y,Z copy; permute into xt on the side stream beside
@@ -1461,7 +1488,8 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if ((rc = begin(side))) return rc;
         // capped only while the permutation is the smaller part: a launch of
         // many estimates over few list sets has more permutation than build
-        const int64_t pgrid = lpermute_blocks_ <= ll_.build_blocks ? (int64_t)kPermuteBlocksPerCu * ctx().n_cu : 0;
+        const int pcu = env_int("MTE_PERMUTE_BLOCKS_PER_CU", kPermuteBlocksPerCu);
+        const int64_t pgrid = pcu > 0 && lpermute_blocks_ <= ll_.build_blocks ? (int64_t)pcu * ctx().n_cu : 0;
         if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side, pgrid))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute, side))) return rc;
