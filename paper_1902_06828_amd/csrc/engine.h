@@ -148,6 +148,7 @@ constexpr int kBuildRows = 2;                // rows per build block when N <= 2
 constexpr int kLeanRows = 2;                 // rows per block of the compiled-dimension build
 // Compiled-dimension build: dz <= kBuildFixedDz Z columns and one Y column.
 constexpr int kBuildFixedDz = 12;
+constexpr int kXcds = 8;   // accelerator complex dies (one L2 each) of an MI355X
 constexpr int kBuildCopies = 1;              // histogram copies per row (spread LDS atomics)
 constexpr int kListStatWord = 16;
 constexpr int kListStatSlots = 64;            // spread so that the atomics do not queue on one address
@@ -185,7 +186,18 @@ struct ListLaunch {
     int max_chunks;               // largest ceil(n / kChunk) of the jobs (reduction grid)
     int sortx;                    // some job has no Z: sort the X columns (Job::xs)
     int coop_lanes;               // the scan finishes cooperatively once this many lanes remain
-    int grouped;                  // one job: lanes over 64-estimate groups, XCD-contiguous blocks
+    int grouped;                  // 1 (one job): lanes over 64-estimate groups, XCD-contiguous
+                                  // blocks; 2 (several jobs): XCD-dealt units, below
+    // grouped == 2: unit u = (job, 64-estimate group of the job, the last one
+    // taking the remainder), its lanes row-major in the set's row order and
+    // padded to whole blocks, runs on XCD u % kXcds.  xcd_off[x * (unit_t + 1)
+    // + t] is the first block, counting XCD x's blocks alone, of x's t-th unit
+    // (unit x + t * kXcds; the entry at t = unit_t, and past x's last unit,
+    // is x's block count); unit_info[u] = job << 32 | group.
+    const int64_t *xcd_off;
+    const int64_t *unit_info;
+    int unit_t, n_units;
+    int64_t scan_blocks;          // grid of the scan
     int scan_step;                // list entries per step of the scan's lane-by-lane loops (4, 8)
     int rank_sets;                // sets counted by ranks (ListSet::zs)
     int64_t rank_waves;           // rank-count waves: sum over those sets' jobs of

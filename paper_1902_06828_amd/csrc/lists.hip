@@ -89,7 +89,6 @@ __device__ __forceinline__ float gload_b(const float *p, uint32_t byte_off) {
 }
 
 constexpr uint64_t kPackMask = (uint64_t(1) << kPackBits) - 1;
-constexpr int kXcds = 8;   // accelerator complex dies (one L2 each) of an MI355X
 
 __device__ __forceinline__ uint64_t pack_counts(int cxz, int cyz, int cz) {
     return (uint64_t)(uint32_t)cxz | ((uint64_t)(uint32_t)cyz << kPackBits) |
@@ -898,6 +897,11 @@ __device__ __forceinline__ void load_step(const Ent *l, Ent (&en)[NU]) {
 
 // Wave-uniform helpers of the cooperative finish.
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// The lane mask of one compare as the compare writes it (no round trip of the
+// predicate through a vector register); masks are combined by the scalar unit.
+// (The scan keeps ballot(): with this form its one-job launch at N = 10^4 took
+// 0.343 ms instead of 0.329.)
+__device__ __forceinline__ uint64_t cmp_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ int lowest(uint64_t m) { return __builtin_amdgcn_readfirstlane(__builtin_ctzll(m)); }
 __device__ __forceinline__ float bcast(float v, int o) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), o));
@@ -933,7 +937,11 @@ __device__ __forceinline__ T *bcast(T *v, int o) {
 // parameters, chosen by the tuner; neither changes a result.
 constexpr int kCoopU = 1;      // list entries per lane per cooperative step
 
-template <int KMAX, int DXM, int KU>
+// UNITS: the lane order of launches of several jobs below (a separate
+// instance, so that the other orders' kernels keep their registers: with both
+// mappings in one kernel the one-job scan took 81 registers instead of 79, 5
+// waves per SIMD instead of 6, and 0.342 ms instead of 0.328 at N = 10^4).
+template <int KMAX, int DXM, int KU, bool UNITS>
 __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     static_assert(KU <= kU, "a step must stay within the sentinels");
     const int lane = tid_x() & 63;
@@ -945,12 +953,15 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
     // XCDs in turn; block b is renumbered so that each XCD takes a contiguous
     // range of lanes, i.e. one or two groups, and its L2 holds those groups'
     // columns of xt (n * 256 bytes each) instead of all of them.  A launch of
-    // several jobs keeps the hardware order and lane = row * E + estimate,
-    // rows taken in the set's Morton order: unequal jobs then spread over all
-    // XCDs, the waves of a row are neighbours, sharing its list entries, and
-    // rows that run together are near in (Y,Z), so that many of the X values
-    // they gather are the same.
-    const bool grouped = L.grouped != 0;          // set by the host for launches of one job only
+    // several jobs runs its lanes over units of (job, estimate group), each
+    // row-major over the group's estimates with the rows in the set's Morton
+    // order (rows that run together are near in (Y,Z), so their list entries
+    // and the X values they gather overlap), and deals the units to the XCDs
+    // in turn (unit u to XCD u mod 8, each XCD taking its units one after
+    // another): an XCD's L2 then holds the xt columns of the group it is on
+    // (n * 256 bytes) instead of gathering over whole jobs' xt (n * E * 4
+    // bytes each), and unequal jobs still spread over all XCDs.
+    const bool grouped = L.grouped == 1;          // set by the host for launches of one job only
     const int coop = L.coop_lanes;
     int64_t b = bid_x();
     if (grouped) {
@@ -958,16 +969,47 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
         const int64_t q = nb / kXcds, rem = nb % kXcds, x = hb % kXcds;
         b = x * q + min(x, rem) + hb / kXcds;
     }
+    bool live;
+    int64_t g;
+    int jb, i, e;
+    if constexpr (UNITS) {
+        // XCD x's k-th block: the last of x's units whose first block is <= k
+        const int x = (int)(b % kXcds);
+        const int64_t k = b / kXcds;
+        const int64_t *xo = L.xcd_off + (int64_t)x * (L.unit_t + 1);
+        if (k >= xo[L.unit_t]) return;            // past x's blocks (no barrier in this kernel)
+        int lo = 0, hi = L.unit_t - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (xo[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const int u = x + lo * kXcds;
+        const int64_t info = L.unit_info[u];
+        jb = (int)(info >> 32);
+        const int grp = (int)(info & 0xffffffff);
+        const Job &Ju = L.jobs[jb];
+        const int ng = max(1, Ju.n_est / 64);
+        const int eg = grp == ng - 1 ? Ju.n_est - 64 * grp : 64;
+        const int64_t ul = (int64_t)Ju.n * eg;
+        const int64_t l0 = (k - xo[lo]) * kBlock + tid_x();
+        // lanes past the unit's last pair mirror it and store nothing
+        live = l0 < ul;
+        const int64_t lu = live ? l0 : ul - 1;
+        const int il = (int)(lu / eg);
+        e = 64 * grp + (int)(lu - (int64_t)il * eg);
+        const ListSet &Su = L.sets[Ju.set];
+        i = Su.order ? Su.order[il] : il;
+        g = L.lane_off[jb] + (int64_t)il * Ju.n_est + e;
+    } else {
     const int64_t g0 = b * kBlock + tid_x();
     // every lane of a wave takes part in the cooperative steps: lanes past
     // the last pair mirror it and store nothing
-    const bool live = g0 < L.lanes;
-    const int64_t g = live ? g0 : L.lanes - 1;
-    const int jb = find_job(L.lane_off, L.n_jobs, g);
-    const Job &J = L.jobs[jb];
-    const ListSet &S = L.sets[J.set];
-    int i, e;
+    live = g0 < L.lanes;
+    g = live ? g0 : L.lanes - 1;
+    jb = find_job(L.lane_off, L.n_jobs, g);
     {
+        const Job &J = L.jobs[jb];
+        const ListSet &S = L.sets[J.set];
         const int64_t r = g - L.lane_off[jb];
         if (grouped) {
             const int64_t gsz = (int64_t)J.n * 64;
@@ -983,6 +1025,9 @@ __global__ __launch_bounds__(kBlock) void list_scan_kernel(const ListLaunch L) {
             i = S.order ? S.order[il] : il;
         }
     }
+    }
+    const Job &J = L.jobs[jb];
+    const ListSet &S = L.sets[J.set];
     const int n = J.n;
     Lane<KMAX, DXM> ln(J, i, e);
 
@@ -1354,29 +1399,42 @@ __global__ __launch_bounds__(kRankThreads) void list_rank_count_kernel(const Lis
         constexpr int kRankU = DXM == 1 ? 4 : 1;
         for (int q = plo; q < phi; q += 64 * kRankU) {
             bool in[kRankU];
-            int mm[kRankU];
+            uint32_t bo[kRankU];
             float y[kRankU], x0[kRankU];
 #pragma unroll
             for (int u = 0; u < kRankU; ++u) {
                 const int m = q + 64 * u + lane;
                 in[u] = m < phi;
-                mm[u] = in[u] ? m : phi - 1;
-                y[u] = yr[mm[u]];
-                x0[u] = xr[mm[u]];
+                // byte offsets from the wave-uniform bases: the loads take
+                // no 64-bit address arithmetic
+                bo[u] = (uint32_t)(in[u] ? m : phi - 1) * 4u;
+                y[u] = gload_b(yr, bo[u]);
+                x0[u] = gload_b(xr, bo[u]);
             }
 #pragma unroll
             for (int u = 0; u < kRankU; ++u) {
                 float d = absdiff(x0[u], px[0]);
                 Unroll<1, DXM>::upto(dx, [&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    d = fmax_(d, absdiff(xr[(int64_t)c * n + mm[u]], px[c]));
+                    d = fmax_(d, absdiff(gload_b(xr + (int64_t)c * n, bo[u]), px[c]));
                 });
-                cy += __builtin_popcountll(ballot(in[u] && absdiff(y[u], py) < pe));
-                cx += __builtin_popcountll(ballot(in[u] && d < pe));
+                // the masks of single compares, combined by the scalar unit
+                const uint64_t inm = cmp_mask(in[u]);
+                cy += __builtin_popcountll(inm & cmp_mask(absdiff(y[u], py) < pe));
+                cx += __builtin_popcountll(inm & cmp_mask(d < pe));
             }
         }
         int cz = phi - plo;
+        // without a Theiler window only the pair's own row is taken out: it
+        // is in the range and within eps in y and x exactly when eps > 0
+        // (its differences are all 0), else the range is empty
         const int w0 = max(0, pi - J.theiler), w1 = min(n - 1, pi + J.theiler);
+        if (J.theiler == 0) {
+            const int own = pe > 0.f ? 1 : 0;
+            cz -= own;
+            cy -= own;
+            cx -= own;
+        } else
         for (int j = w0 + lane; j - lane <= w1; j += 64) {
             const bool inw = j <= w1;
             const int rj = min(max(S.zrank[inw ? j : w1], 0), n - 1);
@@ -1669,9 +1727,12 @@ __global__ __launch_bounds__(kBlock) void list_reduce_kernel(const ListLaunch L,
 }
 
 template <int KMAX, int DXM>
-void *scan_fn(int step) {
-    return step == 4 ? reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 4>)
-                     : reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 8>);
+void *scan_fn(int step, bool units) {
+    if (units)
+        return step == 4 ? reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 4, true>)
+                         : reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 8, true>);
+    return step == 4 ? reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 4, false>)
+                     : reinterpret_cast<void *>(&list_scan_kernel<KMAX, DXM, 8, false>);
 }
 
 }  // namespace
@@ -1724,13 +1785,14 @@ int launch_list_build(const ListLaunch &L, void *stream) {
 
 int launch_list_scan(const ListLaunch &L, void *stream) {
     if (L.lanes <= 0) return 0;
-    const int64_t blocks = (L.lanes + kBlock - 1) / kBlock;
+    const int64_t blocks = L.grouped == 2 ? L.scan_blocks : (L.lanes + kBlock - 1) / kBlock;
     void *fn = nullptr;
     const bool wide = L.dxm > 1;
     const int st = L.scan_step;
-    if (L.kmax == 4) fn = wide ? scan_fn<4, kMaxDx>(st) : scan_fn<4, 1>(st);
-    else if (L.kmax == 8) fn = wide ? scan_fn<8, kMaxDx>(st) : scan_fn<8, 1>(st);
-    else if (L.kmax == 16) fn = wide ? scan_fn<16, kMaxDx>(st) : scan_fn<16, 1>(st);
+    const bool un = L.grouped == 2;
+    if (L.kmax == 4) fn = wide ? scan_fn<4, kMaxDx>(st, un) : scan_fn<4, 1>(st, un);
+    else if (L.kmax == 8) fn = wide ? scan_fn<8, kMaxDx>(st, un) : scan_fn<8, 1>(st, un);
+    else if (L.kmax == 16) fn = wide ? scan_fn<16, kMaxDx>(st, un) : scan_fn<16, 1>(st, un);
     else return -1;
     ListLaunch arg = L;
     void *args[] = {(void *)&arg};

@@ -38,6 +38,20 @@ static size_t round_size(size_t b) {
     return (b + g - 1) / g * g;
 }
 
+// Released blocks stay cached for reuse up to a quarter of the device's
+// memory (a block released past that is freed), and a new block is taken
+// only with kDeviceReserve of device memory left beside it (else the cache is
+// freed first): the HIP runtime allocates kernels' scratch (spill) memory on
+// its own, and a device filled by cached blocks leaves it none, which aborts
+// the queue.
+constexpr size_t kDeviceReserve = size_t(4) << 30;
+
+void DeviceAllocator::free_cached_locked() {
+    for (auto &kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    cached_ = 0;
+}
+
 void *DeviceAllocator::alloc(size_t bytes) {
     bytes = round_size(bytes ? bytes : 1);
     std::lock_guard<std::mutex> lk(mu_);
@@ -49,11 +63,17 @@ void *DeviceAllocator::alloc(size_t bytes) {
         got = it->first;
         cached_ -= got;
         free_.erase(it);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        live_[p] = got;
+        in_use_ += got;
+        peak_ = std::max(peak_, in_use_);
+        return p;
+    }
+    size_t dev_free = 0, dev_total = 0;
+    if (!free_.empty() && hipMemGetInfo(&dev_free, &dev_total) == hipSuccess && dev_free < bytes + kDeviceReserve)
+        free_cached_locked();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        for (auto &kv : free_) (void)hipFree(kv.second);
-        free_.clear();
-        cached_ = 0;
+        free_cached_locked();
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
@@ -72,15 +92,21 @@ void DeviceAllocator::release(void *p, size_t bytes) {
     const size_t got = it != live_.end() ? it->second : round_size(bytes ? bytes : 1);
     if (it != live_.end()) live_.erase(it);
     in_use_ -= got;
+    if (cache_cap_ == 0) {
+        size_t dev_free = 0, dev_total = 0;
+        cache_cap_ = hipMemGetInfo(&dev_free, &dev_total) == hipSuccess ? dev_total / 4 : size_t(16) << 30;
+    }
+    if (cached_ + got > cache_cap_) {
+        (void)hipFree(p);
+        return;
+    }
     cached_ += got;
     free_.emplace(got, p);
 }
 
 void DeviceAllocator::trim() {
     std::lock_guard<std::mutex> lk(mu_);
-    for (auto &kv : free_) (void)hipFree(kv.second);
-    free_.clear();
-    cached_ = 0;
+    free_cached_locked();
 }
 
 DevBuf::~DevBuf() { reset(); }
@@ -924,6 +950,38 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         dxm = std::max(dxm, sp.dx);
         n_keys += sp.n_est();
     }
+    // a launch of several jobs: the scan's units of (job, 64-estimate group),
+    // dealt to the XCDs in turn (MTE_GROUPED_MANY=0: job-major lanes in the
+    // hardware order instead)
+    const bool units = n_ljobs_ > 1 && env_int("MTE_GROUPED_MANY", 1) != 0;
+    std::vector<int64_t> unit_info, unit_blocks, xcd_off;
+    int unit_t = 0;
+    int64_t scan_blocks = 0;
+    if (units) {
+        for (int j = 0; j < n_ljobs_; ++j) {
+            const JobSpec &sp = specs[j];
+            const int ng = std::max(1, sp.n_est() / 64);
+            for (int grp = 0; grp < ng; ++grp) {
+                const int eg = grp == ng - 1 ? sp.n_est() - 64 * grp : 64;
+                unit_info.push_back((int64_t)j << 32 | grp);
+                unit_blocks.push_back(((int64_t)sp.n * eg + kBlock - 1) / kBlock);
+            }
+        }
+        const int nu = (int)unit_info.size();
+        unit_t = (nu + kXcds - 1) / kXcds;
+        xcd_off.assign((size_t)kXcds * (unit_t + 1), 0);
+        for (int x = 0; x < kXcds; ++x) {
+            int64_t acc = 0;
+            for (int t = 0; t < unit_t; ++t) {
+                xcd_off[(size_t)x * (unit_t + 1) + t] = acc;
+                const int u = x + t * kXcds;
+                if (u < nu) acc += unit_blocks[u];
+            }
+            xcd_off[(size_t)x * (unit_t + 1) + unit_t] = acc;
+            scan_blocks = std::max(scan_blocks, acc);
+        }
+        scan_blocks *= kXcds;
+    }
     // scratch layout: per set its lists and Y,Z copy; per job xt, xp, the
     // packed counts and the chunk sums; then the queue
     size_t bytes = 0;
@@ -1020,7 +1078,9 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     const size_t t_jobs = align_up(sizeof(Job) * n_ljobs_, 256);
     const size_t t_sets = align_up(sizeof(ListSet) * n_sets, 256);
     const size_t t_keys = align_up(sizeof(EstKey) * (size_t)n_keys, 256);
-    const size_t t_offs = align_up(sizeof(int64_t) * (5 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1)), 256);
+    const size_t t_offs = align_up(sizeof(int64_t) * (5 * (size_t)(n_ljobs_ + 1) + 2 * ((size_t)n_sets + 1) +
+                                                      xcd_off.size() + unit_info.size()),
+                                   256);
     const size_t tbytes = t_jobs + t_sets + t_keys + t_offs;
     if (measure) {
         *measure += bytes + sizeof(uint32_t) * kListCounterWords + tbytes;
@@ -1118,6 +1178,10 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     std::memcpy(oh + 3 * nj1, row_off.data(), sizeof(int64_t) * (n_sets + 1));
     std::memcpy(oh + 3 * nj1 + (n_sets + 1), build_off.data(), sizeof(int64_t) * (n_sets + 1));
     std::memcpy(oh + 3 * nj1 + 2 * (n_sets + 1), rank_off.data(), sizeof(int64_t) * nj1);
+    const size_t o_units = 4 * nj1 + 2 * ((size_t)n_sets + 1);
+    if (!xcd_off.empty()) std::memcpy(oh + o_units, xcd_off.data(), sizeof(int64_t) * xcd_off.size());
+    if (!unit_info.empty())
+        std::memcpy(oh + o_units + xcd_off.size(), unit_info.data(), sizeof(int64_t) * unit_info.size());
     ljobs_dev_ = reinterpret_cast<Job *>(tb);
     lblk_off_ = od + 2 * nj1;
     lpermute_blocks_ = blk_off[n_ljobs_];
@@ -1149,7 +1213,12 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.sortx = 0;
     for (const JobSpec &sp : specs) L.sortx |= sp.dz == 0;
     L.coop_lanes = env_int("MTE_COOP_LANES", tc.coop_lanes > 0 ? tc.coop_lanes : kCoopLanes);
-    L.grouped = n_ljobs_ == 1 && env_int("MTE_GROUPED", tc.grouped != 0 ? 1 : 0) != 0 ? 1 : 0;
+    L.grouped = units ? 2 : (n_ljobs_ == 1 && env_int("MTE_GROUPED", tc.grouped != 0 ? 1 : 0) != 0 ? 1 : 0);
+    L.xcd_off = units ? od + o_units : nullptr;
+    L.unit_info = units ? od + o_units + xcd_off.size() : nullptr;
+    L.unit_t = unit_t;
+    L.n_units = (int)unit_info.size();
+    L.scan_blocks = scan_blocks;
     L.scan_step = env_int("MTE_SCAN_STEP", tc.scan_step > 0 ? tc.scan_step : (n_ljobs_ == 1 ? 8 : 4)) == 4 ? 4 : 8;
     L.rank_sets = rank_sets;
     L.max_rank_n = max_rank_n;

@@ -43,10 +43,12 @@ public:
     size_t cached() const { return cached_; }
     void reset_peak() { peak_ = in_use_; }
 private:
+    void free_cached_locked();
     std::mutex mu_;
     std::multimap<size_t, void *> free_;
     std::map<void *, size_t> live_;     // block sizes of the blocks handed out
     size_t in_use_ = 0, peak_ = 0, cached_ = 0;
+    size_t cache_cap_ = 0;              // cached bytes kept at most (set on first release)
 };
 
 // RAII device buffer from the context allocator.
