@@ -749,8 +749,12 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     int64_t pairs = 0;
     for (const auto &sp : lists) pairs += (int64_t)sp.n * sp.n_est();
     if (mode == kTuneShape && pairs < kTuneMinPairs) return MTE_OK;
-    // the launch timed: the batch itself, or one job of its first shape
-    const std::vector<JobSpec> probe = mode == kTuneBatch ? lists : std::vector<JobSpec>{rep};
+    // the launch timed: the batch itself, or one job of its first shape (two
+    // copies of it for a launch of several jobs, so that the probe takes the
+    // several-job scan, whose registers and lane order differ; the copies
+    // write the same values to the same outputs)
+    const std::vector<JobSpec> probe =
+        mode == kTuneBatch ? lists : (several ? std::vector<JobSpec>{rep, rep} : std::vector<JobSpec>{rep});
     const bool lean = rep.dy == 1 && rep.dz >= 1 && rep.dz <= kBuildFixedDz && rep.n < 65536;
     std::vector<TileChoice> cand;
     std::vector<int> away;   // knobs that differ from the default
