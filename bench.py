@@ -250,7 +250,7 @@ def c5_leg(mte, budget=2 << 30, window=2000, p_nodes=100):
             "searches_completed_in_window": len(done), "other_errors": [c for c in errors if c != mte._lib.MTE_ECANCELED]}
 
 
-def served(mte, torch, n_burst=48, n_poisson=96, load=0.8):
+def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
     """Requests of N in {1000, 3000, 10000}, Z dim 1..15, S = 200 over a
     100-node coupled-logistic-map network: a burst for saturation throughput
     (after an untimed burst of the same mix, whose rate is reported as the

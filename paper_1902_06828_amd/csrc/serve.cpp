@@ -65,6 +65,14 @@ struct Slot {
 
 constexpr int kSlots = 3;
 constexpr size_t kMaxBatchRequests = 512;
+// Device memory of one batch at most (MTE_BATCH_BYTES_MAX overrides), above
+// which a batch of several requests is halved: requests with lists of their
+// own (a served mix of unrelated conditioning sets) made batches of 85-128
+// requests and 70-120 GB in a burst of 768, whose blocks the allocator's
+// cache could not supply, and the re-allocation of tens of GB stretched such
+// bursts from 0.22 s to 2.4-4.9 s; batches of about ten requests already
+// keep the device busy.
+constexpr size_t kMaxBatchBytes = size_t(16) << 30;
 
 class Server {
 public:
@@ -213,6 +221,11 @@ public:
     void admit(Slot &s) {
         if (mem_blocked) return;
         const size_t budget = ctx().budget;
+        static const size_t batch_cap = [] {
+            const char *v = std::getenv("MTE_BATCH_BYTES_MAX");
+            const long long b = v && *v ? std::atoll(v) : 0;
+            return b > 0 ? (size_t)b : kMaxBatchBytes;
+        }();
         group_front();
         size_t take = std::min(queue.size(), kMaxBatchRequests);
         while (take > 0) {
@@ -237,6 +250,10 @@ public:
             if (rc == MTE_OK) rc = b->prepare(specs, tc, s.stream, &need);
             if (rc != MTE_OK) return fail_front(take, rc, "batch preparation failed");
             const size_t bytes = need + sizeof(double) * n_out;
+            if (take > 1 && bytes > batch_cap) {
+                take /= 2;
+                continue;
+            }
             if (bytes_in_flight + bytes > budget) {
                 if (take > 1) {
                     take /= 2;
