@@ -415,7 +415,10 @@ int mte_link_metrics(const uint8_t *inferred, const uint8_t *truth, int P, int64
  * At most three batches are in flight, each on its own stream; the
  * environment variable MTE_SERVE_SLOTS=1|2|3, read when the loop starts,
  * lowers that limit (1 runs the batches one after another, for attributing
- * time to kernels); results do not depend on it.
+ * time to kernels); results do not depend on it.  A batch of several
+ * requests is halved while it needs more than 16 GiB of device memory
+ * (MTE_BATCH_BYTES_MAX, in bytes, read once, overrides); a single request
+ * above that still runs alone if it fits the HBM budget.
  * ------------------------------------------------------------------------ */
 
 /* Upload data [P][T] (host, row-major) and keep it resident.  *sid_out >= 0. */
