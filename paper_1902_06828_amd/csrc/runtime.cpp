@@ -943,6 +943,8 @@ static void list_caps(int dx, int dy, int dz, int n, int *m1, int *m2) {
     }
 }
 
+constexpr int kUnitsPerXcd = 4;   // fewest scan units per XCD for the XCD-dealt order
+
 int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<int> &set_of, int n_sets,
                          const TileChoice &tc, hipStream_t s, size_t *measure) {
     Ctx &c = ctx();
@@ -965,9 +967,14 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
         n_keys += sp.n_est();
     }
     // a launch of several jobs: the scan's units of (job, 64-estimate group),
-    // dealt to the XCDs in turn (MTE_GROUPED_MANY=0: job-major lanes in the
-    // hardware order instead)
-    const bool units = n_ljobs_ > 1 && env_int("MTE_GROUPED_MANY", 1) != 0;
+    // dealt to the XCDs in turn, when there are at least kUnitsPerXcd per XCD
+    // (fewer leave XCDs idle and tie each unit to one XCD's CUs: a served
+    // batch of two or three requests has six to nine); MTE_GROUPED_MANY=0:
+    // job-major lanes in the hardware order always
+    int64_t n_units_all = 0;
+    for (int j = 0; j < n_ljobs_; ++j) n_units_all += std::max(1, specs[j].n_est() / 64);
+    const bool units = n_ljobs_ > 1 && n_units_all >= (int64_t)kUnitsPerXcd * kXcds &&
+                       env_int("MTE_GROUPED_MANY", 1) != 0;
     std::vector<int64_t> unit_info, unit_blocks, xcd_off;
     int unit_t = 0;
     int64_t scan_blocks = 0;
