@@ -1510,12 +1510,12 @@ int Batch::prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t
 
 // Blocks per CU (4 waves each) of the permutation that runs beside the build
 // (MTE_PERMUTE_BLOCKS_PER_CU overrides; 0 = uncapped).  The build's waves
-// have the higher issue priority, so the cap only sets how many wave slots
-// the permutation holds: at N = 10^4 with 201 estimates, 2 per CU left the
-// permutation last (0.27 ms beside a 0.23 ms build), 5 or more took wave
-// slots from the build (0.27-0.28 ms), 3-4 let both end at 0.24-0.25 ms
-// (3 was the faster in a stream of synchronised test calls).
-constexpr int kPermuteBlocksPerCu = 3;
+// have the higher issue priority and the build is submitted first, so the cap
+// only sets how many wave slots the permutation holds as the build's blocks
+// retire: at N = 10^4 with 201 estimates, 2 per CU gave 0.686-0.692 ms per
+// test against 0.701 ms with 3 and 0.72-0.73 ms with 6 or uncapped (submitted
+// after the permutation, the build had been best with 3).
+constexpr int kPermuteBlocksPerCu = 2;
 
 // Launch sequence: the all-pairs part (reset, permute, main kernel), then
 // the list part (reset, Y,Z copy; permute into xt on the side stream beside
@@ -1571,6 +1571,13 @@ int Batch::launch_all(hipStream_t s, bool timed) {
             return hip_fail(hipGetLastError(), "reset launch");
         if (launch_list_zy(ll_, s)) return hip_fail(hipGetLastError(), "Y,Z copy launch");
         MTE_HIP(hipEventRecord(fork_, s));
+        // the build is submitted first: the side stream's launches (ranks,
+        // permutation, row order) then do not delay its start
+        ll_.stats = ctx().list_stats ? 1 : 0;
+        if ((rc = begin(s))) return rc;
+        if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
+        if (ll_.sortx && launch_list_sortx(ll_, s)) return hip_fail(hipGetLastError(), "X sort launch");
+        if ((rc = end(kStageBuild, s))) return rc;
         MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
         // the ranks of the one-Z-column sets come first: the permutation
         // writes those sets' jobs' X in rank order
@@ -1587,11 +1594,6 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         // scan only, so it waits on the side stream too
         if (launch_list_order(ll_, side)) return hip_fail(hipGetLastError(), "row order launch");
         MTE_HIP(hipEventRecord(join_, side));
-        ll_.stats = ctx().list_stats ? 1 : 0;
-        if ((rc = begin(s))) return rc;
-        if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
-        if (ll_.sortx && launch_list_sortx(ll_, s)) return hip_fail(hipGetLastError(), "X sort launch");
-        if ((rc = end(kStageBuild, s))) return rc;
         MTE_HIP(hipStreamWaitEvent(s, join_, 0));
         if ((rc = begin(s))) return rc;
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
