@@ -490,7 +490,8 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
  *     device calls (cmi_ksg_surrogates_dev);
  *   list path: rows per block of the compiled-dimension build (2, 4), the
  *     scan's cooperative-finish threshold (2, 4, 8 lanes) and entries per
- *     step (4, 8) and, for launches of one job, the estimate-group lane
+ *     step (4, 8), the blocks per CU of the permutation beside the build
+ *     (2, 3) and, for launches of one job, the estimate-group lane
  *     order, per job shape ("L:" keys:
  *     N, dims, k, estimates, Theiler window, replications, one job or
  *     several), tuned by the device calls on the batch itself and by the host
@@ -502,7 +503,7 @@ int mte_tile_configs(int32_t *cfg_out, int capacity, int *count_out);
  * tuning off.
  * mte_tune_report writes the choices made or read in this process, one per
  * line: "<key> variant=<v> split=<m> build_rows=<q> coop_lanes=<c>
- * grouped=<g> scan_step=<s> ms=<t> from=<tuned|file>" (0 / -1: the default).  It writes at
+ * grouped=<g> scan_step=<s> perm_cu=<p> ms=<t> from=<tuned|file>" (0 / -1: the default).  It writes at
  * most cap - 1 bytes and a NUL to buf (buf may be NULL when cap is 0) and
  * the full length to *len_out, so a second call with a larger buffer gets
  * everything.

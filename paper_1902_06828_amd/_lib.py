@@ -451,7 +451,7 @@ def mte_tile_configs():
 def mte_tune_report():
     """The autotuner's choices made or read from the tuning file in this
     process: a list of dicts (key, variant, split, build_rows, coop_lanes,
-    grouped, ms, from)."""
+    grouped, scan_step, perm_cu, ms, from)."""
     n = ctypes.c_size_t()
     _check(lib().mte_tune_report(None, 0, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value + 1)

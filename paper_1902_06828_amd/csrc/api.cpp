@@ -389,9 +389,10 @@ int mte_tune_report(char *buf, size_t cap, size_t *len_out) {
         char line[512];
         for (const auto &t : c.tune_log) {
             snprintf(line, sizeof line,
-                     "%s variant=%d split=%d build_rows=%d coop_lanes=%d grouped=%d scan_step=%d ms=%.4f from=%s\n",
+                     "%s variant=%d split=%d build_rows=%d coop_lanes=%d grouped=%d scan_step=%d perm_cu=%d ms=%.4f "
+                     "from=%s\n",
                      t.key.c_str(), t.tc.variant, t.tc.rs_mult, t.tc.build_qb, t.tc.coop_lanes, t.tc.grouped,
-                     t.tc.scan_step, t.ms, t.from_disk ? "file" : "tuned");
+                     t.tc.scan_step, t.tc.perm_cu, t.ms, t.from_disk ? "file" : "tuned");
             text += line;
         }
     }

@@ -549,8 +549,8 @@ int pair_tiles(const std::vector<JobSpec> &specs, TileChoice *out) {
 }
 
 // ---------------------------------------------------------------- tuning file
-// One choice per line: "mte-tune 2 <arch> <build> <key> <variant> <rs_mult>
-// <build_qb> <coop_lanes> <grouped> <scan_step> <ms>".  Lines of another architecture or
+// One choice per line: "mte-tune 3 <arch> <build> <key> <variant> <rs_mult>
+// <build_qb> <coop_lanes> <grouped> <scan_step> <perm_cu> <ms>".  Lines of another architecture or
 // another build of the library are skipped, so a rebuilt library tunes anew.
 static const char *build_id() {
     static std::string id = [] {
@@ -582,10 +582,11 @@ static void load_tune_file_locked() {
         TileChoice tc;
         double ms = 0.0;
         int ver = 0;
-        if (std::sscanf(line, "mte-tune %d %127s %127s %255s %d %d %d %d %d %d %lf", &ver, arch, bid, key, &tc.variant,
-                        &tc.rs_mult, &tc.build_qb, &tc.coop_lanes, &tc.grouped, &tc.scan_step, &ms) != 11)
+        if (std::sscanf(line, "mte-tune %d %127s %127s %255s %d %d %d %d %d %d %d %lf", &ver, arch, bid, key,
+                        &tc.variant, &tc.rs_mult, &tc.build_qb, &tc.coop_lanes, &tc.grouped, &tc.scan_step, &tc.perm_cu,
+                        &ms) != 12)
             continue;
-        if (ver != 2 || c.arch != arch || std::strcmp(bid, build_id()) != 0) continue;
+        if (ver != 3 || c.arch != arch || std::strcmp(bid, build_id()) != 0) continue;
         c.tuned[key] = tc;
         c.tune_log.push_back(Ctx::TuneNote{key, tc, ms, 1});
     }
@@ -602,10 +603,20 @@ static void save_tune_locked(const std::string &key, const TileChoice &tc, doubl
         (void)mkdir(c.tune_file.substr(0, pos).c_str(), 0755);
     FILE *f = std::fopen(c.tune_file.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "mte-tune 2 %s %s %s %d %d %d %d %d %d %.4f\n", c.arch.c_str(), build_id(), key.c_str(), tc.variant,
-                 tc.rs_mult, tc.build_qb, tc.coop_lanes, tc.grouped, tc.scan_step, ms);
+    std::fprintf(f, "mte-tune 3 %s %s %s %d %d %d %d %d %d %d %.4f\n", c.arch.c_str(), build_id(), key.c_str(),
+                 tc.variant, tc.rs_mult, tc.build_qb, tc.coop_lanes, tc.grouped, tc.scan_step, tc.perm_cu, ms);
     std::fclose(f);
 }
+
+// Blocks per CU (4 waves each) of the permutation that runs beside the build
+// (MTE_PERMUTE_BLOCKS_PER_CU overrides; 0 = uncapped).  The build's waves
+// have the higher issue priority and the build is submitted first, so the cap
+// only sets how many wave slots the permutation holds as the build's blocks
+// retire: at N = 10^4 with 201 estimates, 2 per CU gave 0.686-0.692 ms per
+// test against 0.701 ms with 3 and 0.72-0.73 ms with 6 or uncapped (submitted
+// after the permutation, the build had been best with 3).  Other boxes had the
+// permutation outlast the build at 2, so the tuner also tries one more.
+constexpr int kPermuteBlocksPerCu = 2;
 
 // ---------------------------------------------------------------- tuning
 constexpr double kTuneMargin = 0.97;   // a candidate must be 3% faster to replace the best
@@ -752,6 +763,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
             out->coop_lanes = it->second.coop_lanes;
             out->grouped = it->second.grouped;
             out->scan_step = it->second.scan_step;
+            out->perm_cu = it->second.perm_cu;
             return MTE_OK;
         }
     }
@@ -772,15 +784,18 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     for (int qb : lean ? std::vector<int>{2, 4} : std::vector<int>{0})
         for (int coop : {4, 2, 8})
             for (int grp : several ? std::vector<int>{0} : std::vector<int>{1, 0})
-                for (int step : {step0, 12 - step0}) {
-                    TileChoice tc = *out;
-                    tc.build_qb = qb;
-                    tc.coop_lanes = coop;
-                    tc.grouped = grp;
-                    tc.scan_step = step;
-                    cand.push_back(tc);
-                    away.push_back((qb != qb0) + (coop != 4) + (grp != grp0) + (step != step0));
-                }
+                for (int step : {step0, 12 - step0})
+                    for (int pcu : {kPermuteBlocksPerCu, kPermuteBlocksPerCu + 1}) {
+                        TileChoice tc = *out;
+                        tc.build_qb = qb;
+                        tc.coop_lanes = coop;
+                        tc.grouped = grp;
+                        tc.scan_step = step;
+                        tc.perm_cu = pcu;
+                        cand.push_back(tc);
+                        away.push_back((qb != qb0) + (coop != 4) + (grp != grp0) + (step != step0) +
+                                       (pcu != kPermuteBlocksPerCu));
+                    }
     // the default first, then one knob away, two, ... (stable within a distance)
     std::vector<size_t> order(cand.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -810,6 +825,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     rec.coop_lanes = best.coop_lanes;
     rec.grouped = best.grouped;
     rec.scan_step = best.scan_step;
+    rec.perm_cu = best.perm_cu;
     {
         std::lock_guard<std::mutex> lk(c.mu);
         save_tune_locked(key, rec, best_ms);
@@ -818,6 +834,7 @@ static int tune_lists(const std::vector<JobSpec> &lists, hipStream_t s, int mode
     out->coop_lanes = rec.coop_lanes;
     out->grouped = rec.grouped;
     out->scan_step = rec.scan_step;
+    out->perm_cu = rec.perm_cu;
     return MTE_OK;
 }
 
@@ -1241,6 +1258,7 @@ int Batch::prepare_lists(const std::vector<JobSpec> &specs, const std::vector<in
     L.n_units = (int)unit_info.size();
     L.scan_blocks = scan_blocks;
     L.scan_step = env_int("MTE_SCAN_STEP", tc.scan_step > 0 ? tc.scan_step : (n_ljobs_ == 1 ? 8 : 4)) == 4 ? 4 : 8;
+    perm_cu_ = std::max(0, env_int("MTE_PERMUTE_BLOCKS_PER_CU", tc.perm_cu > 0 ? tc.perm_cu : kPermuteBlocksPerCu));
     L.rank_sets = rank_sets;
     L.max_rank_n = max_rank_n;
     L.rank_off = od + 3 * nj1 + 2 * (n_sets + 1);
@@ -1508,14 +1526,6 @@ int Batch::prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t
     return MTE_OK;
 }
 
-// Blocks per CU (4 waves each) of the permutation that runs beside the build
-// (MTE_PERMUTE_BLOCKS_PER_CU overrides; 0 = uncapped).  The build's waves
-// have the higher issue priority and the build is submitted first, so the cap
-// only sets how many wave slots the permutation holds as the build's blocks
-// retire: at N = 10^4 with 201 estimates, 2 per CU gave 0.686-0.692 ms per
-// test against 0.701 ms with 3 and 0.72-0.73 ms with 6 or uncapped (submitted
-// after the permutation, the build had been best with 3).
-constexpr int kPermuteBlocksPerCu = 2;
 
 // Launch sequence: the all-pairs part (reset, permute, main kernel), then
 // the list part (reset, Y,Z copy; permute into xt on the side stream beside
@@ -1585,8 +1595,7 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if ((rc = begin(side))) return rc;
         // capped only while the permutation is the smaller part: a launch of
         // many estimates over few list sets has more permutation than build
-        const int pcu = env_int("MTE_PERMUTE_BLOCKS_PER_CU", kPermuteBlocksPerCu);
-        const int64_t pgrid = pcu > 0 && lpermute_blocks_ <= ll_.build_blocks ? (int64_t)pcu * ctx().n_cu : 0;
+        const int64_t pgrid = perm_cu_ > 0 && lpermute_blocks_ <= ll_.build_blocks ? (int64_t)perm_cu_ * ctx().n_cu : 0;
         if (launch_permute(ljobs_dev_, n_ljobs_, lpermute_blocks_, lblk_off_, side, pgrid))
             return hip_fail(hipGetLastError(), "permute launch");
         if ((rc = end(kStagePermute, side))) return rc;

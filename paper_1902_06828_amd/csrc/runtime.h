@@ -100,6 +100,7 @@ struct TileChoice {
     int coop_lanes = 0;                // the scan's cooperative-finish threshold
     int grouped = -1;                  // one-job launches: estimate-group lane order (1) or not (0)
     int scan_step = 0;                 // the scan's entries per step (4, 8)
+    int perm_cu = 0;                   // blocks per CU of the permutation beside the build (0: default)
 };
 
 // Which path runs each job of a batch: -1 = all-pairs kernel, otherwise the
@@ -182,6 +183,7 @@ private:
     bool quiet_ = false;                // a tuning launch: leaves the statistics alone
     // fork/join of the list part's permutation onto the side stream
     hipEvent_t fork_ = nullptr, join_ = nullptr;
+    int perm_cu_ = 0;                   // the permutation's blocks per CU beside the build (0: uncapped)
 };
 
 // ---------------------------------------------------------------- context

@@ -1,8 +1,9 @@
 """The autotuner's launch choices change no result, and persist.
 
 The list path's knobs (rows per block of the compiled-dimension build, the
-scan's cooperative-finish threshold and entries per step, the
-estimate-group lane order of one-job launches) are forced through their environment overrides and every
+scan's cooperative-finish threshold and entries per step, the permutation's
+blocks per CU beside the build, the estimate-group lane order of one-job
+launches) are forced through their environment overrides and every
 combination must give the bits of the default.  The batched device call
 tunes a shape once, writes the choice to the tuning file and, after a new
 start, reads it back instead of tuning again."""
@@ -31,13 +32,16 @@ def test_list_knobs_change_no_result(monkeypatch, dims, n, S):
     monkeypatch.setenv("MTE_TUNE", "0")
     say("knobs: default", dims, n, S)
     ref = mte.cmi_ksg_diag(X, Y, Z, 4, S, 7, 1)
-    for qb, coop, grouped, step in (("2", "2", "1", "4"), ("4", "8", "0", "8"), ("4", "4", "1", "4"),
-                                    ("2", "8", "0", "4"), ("4", "2", "0", "8")):
+    for qb, coop, grouped, step, pcu in (("2", "2", "1", "4", "1"), ("4", "8", "0", "8", "3"),
+                                         ("4", "4", "1", "4", "0"), ("2", "8", "0", "4", "2"),
+                                         ("4", "2", "0", "8", "5")):
         monkeypatch.setenv("MTE_BUILD_QB", qb)
         monkeypatch.setenv("MTE_COOP_LANES", coop)
         monkeypatch.setenv("MTE_GROUPED", grouped)
         monkeypatch.setenv("MTE_SCAN_STEP", step)
-        say("knobs: build rows", qb, "coop lanes", coop, "grouped", grouped, "scan step", step)
+        monkeypatch.setenv("MTE_PERMUTE_BLOCKS_PER_CU", pcu)
+        say("knobs: build rows", qb, "coop lanes", coop, "grouped", grouped, "scan step", step,
+            "permutation blocks per CU", pcu)
         out = mte.cmi_ksg_diag(X, Y, Z, 4, S, 7, 1)
         for a, b in zip(ref, out):
             assert np.array_equal(a, b)
@@ -111,7 +115,7 @@ def test_tuning_file_skips_foreign_and_broken_lines(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     good = path.read_text().splitlines()
     assert len(good) == 1
-    f = good[0].split()            # mte-tune 2 <arch> <build> <key> <8 numbers>
+    f = good[0].split()            # mte-tune 3 <arch> <build> <key> <9 numbers>
     foreign = [" ".join(f[:2] + ["gfx000"] + f[3:4] + ["L:foreign-arch"] + f[5:]),
                " ".join(f[:3] + ["another-build"] + ["L:foreign-build"] + f[5:]),
                " ".join(f[:4] + ["L:short-line"] + f[5:8]),
