@@ -261,7 +261,7 @@ int launch_main(int variant, const Job *jobs_dev, int n_jobs, const int64_t *a_o
                 const int64_t *b_off_dev, const LaunchInfo &li, uint32_t *work,
                 const double *harm, void *stream);
 
-int launch_list_zy(const ListLaunch &L, void *stream);      // the sets' contiguous Y,Z copies
+int launch_list_zy(const ListLaunch &L, void *stream);      // the sets' contiguous Y,Z copies; clears the counters
 int launch_list_order(const ListLaunch &L, void *stream);  // the scan's row order (several jobs)
 int launch_list_build(const ListLaunch &L, void *stream);
 int launch_list_sortx(const ListLaunch &L, void *stream);

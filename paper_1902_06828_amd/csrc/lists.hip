@@ -670,9 +670,12 @@ __global__ __launch_bounds__(kBT) void list_build_dz_kernel(const ListSet *__res
 // ------------------------------------------------------------------ columns
 // One thread per (set, row): the row's Z then Y coordinates into the set's
 // contiguous column copy, so that the build addresses every column from one
-// base pointer.
+// base pointer; the first threads also clear the launch's counters.
 __global__ __launch_bounds__(kBlock) void list_zy_kernel(const ListLaunch L) {
     const int64_t g = bid_x() * kBlock + tid_x();
+    // the launch's counters are cleared here too (a kernel launch fewer; the
+    // grid covers at least kListCounterWords threads)
+    if (g < kListCounterWords) L.counters[g] = 0u;
     if (g >= L.rows) return;
     const int t = find_job(L.row_off, L.n_sets, g);
     const ListSet &S = L.sets[t];
@@ -1738,8 +1741,8 @@ void *scan_fn(int step, bool units) {
 }  // namespace
 
 int launch_list_zy(const ListLaunch &L, void *stream) {
-    if (L.rows <= 0) return 0;
-    hipLaunchKernelGGL(list_zy_kernel, dim3((unsigned)((L.rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+    const int64_t threads = L.rows > kListCounterWords ? L.rows : (int64_t)kListCounterWords;
+    hipLaunchKernelGGL(list_zy_kernel, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        (hipStream_t)stream, L);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

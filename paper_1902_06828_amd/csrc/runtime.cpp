@@ -1577,8 +1577,7 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         const hipStream_t side = ctx().side_stream;
         if (!fork_) MTE_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
         if (!join_) MTE_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
-        if (launch_reset(lcounters_.as<uint32_t>(), kListCounterWords, s))
-            return hip_fail(hipGetLastError(), "reset launch");
+        // the Y,Z copy also clears the counters
         if (launch_list_zy(ll_, s)) return hip_fail(hipGetLastError(), "Y,Z copy launch");
         MTE_HIP(hipEventRecord(fork_, s));
         // the build is submitted first: the side stream's launches (ranks,
