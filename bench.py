@@ -89,6 +89,12 @@ def counter_record(kernel):
     return rec["kernels"][kernel]
 
 
+def traffic_record():
+    """The whole counter record, if it still covers the kernel sources."""
+    return {"tuned_choice": json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))).get("tuned_choice")} \
+        if counter_record("scan") is not None else None
+
+
 def measured_traffic(kernel):
     rec = counter_record(kernel)
     return rec["hbm_bytes_per_launch"] if rec else None
@@ -101,6 +107,70 @@ def valu_issue_frac(kernel, kernel_ms):
     if not rec or "valu_insts_per_launch" not in rec:
         return None
     return rec["valu_insts_per_launch"] * 64 / (kernel_ms * 1e-3) / (PEAK_TOPS * 1e12)
+
+
+TRAFFIC_SOURCES = ["paper_1902_06828_amd/csrc/lists.hip", "paper_1902_06828_amd/csrc/engine.h",
+                   "paper_1902_06828_amd/csrc/ksg_device.h"]
+C2_LIST_KEY = "L:n10000:dx1:dy1:dz5:k4:e201:w0:r1:one"
+
+
+def write_traffic(fetch_dir, write_dir, sq_dir, pre_json):
+    """profiles/traffic.json from the counter runs of the C2 leg: the
+    rocprofv3 databases of a FETCH_SIZE pass and a WRITE_SIZE pass (both
+    with --calibrate-copy) and of an SQ pass, and the benchmark's JSON line
+    of the untimed run before them, whose tuning the passes read.  Per kernel
+    the median over its dispatches; HBM bytes = FETCH_SIZE and WRITE_SIZE
+    scaled by their readings for the 1 GiB copy."""
+    import glob
+    import hashlib
+    import sqlite3
+    import statistics
+
+    def per_dispatch(d):
+        dbs = sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True), key=os.path.getmtime)
+        if not dbs:
+            raise SystemExit(f"no rocprofv3 database under {d}")
+        out = {}
+        cur = sqlite3.connect(dbs[-1]).cursor()
+        for k, cn, v, di in cur.execute("select kernel_name, counter_name, value, dispatch_id "
+                                        "from counters_collection"):
+            out.setdefault(k, {}).setdefault(cn, {})
+            out[k][cn][di] = out[k][cn].get(di, 0.0) + v
+        return out
+
+    def med(m, pick, cn):
+        ks = [k for k in m if pick(k)]
+        if len(ks) != 1:
+            raise SystemExit(f"expected one kernel for {cn}, found {ks}")
+        vals = list(m[ks[0]][cn].values())
+        return statistics.median(vals), len(vals), ks[0]
+
+    pf, pw, ps = per_dispatch(fetch_dir), per_dispatch(write_dir), per_dispatch(sq_dir)
+    copy = lambda k: "neg" in k.lower()
+    cf = med(pf, copy, "FETCH_SIZE")[0]
+    cw = med(pw, copy, "WRITE_SIZE")[0]
+    gib = 1 << 30
+    cal = {"bytes_read": gib, "bytes_written": gib, "fetch_kib_raw": cf, "write_kib_raw": cw,
+           "fetch_factor": gib / 1024 / cf, "write_factor": gib / 1024 / cw}
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    pre = json.loads([ln for ln in open(pre_json) if ln.startswith("{")][-1])
+    choice = [c for c in pre.get("tuned_choices", {}).get("batched_and_plain", []) if c["key"] == C2_LIST_KEY]
+    rec = {"workload": "C2, N=10000, 201 estimates", "sources": TRAFFIC_SOURCES, "sha256": h.hexdigest(),
+           "copy_calibration": cal, "tuned_choice": choice[0] if choice else None, "kernels": {}}
+    for tag, pick in (("scan", lambda k: "list_scan_kernel" in k), ("build", lambda k: "list_build" in k)):
+        f, nf, kn = med(pf, pick, "FETCH_SIZE")
+        w, nw, _ = med(pw, pick, "WRITE_SIZE")
+        v, nv, _ = med(ps, pick, "SQ_INSTS_VALU")
+        rec["kernels"][tag] = {
+            "kernel": kn.replace("mte::(anonymous namespace)::", "").replace("void ", "").split("(")[0],
+            "fetch_kib_raw": f, "write_kib_raw": w, "dispatches": [nf, nw, nv],
+            "hbm_bytes_per_launch": (f * cal["fetch_factor"] + w * cal["write_factor"]) * 1024,
+            "valu_insts_per_launch": v}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_model():
@@ -442,7 +512,13 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 1 GiB (256Mi float32 read + written) before the "
                          "timed region, as the reference for HBM byte counters")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR", "PRE_JSON"),
+                    help="write profiles/traffic.json from the C2 counter runs' rocprofv3 databases and the "
+                         "JSON line of the untimed run before them, then exit (no GPU needed)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the KSG path runs on a single MI355X and no multi-GPU "
               "form is implemented; use --gpus 1", file=sys.stderr)
@@ -524,7 +600,25 @@ def main():
         return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak if achieved else None, "traffic": measured_traffic(stage),
                 "kernel": stage, "kernel_ms": k_ms, "work_per_launch": work,
-                "valu_issue_frac": valu_issue_frac(stage, k_ms), **extra}
+                "valu_issue_frac": valu_issue_frac(stage, k_ms), **extra, **choice_note(stage)}
+
+    # the counter record holds the launch choices its run made; the tuner may
+    # choose differently on another box (the scan's traffic depends on the
+    # cooperative-finish threshold, the build's on its rows per block)
+    this_choice = [c for c in mte.mte_tune_report() if c["key"] == C2_LIST_KEY]
+    this_choice = this_choice[-1] if this_choice else None
+
+    def choice_note(stage):
+        rec = traffic_record()
+        counted = rec.get("tuned_choice") if rec else None
+        knobs = {"scan": ("coop_lanes", "scan_step", "grouped"), "build": ("build_rows",)}.get(stage)
+        if not knobs:
+            return {}
+        same = (counted is not None and this_choice is not None and
+                all(counted.get(k) == this_choice.get(k) for k in knobs))
+        return {"tuned_choice": {k: this_choice.get(k) for k in knobs} if this_choice else None,
+                "traffic_tuned_choice": {k: counted.get(k) for k in knobs} if counted else None,
+                "traffic_choice_matches": same}
 
     # on the list path the permutation runs beside the build (a second stream),
     # so it is not on the step's critical path
