@@ -101,7 +101,7 @@ def test_greedy_rounds_tuned_or_not(tmp_path, monkeypatch):
 
 
 def test_tuning_file_skips_foreign_and_broken_lines(tmp_path, monkeypatch):
-    # a choice written by this build on this device is read back; lines of
+    # a choice written by the same library build on the same device is read back; lines of
     # another architecture or another build of the library, and lines that
     # do not parse, are skipped
     path = tmp_path / "tune.txt"
