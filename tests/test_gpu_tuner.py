@@ -130,3 +130,22 @@ def test_tuning_file_skips_foreign_and_broken_lines(tmp_path, monkeypatch):
     say("report after restart", rep)
     assert [r["key"] for r in rep] == [f[4]] and rep[0]["from"] == "file"
     mte.mte_shutdown()
+
+
+def test_several_job_lane_orders_agree(monkeypatch):
+    # a greedy round's candidates are one launch of many jobs: with at least
+    # four 64-estimate units per XCD the scan deals (job, group) units to the
+    # XCDs, else it keeps job-major lanes; the selection and every statistic
+    # are the same either way
+    monkeypatch.setenv("MTE_TUNE", "0")
+    series, links = synth.var_network(6, 3000, seed=11)
+    target = min(i for (i, _, _, _) in links)
+    cands = [j for j in range(6) if j != target]
+    kw = dict(max_lag_sources=5, alpha=0.05, S=200, seed=4)
+    say("greedy, XCD-dealt units")
+    units = mte.mte_select_sources(series, target, cands, **kw)
+    monkeypatch.setenv("MTE_GROUPED_MANY", "0")
+    say("greedy, job-major lanes")
+    plain = mte.mte_select_sources(series, target, cands, **kw)
+    for key in ("target_past", "sources", "sources_before_omnibus", "omnibus_te", "omnibus_p", "n_estimates"):
+        assert units[key] == plain[key]
