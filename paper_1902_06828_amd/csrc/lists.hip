@@ -648,13 +648,15 @@ __global__ __launch_bounds__(kBT) void list_build_dz_kernel(const ListSet *__res
         if (r >= nq) continue;
         const int64_t i = i0 + r;
         const uint32_t total = (uint32_t)(n - 1 - min((int)i, tw) - min(n - 1 - (int)i, tw));
-        uint32_t kbw = 0, krw = 0;
+        // the row's kept bins and rows, summed again from the waves' shares
+        // in LDS (a register array indexed by r would go to scratch memory)
+        uint32_t nb = 0, nr = 0;
 #pragma unroll
-        for (int rr = 0; rr < QB; ++rr)
-            if (rr == r) {
-                kbw = w == 0 ? kb[rr][0] : kb[rr][1];
-                krw = w == 0 ? kr[rr][0] : kr[rr][1];
-            }
+        for (int v2 = 0; v2 < kBW; ++v2) {
+            nb += sm.red[2 * r][v2];
+            nr += sm.red[2 * r + 1][v2];
+        }
+        const uint32_t kbw = w == 0 ? nb & 0xffffu : nb >> 16, krw = w == 0 ? nr & 0xffffu : nr >> 16;
         const bool whole = krw == total || (kbw << kKeyShift) >= __float_as_uint(inf_f());
         const float bound = whole ? inf_f() : __uint_as_float(kbw << kKeyShift);
         const float sent = whole ? inf_f() : __uint_as_float((kbw << kKeyShift) + 1u);
