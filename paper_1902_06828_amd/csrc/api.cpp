@@ -431,7 +431,7 @@ int mte_kernel_timing_stage(int stage, int64_t *launches_out, double *total_ms_o
     }
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto &pe : ev) {
-        c.event_pool.push_back(pe.a);
+        if (pe.own_a) c.event_pool.push_back(pe.a);
         c.event_pool.push_back(pe.b);
     }
     for (int t = 0; t < kStages; ++t) {

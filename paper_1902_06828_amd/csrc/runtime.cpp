@@ -258,7 +258,7 @@ int shutdown_all() {
     if (!c.inited) return MTE_OK;
     MTE_HIP(hipDeviceSynchronize());
     for (auto &pe : c.pending_events) {
-        (void)hipEventDestroy(pe.a);
+        if (pe.own_a) (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
     }
     c.pending_events.clear();
@@ -367,10 +367,17 @@ int timing_event(hipEvent_t *e) {
     return MTE_OK;
 }
 
-void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b) {
+void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b, bool own_a) {
     Ctx &c = ctx();
     std::lock_guard<std::mutex> lk(c.mu);
-    c.pending_events.push_back(Ctx::Pending{stage, a, b});
+    c.pending_events.push_back(Ctx::Pending{stage, a, b, own_a});
+}
+
+void record_timing_pairs(const std::vector<Ctx::Pending> &pairs) {
+    if (pairs.empty()) return;
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.pending_events.insert(c.pending_events.end(), pairs.begin(), pairs.end());
 }
 
 // ---------------------------------------------------------------- paths
@@ -1532,18 +1539,33 @@ int Batch::prepare_solo(const std::vector<JobSpec> &specs, hipStream_t s, size_t
 // the build and the X sort, which read only the unpermuted columns; joined
 // before the scan; then scan, fallback, reduce).
 int Batch::launch_all(hipStream_t s, bool timed) {
+    // timed: a stage's events bracket its kernels; a stage that follows
+    // another on the same stream starts at that one's end event (each
+    // recorded event is a queue packet, a few microseconds of device time)
     hipEvent_t ev[2] = {nullptr, nullptr};
+    bool own_a = true;
+    struct Pairs {
+        std::vector<Ctx::Pending> v;
+        ~Pairs() { record_timing_pairs(v); }
+    } pairs;
     auto begin = [&](hipStream_t st) -> int {
         if (!timed) return MTE_OK;
         int rc;
         if ((rc = timing_event(&ev[0])) || (rc = timing_event(&ev[1]))) return rc;
+        own_a = true;
         MTE_HIP(hipEventRecord(ev[0], st));
         return MTE_OK;
+    };
+    auto begin_after = [&]() -> int {   // right after end() on the same stream
+        if (!timed) return MTE_OK;
+        ev[0] = ev[1];
+        own_a = false;
+        return timing_event(&ev[1]);
     };
     auto end = [&](int stage, hipStream_t st) -> int {
         if (!timed) return MTE_OK;
         MTE_HIP(hipEventRecord(ev[1], st));
-        record_timing_pair(stage, ev[0], ev[1]);
+        pairs.v.push_back(Ctx::Pending{stage, ev[0], ev[1], own_a});
         return MTE_OK;
     };
     int rc;
@@ -1579,15 +1601,17 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (!join_) MTE_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
         // the Y,Z copy also clears the counters
         if (launch_list_zy(ll_, s)) return hip_fail(hipGetLastError(), "Y,Z copy launch");
-        MTE_HIP(hipEventRecord(fork_, s));
         // the build is submitted first: the side stream's launches (ranks,
-        // permutation, row order) then do not delay its start
+        // permutation, row order) then do not delay its start.  The side
+        // stream forks at the build's start event when timed
         ll_.stats = ctx().list_stats ? 1 : 0;
         if ((rc = begin(s))) return rc;
+        const hipEvent_t fork = timed ? ev[0] : fork_;
+        if (!timed) MTE_HIP(hipEventRecord(fork_, s));
         if (launch_list_build(ll_, s)) return hip_fail(hipGetLastError(), "list build launch");
         if (ll_.sortx && launch_list_sortx(ll_, s)) return hip_fail(hipGetLastError(), "X sort launch");
         if ((rc = end(kStageBuild, s))) return rc;
-        MTE_HIP(hipStreamWaitEvent(side, fork_, 0));
+        MTE_HIP(hipStreamWaitEvent(side, fork, 0));
         // the ranks of the one-Z-column sets come first: the permutation
         // writes those sets' jobs' X in rank order
         if (launch_list_rank_sort(ll_, side)) return hip_fail(hipGetLastError(), "rank launch");
@@ -1607,10 +1631,10 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
         if (launch_list_rank_count(ll_, s)) return hip_fail(hipGetLastError(), "rank count launch");
         if ((rc = end(kStageScan, s))) return rc;
-        if ((rc = begin(s))) return rc;
+        if ((rc = begin_after())) return rc;
         if (launch_list_fallback(ll_, s)) return hip_fail(hipGetLastError(), "list fallback launch");
         if ((rc = end(kStageFallback, s))) return rc;
-        if ((rc = begin(s))) return rc;
+        if ((rc = begin_after())) return rc;
         if (launch_list_reduce(ll_, harm_table(), s)) return hip_fail(hipGetLastError(), "list reduce launch");
         if ((rc = end(kStageReduce, s))) return rc;
     }

@@ -215,7 +215,9 @@ struct Ctx {
     std::string arch, tune_file;
     // kernel timing per stage
     bool timing = false;
-    struct Pending { int stage; hipEvent_t a, b; };
+    // a is shared with the previous pair's b (and not returned or destroyed
+    // twice) when own_a is false
+    struct Pending { int stage; hipEvent_t a, b; bool own_a; };
     std::vector<Pending> pending_events;
     std::vector<hipEvent_t> event_pool;   // read timing events, for reuse
     int64_t timed_launches[kStages] = {};
@@ -295,7 +297,10 @@ int autocorr_decay_time(const float *x, int64_t T, int max_lag);
 // Host mirror of the device harmonic table (same summation order).
 double harmonic_host(int64_t n);
 
-void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b);
+void record_timing_pair(int stage, hipEvent_t a, hipEvent_t b, bool own_a = true);
+// several pairs at once (one launch's: a readout then sees all of them or none,
+// so an event shared by two of them is never returned to the pool early)
+void record_timing_pairs(const std::vector<Ctx::Pending> &pairs);
 
 // Per-node z-score of a host series [R][P][T] (see runtime.cpp).
 void standardise_host(const float *in, int R, int P, int64_t T, float *out);
