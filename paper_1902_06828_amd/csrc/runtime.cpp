@@ -1625,8 +1625,11 @@ int Batch::launch_all(hipStream_t s, bool timed) {
         // the scan's row order (launches of several jobs) is needed by the
         // scan only, so it waits on the side stream too
         if (launch_list_order(ll_, side)) return hip_fail(hipGetLastError(), "row order launch");
-        MTE_HIP(hipEventRecord(join_, side));
-        MTE_HIP(hipStreamWaitEvent(s, join_, 0));
+        // timed with no row-order kernel (one job), the permutation's end
+        // event is the join
+        const bool join_at_end = timed && ll_.n_jobs <= 1;
+        if (!join_at_end) MTE_HIP(hipEventRecord(join_, side));
+        MTE_HIP(hipStreamWaitEvent(s, join_at_end ? ev[1] : join_, 0));
         if ((rc = begin(s))) return rc;
         if (launch_list_scan(ll_, s)) return hip_fail(hipGetLastError(), "list scan launch");
         if (launch_list_rank_count(ll_, s)) return hip_fail(hipGetLastError(), "rank count launch");
