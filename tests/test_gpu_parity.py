@@ -169,6 +169,49 @@ def test_batched_equals_plain():
         assert surr[s] == mte.cmi_ksg(Xs, Y, Z, 4)
 
 
+def test_stage_timing_events():
+    # timed launches bracket each stage with events, sharing one where two
+    # stages meet on a stream; every launch adds one to each list stage and
+    # the results are those of untimed launches (one job, then the several-job
+    # launches of a greedy search, which join after the row-order kernel)
+    torch = pytest.importorskip("torch")
+    X, Y, Z = synth.random_points(2500, (1, 1, 5), seed=46)
+    S, seed, cand = 20, 9, 2
+    ref = mte.cmi_ksg_diag(X, Y, Z, 4, S, seed, cand)[0]
+    dev = torch.device("cuda:0")
+    dX, dY, dZ = (torch.from_numpy(a).to(dev) for a in (X, Y, Z))
+    out = torch.zeros(S + 1, dtype=torch.float64, device=dev)
+    series, _ = synth.var_network(4, 2000, seed=3)
+    kw = dict(max_lag_sources=3, alpha=0.05, S=50, seed=2)
+    stages = ("build", "scan", "fallback", "reduce", "permute")
+    for st in mte._lib.STAGES:
+        mte.mte_kernel_timing_stage(st, reset=True)
+    mte.mte_kernel_timing(True)
+    try:
+        for rep in range(3):
+            say("timed one-job launch", rep)
+            out.zero_()
+            mte.cmi_ksg_surrogates_dev(dX, dY, dZ, 4, S, seed, cand, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), rep
+            for st in stages:
+                n, ms = mte.mte_kernel_timing_stage(st)
+                assert n == rep + 1 and ms > 0.0, (st, n, ms)
+        say("timed greedy search")
+        timed = mte.mte_select_sources(series, 0, [1, 2, 3], **kw)
+        for st in stages:
+            n, ms = mte.mte_kernel_timing_stage(st)
+            assert n > 3 and ms > 0.0, (st, n, ms)
+    finally:
+        mte.mte_kernel_timing(False)
+        for st in mte._lib.STAGES:
+            mte.mte_kernel_timing_stage(st, reset=True)
+    say("untimed greedy search")
+    plain = mte.mte_select_sources(series, 0, [1, 2, 3], **kw)
+    for key in ("target_past", "sources", "sources_before_omnibus", "omnibus_te", "omnibus_p", "n_estimates"):
+        assert timed[key] == plain[key]
+
+
 def test_device_api_and_graph_replay():
     torch = pytest.importorskip("torch")
     X, Y, Z = synth.random_points(2500, (1, 1, 5), seed=44)
