@@ -316,8 +316,19 @@ def c5_leg(mte, budget=2 << 30, window=2000, p_nodes=100):
             "p99_latency_s": st["p99_latency_s"], "batches": st["batches"],
             "mean_batch_requests": st["mean_batch_requests"], "peak_bytes_in_use": st["peak_bytes_in_use"],
             "budget_bytes": st["budget_bytes"], "admissions_that_waited": st["waited"],
+            "latency_phases": latency_phases(st),
             "rejected": st["rejected"], "searches_cancelled": errors.count(mte._lib.MTE_ECANCELED),
             "searches_completed_in_window": len(done), "other_errors": [c for c in errors if c != mte._lib.MTE_ECANCELED]}
+
+
+def latency_phases(st):
+    """p50/p99 of each phase of the served latency and the phases averaged
+    over the requests at or above the p99 latency (the request loop's
+    statistics)."""
+    keys = ["queue_p50_s", "queue_p99_s", "host_p50_s", "host_p99_s", "device_p50_s", "device_p99_s",
+            "tail_queue_s", "tail_host_s", "tail_device_s", "tail_mean_n", "tail_mean_batch_requests",
+            "tail_requests"]
+    return {k: st[k] for k in keys}
 
 
 def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
@@ -385,6 +396,7 @@ def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
         "p99_latency_s": st["p99_latency_s"],
         "batches": st["batches"],
         "mean_batch_requests": st["mean_batch_requests"],
+        "latency_phases": latency_phases(st),
     }
 
 
@@ -688,6 +700,12 @@ def main():
         srv = served(mte, torch)
         log(f"served: {srv['saturation_evals_per_s']:.1f} evals/s saturated (first burst {srv['first_burst_evals_per_s']:.1f}); Poisson p50 "
             f"{srv['p50_latency_s'] * 1e3:.1f} ms p99 {srv['p99_latency_s'] * 1e3:.1f} ms")
+        ph = srv["latency_phases"]
+        log(f"served latency phases (ms): queued p50 {ph['queue_p50_s'] * 1e3:.2f} p99 {ph['queue_p99_s'] * 1e3:.2f}, "
+            f"host p50 {ph['host_p50_s'] * 1e3:.2f} p99 {ph['host_p99_s'] * 1e3:.2f}, device p50 "
+            f"{ph['device_p50_s'] * 1e3:.2f} p99 {ph['device_p99_s'] * 1e3:.2f}; the {ph['tail_requests']} requests at or "
+            f"above p99: queued {ph['tail_queue_s'] * 1e3:.2f}, host {ph['tail_host_s'] * 1e3:.2f}, device "
+            f"{ph['tail_device_s'] * 1e3:.2f}, mean N {ph['tail_mean_n']:.0f}, batch {ph['tail_mean_batch_requests']:.1f}")
 
     note_tuning("served")
     c3 = None

@@ -467,6 +467,17 @@ typedef struct {
     int64_t peak_bytes_in_use;
     int64_t budget_bytes;
     int64_t waited;           /* requests admitted after waiting at the queue front for memory */
+    /* Phases of a completed request's latency (seconds): queued = submit to
+     * the start of the admission that launched it (waits for a free slot or
+     * for memory included), host = that admission (sizing, preparing and
+     * enqueueing its batch), device = launch to the retirement that found the
+     * batch done (its kernels, kernels of other batches sharing the GPU, the
+     * result copy and the loop's polling).  p50/p99 of each phase on its own: */
+    double queue_p50_s, queue_p99_s, host_p50_s, host_p99_s, device_p50_s, device_p99_s;
+    /* The requests whose latency is at or above p99_latency_s: their count,
+     * mean phases, mean N and mean requests per batch. */
+    double tail_queue_s, tail_host_s, tail_device_s, tail_mean_n, tail_mean_batch_requests;
+    int64_t tail_requests;
 } mte_serve_stats;
 
 /* Statistics since the last reset (reset = 1 clears them after reading). */

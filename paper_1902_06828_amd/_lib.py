@@ -65,7 +65,13 @@ class mte_serve_stats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("estimates", ctypes.c_int64),
                 ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("mean_batch_requests", ctypes.c_double), ("peak_bytes_in_use", ctypes.c_int64),
-                ("budget_bytes", ctypes.c_int64), ("waited", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("waited", ctypes.c_int64),
+                ("queue_p50_s", ctypes.c_double), ("queue_p99_s", ctypes.c_double),
+                ("host_p50_s", ctypes.c_double), ("host_p99_s", ctypes.c_double),
+                ("device_p50_s", ctypes.c_double), ("device_p99_s", ctypes.c_double),
+                ("tail_queue_s", ctypes.c_double), ("tail_host_s", ctypes.c_double),
+                ("tail_device_s", ctypes.c_double), ("tail_mean_n", ctypes.c_double),
+                ("tail_mean_batch_requests", ctypes.c_double), ("tail_requests", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p

@@ -249,7 +249,7 @@ extern "C" {
 
 const char *mte_last_error(void) { return mte::last_error(); }
 
-int mte_abi_version(void) { return 6; }
+int mte_abi_version(void) { return 7; }
 
 int mte_init(int device, size_t hbm_budget_bytes) { return init_device(device, hbm_budget_bytes); }
 

@@ -45,6 +45,9 @@ struct Req {
     mte_request r{};
     std::vector<int32_t> nodes, lags;
     Clock::time_point t_submit, t_done;
+    // the admission that launched it: its start and the end of its enqueue
+    Clock::time_point t_admit, t_launch;
+    int batch_reqs = 0;            // requests in that batch
     int state = 0;                 // 0 queued, 1 on the GPU, 2 done
     bool waited = false;           // held at the queue front for memory
     int status = MTE_OK;
@@ -92,7 +95,16 @@ public:
     // statistics
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, estimates = 0, batch_reqs = 0;
     int64_t waited = 0;            // requests admitted after waiting for memory
-    std::vector<double> latencies;
+    // latency of each completed request and its phases: queued (submit to the
+    // start of the admission that launched it), host (that admission: sizing,
+    // preparing and enqueueing the batch) and device (launch to the retirement
+    // that found the batch done)
+    struct Lat {
+        double total, queue, host, device;
+        int64_t n;
+        int batch;
+    };
+    std::vector<Lat> latencies;
     size_t peak_bytes = 0;
 
     int start_locked() {
@@ -125,7 +137,10 @@ public:
         if (status == MTE_OK) {
             completed++;
             estimates += (int64_t)q->result.size();
-            latencies.push_back(std::chrono::duration<double>(q->t_done - q->t_submit).count());
+            auto sec = [](Clock::duration d) { return std::chrono::duration<double>(d).count(); };
+            latencies.push_back(Lat{sec(q->t_done - q->t_submit), sec(q->t_admit - q->t_submit),
+                                    sec(q->t_launch - q->t_admit), sec(q->t_done - q->t_launch), q->r.N,
+                                    q->batch_reqs});
         } else {
             rejected++;
         }
@@ -220,6 +235,7 @@ public:
     // batches hold memory makes the front wait as well.
     void admit(Slot &s) {
         if (mem_blocked) return;
+        const Clock::time_point t_admit = Clock::now();
         const size_t budget = ctx().budget;
         static const size_t batch_cap = [] {
             const char *v = std::getenv("MTE_BATCH_BYTES_MAX");
@@ -282,8 +298,12 @@ public:
             }
             s.reqs.assign(queue.begin(), queue.begin() + (long)take);
             queue.erase(queue.begin(), queue.begin() + (long)take);
+            const Clock::time_point t_launch = Clock::now();
             for (auto &q : s.reqs) {
                 q->state = 1;
+                q->t_admit = t_admit;
+                q->t_launch = t_launch;
+                q->batch_reqs = (int)take;
                 if (q->waited) waited++;
             }
             s.batch = std::move(b);
@@ -557,14 +577,38 @@ int mte_serve_get_stats(mte_serve_stats *out, int reset) {
     out->budget_bytes = (int64_t)ctx().budget;
     out->waited = sv.waited;
     if (!sv.latencies.empty()) {
-        std::vector<double> l = sv.latencies;
-        std::sort(l.begin(), l.end());
-        auto pct = [&](double p) {
-            size_t i = (size_t)std::min<double>((double)l.size() - 1, std::ceil(p * (double)l.size()) - 1);
-            return l[i];
+        const size_t m = sv.latencies.size();
+        auto pct = [&](double Server::Lat::*f, double p) {
+            std::vector<double> l(m);
+            for (size_t i = 0; i < m; ++i) l[i] = sv.latencies[i].*f;
+            std::sort(l.begin(), l.end());
+            return l[(size_t)std::min<double>((double)m - 1, std::ceil(p * (double)m) - 1)];
         };
-        out->p50_latency_s = pct(0.50);
-        out->p99_latency_s = pct(0.99);
+        out->p50_latency_s = pct(&Server::Lat::total, 0.50);
+        out->p99_latency_s = pct(&Server::Lat::total, 0.99);
+        out->queue_p50_s = pct(&Server::Lat::queue, 0.50);
+        out->queue_p99_s = pct(&Server::Lat::queue, 0.99);
+        out->host_p50_s = pct(&Server::Lat::host, 0.50);
+        out->host_p99_s = pct(&Server::Lat::host, 0.99);
+        out->device_p50_s = pct(&Server::Lat::device, 0.50);
+        out->device_p99_s = pct(&Server::Lat::device, 0.99);
+        // the requests at or above the p99 latency, their phases averaged
+        int64_t nt = 0;
+        for (const auto &L : sv.latencies) {
+            if (L.total < out->p99_latency_s) continue;
+            ++nt;
+            out->tail_queue_s += L.queue;
+            out->tail_host_s += L.host;
+            out->tail_device_s += L.device;
+            out->tail_mean_n += (double)L.n;
+            out->tail_mean_batch_requests += (double)L.batch;
+        }
+        out->tail_requests = nt;
+        out->tail_queue_s /= (double)nt;
+        out->tail_host_s /= (double)nt;
+        out->tail_device_s /= (double)nt;
+        out->tail_mean_n /= (double)nt;
+        out->tail_mean_batch_requests /= (double)nt;
     }
     if (reset) {
         sv.submitted = sv.completed = sv.rejected = sv.batches = sv.estimates = sv.batch_reqs = sv.waited = 0;

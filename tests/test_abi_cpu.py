@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert mte.lib().mte_abi_version() == 6
+    assert mte.lib().mte_abi_version() == 7
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 100, 1000, 4097, 10000])

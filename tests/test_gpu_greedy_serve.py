@@ -100,6 +100,15 @@ def test_request_loop_alone_vs_mix():
     mix = [mte.mte_wait(t, q["S"]) for t, q in zip(tickets, reqs)]
     st = mte.mte_serve_get_stats(reset=True)
     assert st["completed"] == len(reqs) and st["rejected"] == 0
+    # latency phases: none negative, each p99 within the total's, and the
+    # tail's phases add up to its latencies (at least the p99 latency)
+    for ph in ("queue", "host", "device"):
+        assert 0.0 <= st[ph + "_p50_s"] <= st[ph + "_p99_s"] <= st["p99_latency_s"] * (1 + 1e-9)
+    assert 1 <= st["tail_requests"] <= len(reqs)
+    tail = st["tail_queue_s"] + st["tail_host_s"] + st["tail_device_s"]
+    assert tail >= st["p99_latency_s"] * (1 - 1e-9)
+    assert st["tail_mean_n"] in {400.0, 1000.0, 2500.0} or 400.0 <= st["tail_mean_n"] <= 2500.0
+    assert 1.0 <= st["tail_mean_batch_requests"] <= len(reqs)
     say("alone")
     for q, (v, s) in zip(reqs, mix):
         t = mte.mte_submit(sid, **q)
