@@ -204,11 +204,25 @@ def cpu_baseline(X, Y, Z, budget_s=15.0, single_s=6.0):
         cksg.cmi_ksg(Xe, Y, Z, K_NN, threads=1)
         n1 += 1
     dt1 = time.perf_counter() - t1
+    # C1 (one estimate at N = 1000, D = 3): the oracle's latency per call
+    import synth
+    X1, Y1, Z1, _ = synth.c1_gaussian(1000, 1)
+    c1 = {}
+    for name, th in (("c1_oracle_s", None), ("c1_oracle_single_thread_s", 1)):
+        lat = []
+        for _ in range(5):
+            t = time.perf_counter()
+            if th is None:
+                cksg.cmi_ksg(X1, Y1, Z1, K_NN)
+            else:
+                cksg.cmi_ksg(X1, Y1, Z1, K_NN, threads=th)
+            lat.append(time.perf_counter() - t)
+        c1[name] = float(np.median(lat))
     return {"value": count / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} of the 201 C2 estimates (the estimate, then surrogates 0..{count - 2}), "
                       f"brute-force C oracle, OpenMP over query rows",
             "single_thread_evals_per_s": n1 / dt1, "single_thread_sample": f"the first {n1} C2 estimates",
-            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), **c1}
 
 
 def c1_leg(mte, torch, dev, reps=200):
@@ -331,11 +345,12 @@ def latency_phases(st):
     return {k: st[k] for k in keys}
 
 
-def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
+def served(mte, torch, n_burst=768, n_poisson=384, loads=(0.5, 0.8, 0.95), load=0.8):
     """Requests of N in {1000, 3000, 10000}, Z dim 1..15, S = 200 over a
     100-node coupled-logistic-map network: a burst for saturation throughput
     (after an untimed burst of the same mix, whose rate is reported as the
-    first burst's), then Poisson arrivals at `load` x that rate for latency."""
+    first burst's), then Poisson arrivals at each of `loads` x that rate for
+    latency; the top-level latency figures are those at `load`."""
     import synth
     series, _ = synth.clm_network(100, N_ROWS, seed=4)
     sid = mte.mte_series_register(series)
@@ -368,21 +383,30 @@ def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
     burst_s = time.perf_counter() - t
     st_burst = mte.mte_serve_get_stats(reset=True)
     rate = n_burst / burst_s
-    reqs = [make(r) for r in range(n_poisson)]
-    gaps = g.exponential(1.0 / (load * rate), size=n_poisson)
-    t = time.perf_counter()
-    tickets = []
-    next_t = t
-    for q, gap in zip(reqs, gaps):
-        next_t += gap
-        while time.perf_counter() < next_t:
-            time.sleep(min(0.0005, max(0.0, next_t - time.perf_counter())))
-        tickets.append(mte.mte_submit(sid, **q))
-    for tk in tickets:
-        mte.mte_wait(tk, S)
-    poisson_s = time.perf_counter() - t
-    st = mte.mte_serve_get_stats(reset=True)
+
+    def poisson(ld):
+        reqs = [make(r) for r in range(n_poisson)]
+        gaps = g.exponential(1.0 / (ld * rate), size=n_poisson)
+        t = time.perf_counter()
+        tickets = []
+        next_t = t
+        for q, gap in zip(reqs, gaps):
+            next_t += gap
+            while time.perf_counter() < next_t:
+                time.sleep(min(0.0005, max(0.0, next_t - time.perf_counter())))
+            tickets.append(mte.mte_submit(sid, **q))
+        for tk in tickets:
+            mte.mte_wait(tk, S)
+        wall = time.perf_counter() - t
+        st = mte.mte_serve_get_stats(reset=True)
+        return {"offered_load": ld, "requests": n_poisson, "evals_per_s": st["estimates"] / wall,
+                "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+                "batches": st["batches"], "mean_batch_requests": st["mean_batch_requests"],
+                "latency_phases": latency_phases(st)}
+
+    by_load = [poisson(ld) for ld in loads]
     mte.mte_series_release(sid)
+    main = next(x for x in by_load if x["offered_load"] == load)
     return {
         "workload": "100-node CLM, requests of N in {1000,3000,10000}, Z dim 1..15, S=200",
         "saturation_evals_per_s": st_burst["estimates"] / burst_s,
@@ -391,12 +415,13 @@ def served(mte, torch, n_burst=768, n_poisson=384, load=0.8):
         "burst_mean_batch_requests": st_burst["mean_batch_requests"],
         "offered_load": load,
         "poisson_requests": n_poisson,
-        "poisson_evals_per_s": st["estimates"] / poisson_s,
-        "p50_latency_s": st["p50_latency_s"],
-        "p99_latency_s": st["p99_latency_s"],
-        "batches": st["batches"],
-        "mean_batch_requests": st["mean_batch_requests"],
-        "latency_phases": latency_phases(st),
+        "poisson_evals_per_s": main["evals_per_s"],
+        "p50_latency_s": main["p50_latency_s"],
+        "p99_latency_s": main["p99_latency_s"],
+        "batches": main["batches"],
+        "mean_batch_requests": main["mean_batch_requests"],
+        "latency_phases": main["latency_phases"],
+        "poisson_by_load": by_load,
     }
 
 
@@ -700,12 +725,16 @@ def main():
         srv = served(mte, torch)
         log(f"served: {srv['saturation_evals_per_s']:.1f} evals/s saturated (first burst {srv['first_burst_evals_per_s']:.1f}); Poisson p50 "
             f"{srv['p50_latency_s'] * 1e3:.1f} ms p99 {srv['p99_latency_s'] * 1e3:.1f} ms")
-        ph = srv["latency_phases"]
-        log(f"served latency phases (ms): queued p50 {ph['queue_p50_s'] * 1e3:.2f} p99 {ph['queue_p99_s'] * 1e3:.2f}, "
-            f"host p50 {ph['host_p50_s'] * 1e3:.2f} p99 {ph['host_p99_s'] * 1e3:.2f}, device p50 "
-            f"{ph['device_p50_s'] * 1e3:.2f} p99 {ph['device_p99_s'] * 1e3:.2f}; the {ph['tail_requests']} requests at or "
-            f"above p99: queued {ph['tail_queue_s'] * 1e3:.2f}, host {ph['tail_host_s'] * 1e3:.2f}, device "
-            f"{ph['tail_device_s'] * 1e3:.2f}, mean N {ph['tail_mean_n']:.0f}, batch {ph['tail_mean_batch_requests']:.1f}")
+        for pl in srv["poisson_by_load"]:
+            ph = pl["latency_phases"]
+            log(f"served at {pl['offered_load']:.2f}x saturation: {pl['evals_per_s']:.0f} evals/s, p50 "
+                f"{pl['p50_latency_s'] * 1e3:.1f} ms p99 {pl['p99_latency_s'] * 1e3:.1f} ms; phases (ms): queued p50 "
+                f"{ph['queue_p50_s'] * 1e3:.2f} p99 {ph['queue_p99_s'] * 1e3:.2f}, host p50 {ph['host_p50_s'] * 1e3:.2f} "
+                f"p99 {ph['host_p99_s'] * 1e3:.2f}, device p50 {ph['device_p50_s'] * 1e3:.2f} p99 "
+                f"{ph['device_p99_s'] * 1e3:.2f}; the {ph['tail_requests']} requests at or above p99: queued "
+                f"{ph['tail_queue_s'] * 1e3:.2f}, host {ph['tail_host_s'] * 1e3:.2f}, device "
+                f"{ph['tail_device_s'] * 1e3:.2f}, mean N {ph['tail_mean_n']:.0f}, batch "
+                f"{ph['tail_mean_batch_requests']:.1f}")
 
     note_tuning("served")
     c3 = None
