@@ -123,6 +123,23 @@ def build_sanitized(verbose: bool = False) -> str:
     return LIB_SAN
 
 
+# The VALU issue-rate probe (a program of its own, not part of the library):
+# the measurement behind the ALU peaks the benchmark prices kernels against.
+PROBE = os.path.join(PKG, "valu_issue_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    cmd = [HIPCC, "-O3", "-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", os.path.join(CSRC, "valu_issue_probe.hip"), "-o", PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE + ".tmp", PROBE)
+    if verbose:
+        print("built", PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
@@ -138,6 +155,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_probe(verbose)
     return LIB
 
 
