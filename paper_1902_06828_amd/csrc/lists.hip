@@ -95,8 +95,11 @@ __device__ __forceinline__ uint64_t pack_counts(int cxz, int cyz, int cz) {
            ((uint64_t)(uint32_t)cz << (2 * kPackBits));
 }
 
+// Bucket key of a distance d >= 0 (+inf included): its exponent and top
+// mantissa bits.  The sign bit is clear, so a plain shift (which gfx950
+// issues at twice the rate of a bit-field extract) gives the 12-bit field.
 __device__ __forceinline__ uint32_t key_of(float d) {
-    return __builtin_amdgcn_ubfe(__float_as_uint(d), kKeyShift, 32 - kKeyShift - 1);
+    return __float_as_uint(d) >> kKeyShift;
 }
 
 // Smallest value of d's bucket (d >= 0).
@@ -507,8 +510,14 @@ __global__ __launch_bounds__(kBT) void list_build_dz_kernel(const ListSet *__res
 #pragma unroll
             for (int u = 0; u < kLR; ++u) {
                 const uint32_t k1 = key_of(ayz[r][u]) | sink[u], k2 = key_of(az[r][u]) | sink[u];
-                atomicAdd(&sm.h[r][k1], k1 == k2 ? kInc1 + kInc2 : kInc1);
-                if (k1 != k2) atomicAdd(&sm.h[r][k2], kInc2);
+                // one compare: the increment is chosen in the branch that
+                // takes the second key's atomic
+                uint32_t inc = kInc1 + kInc2;
+                if (k1 != k2) {
+                    inc = kInc1;
+                    atomicAdd(&sm.h[r][k2], kInc2);
+                }
+                atomicAdd(&sm.h[r][k1], inc);
             }
     };
     int j0 = tid;
