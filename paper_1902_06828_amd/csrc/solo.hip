@@ -50,8 +50,12 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
+// Row j (0 <= j < n) of a column: a uniform base plus a 32-bit byte offset,
+// the form a global load takes with no 64-bit address arithmetic (an int
+// index is sign-extended and added in 64 bits per load).
 __device__ __forceinline__ float lload(const float *p, int j) {
-    return ((const __attribute__((address_space(1))) float *)p)[j];
+    using gchar = const __attribute__((address_space(1))) char;
+    return *(const __attribute__((address_space(1))) float *)((gchar *)p + (uint32_t)j * 4u);
 }
 
 // Wave-uniform values moved to scalar registers (the compiler cannot prove a
